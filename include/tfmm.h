@@ -1,0 +1,179 @@
+/*
+ * tfmm.h -- C ABI of libtfmm, an MI355X (gfx950) implementation of the
+ * angular-momentum-conserving Fast Multipole Method of Korobkin et al.,
+ * "Conservation of Angular Momentum in the Fast Multipole Method"
+ * (arXiv:2107.07166).
+ *
+ * What is computed (paper Sec. 2, notation kept): N particles at X_a with
+ * masses m_a; gravitational forces F_a = m_a a_a with G a parameter.  Pairs of
+ * tree nodes A, B that pass the multipole acceptance criterion
+ * (Eq. mac_criterion: (r_A,max + r_B,max) / R <= theta, theta = tan of the
+ * MAC angle, 0 <= theta < 1) interact through the Taylor series of Eq. taylor
+ * truncated at total degree p about the two centres of mass; all other pairs
+ * of leaves interact exactly (Eq. jia).  Both directions of every pair use
+ * the same expression (mutual interactions), so linear momentum is conserved
+ * (Eq. netforce).  Two variants:
+ *   TFMM_STANDARD   -- the symmetric expansion itself (leaves the spurious
+ *                      torques of Eq. total_torque);
+ *   TFMM_CONSERVING -- each far-field pair force re-projected onto the line
+ *                      joining the two particles (Eq. realign), with the
+ *                      projection scalar expanded in (x_a - y_b) to degree
+ *                      p-1 (Eqs. nab-expansion, abnab-expansion; equal to
+ *                      Eq. aaB1 at p = 2): no spurious torque.
+ * Softening: the kernel is -(r^2 + eps^2)^(-1/2) in the near and far field.
+ *
+ * Conventions for every entry point:
+ *  - return value: TFMM_OK (0) or a negative tfmm_status; on error the
+ *    context keeps a message, see tfmm_last_error();
+ *  - device pointers are HIP device addresses (e.g. torch.Tensor.data_ptr()
+ *    of a CUDA/HIP tensor); they stay owned by the caller and must outlive
+ *    the stream work that reads or writes them;
+ *  - `stream` is a hipStream_t (NULL = the null stream); work is enqueued on
+ *    it in order.  Calls return after enqueueing, except where noted as
+ *    "synchronising" (they wait for the stream);
+ *  - a context is not thread-safe: use one per host thread;
+ *  - after TFMM_EDEVICE the context is unusable and must be destroyed.
+ */
+#ifndef TFMM_H
+#define TFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TFMM_OK = 0,
+    TFMM_EINVAL = -1,  /* invalid argument; nothing was enqueued */
+    TFMM_ENOMEM = -2,  /* the context's device-memory budget would be exceeded */
+    TFMM_EDEVICE = -3, /* a HIP call failed; the context is now unusable */
+    TFMM_ESTATE = -4   /* object used out of order (e.g. lists before a walk) */
+} tfmm_status;
+
+typedef enum { TFMM_STANDARD = 0, TFMM_CONSERVING = 1 } tfmm_variant;
+
+/* TFMM_FP64: every step in FP64.  TFMM_MIXED32: near field (P2P) and M2L in
+ * FP32 with FP64 accumulation across source leaves / per node; tree, centres
+ * of mass, r_max, moments (P2M, M2M), L2L, L2P and all reductions in FP64. */
+typedef enum { TFMM_FP64 = 0, TFMM_MIXED32 = 1 } tfmm_precision;
+
+typedef struct tfmm_ctx tfmm_ctx;   /* device, memory budget, error state */
+typedef struct tfmm_tree tfmm_tree; /* one particle set: keys, octree, lists, expansions */
+
+typedef struct {
+    int p;            /* expansion order, 1..8 (Eq. taylor truncated at degree p) */
+    double theta;     /* tan(theta_MAC) of Eq. mac_criterion, 0 <= theta < 1 */
+    double softening; /* Plummer softening eps >= 0 */
+    double G;         /* gravitational constant */
+    int variant;      /* tfmm_variant */
+    int precision;    /* tfmm_precision */
+} tfmm_params;
+
+/* Create a context on HIP device `device` that may hold at most
+ * `hbm_budget_bytes` of library-owned device memory (0 = no limit).
+ * Errors: EINVAL (bad device or NULL out), EDEVICE. */
+int tfmm_ctx_create(int device, size_t hbm_budget_bytes, tfmm_ctx **out);
+
+/* Destroy a context; every tree created from it must be destroyed first.
+ * Synchronises the device.  NULL is ignored. */
+int tfmm_ctx_destroy(tfmm_ctx *ctx);
+
+/* Message of the last failed call on this context ("" if none).  Valid until
+ * the next call on the context. */
+const char *tfmm_last_error(const tfmm_ctx *ctx);
+
+/* Device memory currently held by the context's trees and scratch. */
+size_t tfmm_ctx_bytes_in_use(const tfmm_ctx *ctx);
+
+/* Build the tree for n particles.  pos: device, n x 3 FP64 row-major (x, y, z
+ * of particle a at pos[3a..3a+2]); mass: device, n FP64 (> 0).  n_leaf: a
+ * node with more than n_leaf particles is split (1..4096).  Keys: 21 bits per
+ * axis over the bounding cube, stable sort, octree numbered level by level in
+ * Morton order; per node FP64 mass, centre of mass and r_max (the exact
+ * largest particle distance from the centre of mass, Eq. mac_criterion).
+ * Synchronising (reads per-level sizes).  The tree keeps its own sorted copy
+ * of pos and mass.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int tfmm_build_tree(tfmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                    int n_leaf, void *stream, tfmm_tree **out);
+
+/* Rebuild an existing tree in place for new positions (same n, same masses
+ * pointer semantics as tfmm_build_tree); reuses its device buffers.
+ * Synchronising.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int tfmm_tree_rebuild(tfmm_tree *tree, const double *pos, const double *mass, void *stream);
+
+/* Run the mutual dual-tree walk for `theta` (Eq. mac_criterion) and build the
+ * per-target interaction lists.  tfmm_evaluate_forces calls it when theta
+ * changed; exposed for list export.  Synchronising.  Errors: EINVAL, ENOMEM,
+ * EDEVICE. */
+int tfmm_tree_walk(tfmm_tree *tree, double theta, void *stream);
+
+/* Forces on every particle: force (device, n x 3 FP64 row-major, original
+ * particle order) = G m_a (near + far) for the tree's particles.
+ * potential: must be NULL (not provided).  Asynchronous except for the walk
+ * when params->theta differs from the tree's last walk.
+ * Errors: EINVAL (p outside 1..8, theta outside [0,1), eps < 0, bad variant
+ * or precision, NULL force), ENOMEM, EDEVICE. */
+int tfmm_evaluate_forces(tfmm_tree *tree, const tfmm_params *params, double *force,
+                         double *potential, void *stream);
+
+/* Build + evaluate in one call (tree is built, used and destroyed).
+ * Synchronising.  Errors: as tfmm_build_tree and tfmm_evaluate_forces. */
+int tfmm_evaluate_forces_oneshot(tfmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                                 int n_leaf, const tfmm_params *params, double *force, void *stream);
+
+/* Momentum diagnostics in FP64 (Eqs. netforce, total_torque summed over all
+ * particles, about the system centre of mass).  pos, mass, force: device, as
+ * above; vel: device n x 3 or NULL.  out: host, 20 doubles:
+ *   [0..2] sum F, [3] sum |F|, [4..6] sum (X - Xcm) x F, [7] sum |X - Xcm||F|,
+ *   [8..10] P = sum m v, [11..13] L = sum m (X - Xcm) x v, [14] sum m,
+ *   [15..17] Xcm, [18] |sum F| / sum |F|, [19] |sum (X-Xcm) x F| / sum |X-Xcm||F|.
+ * Deterministic fixed-order reduction.  Synchronising.  Errors: EINVAL, EDEVICE. */
+int tfmm_momentum_diagnostics(tfmm_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                              const double *mass, const double *force, void *stream, double *out);
+
+/* Sizes of a tree: out[0] n, [1] nodes, [2] leaves, [3] deepest level,
+ * [4] far (M2L) unordered pairs, [5] near (P2P) unordered pairs, [6] directed
+ * near particle interactions (sum over directed leaf pairs of n_target *
+ * n_source, self pairs n(n-1)), [7] directed far pairs.  [4..7] are -1 before
+ * the first walk.  Host output.  Errors: EINVAL. */
+int tfmm_tree_info(const tfmm_tree *tree, int64_t *out);
+
+/* Copy the tree to host buffers (each may be NULL; caller-allocated):
+ * keys: n uint64 in original particle order; order: n int32, sorted position
+ * -> original index; and per node (sizes from tfmm_tree_info): level (int32),
+ * prefix (uint64, key >> 3(21 - level)), first / count (int32, sorted range),
+ * child_first (int32, -1 for leaves), nchild (int32), parent (int32, -1 for
+ * the root), com (3 FP64 per node), mass (FP64), rmax (FP64).  Synchronising.
+ * Errors: EINVAL, EDEVICE. */
+int tfmm_tree_export(tfmm_tree *tree, uint64_t *keys, int32_t *order, int32_t *level,
+                     uint64_t *prefix, int32_t *first, int32_t *count, int32_t *child_first,
+                     int32_t *nchild, int32_t *parent, double *com, double *mass, double *rmax);
+
+/* Copy the last walk's unordered pairs to host buffers (int32 pairs, lower
+ * node index first, in the walk's emission order): far (M2L) and near (P2P,
+ * self pairs (L, L) included).  Synchronising.  Errors: EINVAL, ESTATE (no
+ * walk yet), EDEVICE. */
+int tfmm_lists_export(tfmm_tree *tree, int32_t *m2l_pairs, int32_t *p2p_pairs);
+
+/* Destroy a tree and release its device memory.  Synchronises the device.
+ * NULL is ignored. */
+int tfmm_tree_destroy(tfmm_tree *tree);
+
+/* Conservative estimate of the device bytes a tree of n particles at order p
+ * needs (for admission control).  Pure host computation. */
+size_t tfmm_footprint_bytes(int64_t n, int p, int n_leaf, int precision);
+
+/* Per-phase device times (milliseconds) of the last tfmm_evaluate_forces on
+ * this tree, measured with HIP events on its stream when timing is enabled
+ * (tfmm_tree_set_timing): out[0] M2L, [1] P2P, [2] L2L, [3] L2P, [4] moments,
+ * [5] whole evaluation.  Synchronising.  Errors: EINVAL, ESTATE. */
+int tfmm_tree_set_timing(tfmm_tree *tree, int enable);
+int tfmm_tree_phase_times(tfmm_tree *tree, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFMM_H */

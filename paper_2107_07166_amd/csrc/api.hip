@@ -1,0 +1,381 @@
+// The C ABI (include/tfmm.h): argument checks, error capture and the order of
+// the phases on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "common.h"
+
+namespace tfmm {
+
+DevBuf::~DevBuf() { release(); }
+
+void DevBuf::release() {
+    if (p && ctx) ctx->free(p, cap);
+    p = nullptr;
+    cap = 0;
+}
+
+void DevBuf::ensure(Ctx* c, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (p && cap >= bytes) return;
+    release();
+    ctx = c;
+    const size_t want = (size_t)round_up((int64_t)bytes, 256);
+    p = c->alloc(want);
+    cap = want;
+}
+
+void DevBuf::ensure_keep(Ctx* c, size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 16;
+    if (p && cap >= bytes) return;
+    const size_t want = (size_t)round_up((int64_t)bytes, 256);
+    void* q = c->alloc(want);
+    if (p) {
+        TFMM_HIP(hipMemcpyAsync(q, p, cap, hipMemcpyDeviceToDevice, s));
+        TFMM_HIP(hipStreamSynchronize(s));
+    }
+    release();
+    ctx = c;
+    p = q;
+    cap = want;
+}
+
+void* Ctx::alloc(size_t bytes) {
+    if (budget && used + bytes > budget)
+        fail(TFMM_ENOMEM, "device memory budget exceeded (" + std::to_string(used + bytes) + " > " +
+                              std::to_string(budget) + " bytes)");
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, bytes);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        fail(TFMM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: out of device memory");
+    }
+    if (e != hipSuccess) fail(TFMM_EDEVICE, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    used += bytes;
+    return q;
+}
+
+void Ctx::free(void* q, size_t bytes) {
+    if (!q) return;
+    // a buffer is only released when it grows or its owner goes away; kernels
+    // queued earlier may still read it
+    (void)hipDeviceSynchronize();
+    (void)hipFree(q);
+    used -= std::min(used, bytes);
+}
+
+namespace {
+
+template <typename F>
+int guarded(Ctx* ctx, F&& f) {
+    if (ctx && ctx->broken) {
+        ctx->err = "context is unusable after an earlier device error";
+        return TFMM_EDEVICE;
+    }
+    try {
+        if (ctx) ctx->err.clear();
+        f();
+        return TFMM_OK;
+    } catch (const Error& e) {
+        if (ctx) {
+            ctx->err = e.msg;
+            if (e.code == TFMM_EDEVICE) ctx->broken = true;
+        }
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (ctx) ctx->err = "host allocation failed";
+        return TFMM_ENOMEM;
+    }
+}
+
+void set_device(Ctx* ctx) { TFMM_HIP(hipSetDevice(ctx->device)); }
+
+void check_params(const tfmm_params* p) {
+    if (!p) fail(TFMM_EINVAL, "params is NULL");
+    if (p->p < 1 || p->p > kMaxP) fail(TFMM_EINVAL, "p must be in 1..8");
+    if (!(p->theta >= 0.0) || !(p->theta < 1.0)) fail(TFMM_EINVAL, "theta must satisfy 0 <= theta < 1");
+    if (!(p->softening >= 0.0) || !std::isfinite(p->softening)) fail(TFMM_EINVAL, "softening must be >= 0");
+    if (!std::isfinite(p->G)) fail(TFMM_EINVAL, "G must be finite");
+    if (p->variant != TFMM_STANDARD && p->variant != TFMM_CONSERVING) fail(TFMM_EINVAL, "unknown variant");
+    if (p->precision != TFMM_FP64 && p->precision != TFMM_MIXED32) fail(TFMM_EINVAL, "unknown precision");
+}
+
+void evaluate(Tree& t, const tfmm_params* prm, double* force, hipStream_t s) {
+    if (!t.walk_valid || t.walk_theta != prm->theta) walk_tree(t, prm->theta, s);
+    const double eps2 = prm->softening * prm->softening;
+    if (t.timing) {
+        if (!t.ev_ready) {
+            for (auto& e : t.ev) TFMM_HIP(hipEventCreate(&e));
+            t.ev_ready = true;
+        }
+        TFMM_HIP(hipEventRecord(t.ev[0], s));
+    }
+    compute_moments(t, prm->p, s);
+    prepare_sources(t, prm->precision, s);
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[1], s));
+    run_m2l(t, prm->p, prm->variant, prm->precision, eps2, s);
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[2], s));
+    run_l2l(t, prm->p, prm->variant, s);
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[3], s));
+    run_p2p(t, prm->precision, eps2, s);
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[4], s));
+    run_l2p(t, prm->p, prm->variant, prm->G, force, s);
+    if (t.timing) {
+        TFMM_HIP(hipEventRecord(t.ev[5], s));
+        t.have_times = true;
+    }
+}
+
+}  // namespace
+}  // namespace tfmm
+
+using namespace tfmm;
+
+extern "C" {
+
+int tfmm_ctx_create(int device, size_t hbm_budget_bytes, tfmm_ctx** out) {
+    if (!out) return TFMM_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return TFMM_EDEVICE;
+    if (device < 0 || device >= ndev) return TFMM_EINVAL;
+    tfmm_ctx* c = new (std::nothrow) tfmm_ctx();
+    if (!c) return TFMM_ENOMEM;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    const int rc = guarded(c, [&] {
+        set_device(c);
+        c->pinned_bytes = 1 << 16;
+        TFMM_HIP(hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault));
+    });
+    if (rc != TFMM_OK) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return TFMM_OK;
+}
+
+int tfmm_ctx_destroy(tfmm_ctx* ctx) {
+    if (!ctx) return TFMM_OK;
+    if (ctx->live_trees > 0) {
+        ctx->err = "destroy every tree of the context first";
+        return TFMM_ESTATE;
+    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+    return TFMM_OK;
+}
+
+const char* tfmm_last_error(const tfmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+size_t tfmm_ctx_bytes_in_use(const tfmm_ctx* ctx) { return ctx ? ctx->used : 0; }
+
+int tfmm_build_tree(tfmm_ctx* ctx, int64_t n, const double* pos, const double* mass, int n_leaf, void* stream,
+                    tfmm_tree** out) {
+    if (!ctx) return TFMM_EINVAL;
+    if (!out) {
+        ctx->err = "out is NULL";
+        return TFMM_EINVAL;
+    }
+    *out = nullptr;
+    tfmm_tree* t = nullptr;
+    const int rc = guarded(ctx, [&] {
+        if (n < 1 || n > (int64_t)INT32_MAX / 2) fail(TFMM_EINVAL, "n must be in 1..2^30");
+        if (!pos || !mass) fail(TFMM_EINVAL, "pos and mass must be device pointers");
+        if (n_leaf < 1 || n_leaf > 4096) fail(TFMM_EINVAL, "n_leaf must be in 1..4096");
+        set_device(ctx);
+        t = new tfmm_tree();
+        t->ctx = ctx;
+        t->n = n;
+        t->n_leaf = n_leaf;
+        ctx->live_trees++;
+        build_tree(*t, pos, mass, (hipStream_t)stream);
+    });
+    if (rc != TFMM_OK) {
+        if (t) {
+            ctx->live_trees--;
+            delete t;
+        }
+        return rc;
+    }
+    *out = t;
+    return TFMM_OK;
+}
+
+int tfmm_tree_rebuild(tfmm_tree* tree, const double* pos, const double* mass, void* stream) {
+    if (!tree) return TFMM_EINVAL;
+    return guarded(tree->ctx, [&] {
+        if (!pos || !mass) fail(TFMM_EINVAL, "pos and mass must be device pointers");
+        set_device(tree->ctx);
+        build_tree(*tree, pos, mass, (hipStream_t)stream);
+    });
+}
+
+int tfmm_tree_walk(tfmm_tree* tree, double theta, void* stream) {
+    if (!tree) return TFMM_EINVAL;
+    return guarded(tree->ctx, [&] {
+        if (!(theta >= 0.0) || !(theta < 1.0)) fail(TFMM_EINVAL, "theta must satisfy 0 <= theta < 1");
+        set_device(tree->ctx);
+        walk_tree(*tree, theta, (hipStream_t)stream);
+    });
+}
+
+int tfmm_evaluate_forces(tfmm_tree* tree, const tfmm_params* params, double* force, double* potential,
+                         void* stream) {
+    if (!tree) return TFMM_EINVAL;
+    return guarded(tree->ctx, [&] {
+        check_params(params);
+        if (!force) fail(TFMM_EINVAL, "force must be a device pointer");
+        if (potential) fail(TFMM_EINVAL, "potential output is not provided; pass NULL");
+        set_device(tree->ctx);
+        evaluate(*tree, params, force, (hipStream_t)stream);
+    });
+}
+
+int tfmm_evaluate_forces_oneshot(tfmm_ctx* ctx, int64_t n, const double* pos, const double* mass, int n_leaf,
+                                 const tfmm_params* params, double* force, void* stream) {
+    if (!ctx) return TFMM_EINVAL;
+    tfmm_tree* t = nullptr;
+    int rc = guarded(ctx, [&] { check_params(params); });
+    if (rc != TFMM_OK) return rc;
+    rc = tfmm_build_tree(ctx, n, pos, mass, n_leaf, stream, &t);
+    if (rc != TFMM_OK) return rc;
+    rc = tfmm_evaluate_forces(t, params, force, nullptr, stream);
+    if (rc == TFMM_OK) rc = guarded(ctx, [&] { TFMM_HIP(hipStreamSynchronize((hipStream_t)stream)); });
+    const std::string keep = ctx->err;
+    tfmm_tree_destroy(t);
+    if (rc != TFMM_OK) ctx->err = keep;
+    return rc;
+}
+
+int tfmm_momentum_diagnostics(tfmm_ctx* ctx, int64_t n, const double* pos, const double* vel, const double* mass,
+                              const double* force, void* stream, double* out) {
+    if (!ctx) return TFMM_EINVAL;
+    return guarded(ctx, [&] {
+        if (n < 1 || !pos || !mass || !force || !out) fail(TFMM_EINVAL, "bad diagnostics arguments");
+        set_device(ctx);
+        run_diagnostics(n, pos, vel, mass, force, out, ctx, (hipStream_t)stream);
+    });
+}
+
+int tfmm_tree_info(const tfmm_tree* tree, int64_t* out) {
+    if (!tree || !out) return TFMM_EINVAL;
+    out[0] = tree->n;
+    out[1] = tree->n_nodes;
+    out[2] = tree->n_leaves;
+    out[3] = tree->max_level;
+    out[4] = tree->walk_valid ? tree->n_m2l : -1;
+    out[5] = tree->walk_valid ? tree->n_p2p : -1;
+    out[6] = tree->walk_valid ? tree->n_near_int : -1;
+    out[7] = tree->walk_valid ? 2 * tree->n_m2l : -1;
+    return TFMM_OK;
+}
+
+int tfmm_tree_export(tfmm_tree* tree, uint64_t* keys, int32_t* order, int32_t* level, uint64_t* prefix,
+                     int32_t* first, int32_t* count, int32_t* child_first, int32_t* nchild, int32_t* parent,
+                     double* com, double* mass, double* rmax) {
+    if (!tree) return TFMM_EINVAL;
+    return guarded(tree->ctx, [&] {
+        Tree& t = *tree;
+        set_device(t.ctx);
+        TFMM_HIP(hipDeviceSynchronize());
+        const size_t n = (size_t)t.n, nn = (size_t)t.n_nodes;
+        if (keys || order) {
+            std::vector<uint64_t> sk(n);
+            std::vector<int32_t> pm(n);
+            TFMM_HIP(hipMemcpy(sk.data(), t.keys.p, n * 8, hipMemcpyDeviceToHost));
+            TFMM_HIP(hipMemcpy(pm.data(), t.perm.p, n * 4, hipMemcpyDeviceToHost));
+            if (order) std::memcpy(order, pm.data(), n * 4);
+            if (keys)
+                for (size_t j = 0; j < n; ++j) keys[pm[j]] = sk[j];
+        }
+        if (level) TFMM_HIP(hipMemcpy(level, t.nd_level.p, nn * 4, hipMemcpyDeviceToHost));
+        if (prefix) TFMM_HIP(hipMemcpy(prefix, t.nd_prefix.p, nn * 8, hipMemcpyDeviceToHost));
+        if (first) TFMM_HIP(hipMemcpy(first, t.nd_first.p, nn * 4, hipMemcpyDeviceToHost));
+        if (count) TFMM_HIP(hipMemcpy(count, t.nd_count.p, nn * 4, hipMemcpyDeviceToHost));
+        if (child_first) TFMM_HIP(hipMemcpy(child_first, t.nd_child_first.p, nn * 4, hipMemcpyDeviceToHost));
+        if (nchild) TFMM_HIP(hipMemcpy(nchild, t.nd_nchild.p, nn * 4, hipMemcpyDeviceToHost));
+        if (parent) TFMM_HIP(hipMemcpy(parent, t.nd_parent.p, nn * 4, hipMemcpyDeviceToHost));
+        if (rmax) TFMM_HIP(hipMemcpy(rmax, t.nd_rmax.p, nn * 8, hipMemcpyDeviceToHost));
+        if (com || mass) {
+            std::vector<double> z(nn * 4);
+            TFMM_HIP(hipMemcpy(z.data(), t.nd_Z.p, nn * 32, hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < nn; ++i) {
+                if (com)
+                    for (int d = 0; d < 3; ++d) com[3 * i + d] = z[4 * i + d];
+                if (mass) mass[i] = z[4 * i + 3];
+            }
+        }
+    });
+}
+
+int tfmm_lists_export(tfmm_tree* tree, int32_t* m2l_pairs, int32_t* p2p_pairs) {
+    if (!tree) return TFMM_EINVAL;
+    return guarded(tree->ctx, [&] {
+        Tree& t = *tree;
+        if (!t.walk_valid) fail(TFMM_ESTATE, "no walk has been run on this tree");
+        set_device(t.ctx);
+        TFMM_HIP(hipDeviceSynchronize());
+        if (m2l_pairs && t.n_m2l > 0)
+            TFMM_HIP(hipMemcpy(m2l_pairs, t.m2l_pairs.p, (size_t)t.n_m2l * 8, hipMemcpyDeviceToHost));
+        if (p2p_pairs && t.n_p2p > 0)
+            TFMM_HIP(hipMemcpy(p2p_pairs, t.p2p_pairs.p, (size_t)t.n_p2p * 8, hipMemcpyDeviceToHost));
+    });
+}
+
+int tfmm_tree_destroy(tfmm_tree* tree) {
+    if (!tree) return TFMM_OK;
+    Ctx* ctx = tree->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (tree->ev_ready)
+        for (auto& e : tree->ev) (void)hipEventDestroy(e);
+    delete tree;
+    ctx->live_trees--;
+    return TFMM_OK;
+}
+
+size_t tfmm_footprint_bytes(int64_t n, int p, int n_leaf, int precision) {
+    if (n < 1 || p < 1 || p > kMaxP || n_leaf < 1) return 0;
+    const double nn = 4.0 * (double)n / (double)n_leaf + 1024.0;  // nodes (generous)
+    const double nc = c_le(p), ncp = (double)round_up(c_le(p), 4), nloc = 4.0 * c_le(p - 1) + nc;
+    double b = 0;
+    b += (double)n * (8 + 8 + 4 + 4 + 1 + 4 + 8 + 32 + 4 + (precision == TFMM_MIXED32 ? 16 : 32) + 24);
+    b += nn * (4 * 6 + 8 + 32 + 32 + 8 + 8 + 4);
+    b += nn * (nc * 8 + ncp * 12 + 2 * nloc * 8);
+    b += nn * (400.0 * 8 * 2 + 80.0 * 8 * 2);  // pair lists, directed lists, frontiers
+    b += (double)n * 16;                       // scratch
+    return (size_t)(b * 1.25) + (64u << 20);
+}
+
+int tfmm_tree_set_timing(tfmm_tree* tree, int enable) {
+    if (!tree) return TFMM_EINVAL;
+    tree->timing = enable != 0;
+    tree->have_times = false;
+    return TFMM_OK;
+}
+
+int tfmm_tree_phase_times(tfmm_tree* tree, double* out) {
+    if (!tree || !out) return TFMM_EINVAL;
+    return guarded(tree->ctx, [&] {
+        Tree& t = *tree;
+        if (!t.have_times) fail(TFMM_ESTATE, "no timed evaluation on this tree");
+        TFMM_HIP(hipEventSynchronize(t.ev[5]));
+        float ms[5];
+        for (int i = 0; i < 5; ++i) TFMM_HIP(hipEventElapsedTime(&ms[i], t.ev[i], t.ev[i + 1]));
+        float all = 0;
+        TFMM_HIP(hipEventElapsedTime(&all, t.ev[0], t.ev[5]));
+        out[0] = ms[1];  // M2L
+        out[1] = ms[3];  // P2P
+        out[2] = ms[2];  // L2L
+        out[3] = ms[4];  // L2P
+        out[4] = ms[0];  // moments + sources
+        out[5] = all;
+    });
+}
+
+}  // extern "C"

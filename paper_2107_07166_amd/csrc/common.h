@@ -1,0 +1,172 @@
+// Internal declarations shared by the libtfmm translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tfmm.h"
+
+namespace tfmm {
+
+// Internal failures travel as exceptions and become status codes at the ABI.
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+#define TFMM_HIP(call)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            ::tfmm::fail(TFMM_EDEVICE, std::string(#call) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TFMM_LAUNCHED() TFMM_HIP(hipGetLastError())
+
+constexpr int kLevels = 21;       // key bits per axis = deepest octree level
+constexpr int kWave = 64;         // CDNA wavefront width
+constexpr int kMaxP = 8;
+
+inline int c_le(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) * (n + 3) / 6; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+struct Ctx;
+
+// Grow-only device buffer, accounted against the owning context's budget.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    Ctx* ctx = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    void ensure(Ctx* c, size_t bytes);                 // contents not preserved
+    void ensure_keep(Ctx* c, size_t bytes, hipStream_t s);  // contents preserved (async copy)
+    void release();
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Ctx {
+    int device = 0;
+    size_t budget = 0;  // 0 = unlimited
+    size_t used = 0;
+    std::string err;
+    bool broken = false;
+    void* pinned = nullptr;  // small pinned host staging area
+    size_t pinned_bytes = 0;
+    int live_trees = 0;
+    void* alloc(size_t bytes);
+    void free(void* p, size_t bytes);
+};
+
+// Per-precision scalar types for the interaction kernels.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+struct Tree {
+    Ctx* ctx = nullptr;
+    int64_t n = 0;
+    int n_leaf = 0;
+    // tree sizes (host copies)
+    int64_t n_nodes = 0, n_leaves = 0;
+    int max_level = 0;
+    std::vector<int64_t> level_begin;  // node index range of each level, size max_level + 2
+    double bbox[5] = {0, 0, 0, 0, 0};  // lo x/y/z, ext, scale
+
+    // particles (sorted order unless noted)
+    DevBuf keys, keys2;        // uint64 Morton keys
+    DevBuf perm, perm2;        // int32 sorted position -> original index
+    DevBuf lvlb;               // uint8 level at which a key boundary appears before position j
+    DevBuf owner, flags;       // int32 scratch for the level-by-level octree build
+    DevBuf Xm;                 // double4 (x, y, z, m)
+    DevBuf leaf_of;            // int32 leaf node of each sorted position
+    DevBuf src4;               // float4/double4 (x, y, z relative to the leaf centre of mass, m)
+    int src_prec = -1;
+
+    // nodes (level-major, Morton order within a level)
+    DevBuf nd_level, nd_prefix, nd_first, nd_count, nd_child_first, nd_nchild, nd_parent;
+    DevBuf nd_S;               // double4 (sum m x, sum m y, sum m z, M)
+    DevBuf nd_Z;               // double4 (centre of mass x, y, z, M)
+    DevBuf nd_r2bits;          // uint64 bits of max squared distance (atomicMax target)
+    DevBuf nd_rmax;            // double
+    DevBuf leaves;             // int32 node ids of the leaves
+
+    // walk and per-target interaction lists
+    bool walk_valid = false;
+    double walk_theta = -1.0;
+    int64_t n_m2l = -1, n_p2p = -1, n_near_int = -1;
+    DevBuf m2l_pairs, p2p_pairs;  // int2, lower node id first
+    DevBuf m2l_off, m2l_src;      // per-target CSR (node ids), directed
+    DevBuf p2p_off, p2p_src;
+    DevBuf m2l_targets;           // nodes with a non-empty far list
+    int64_t n_m2l_targets = 0;
+
+    // expansions
+    int mom_p = -1;
+    DevBuf mom;                   // FP64 raw moments, NC per node
+    DevBuf W32, W64;              // (-1)^|k| M_k / k!, NCP per node (FP32 / FP64 copies)
+    DevBuf loc;                   // FP64 M2L locals per node (NLOC per node)
+    DevBuf loc_leaf;              // FP64 gathered locals per leaf
+    DevBuf near3;                 // FP64 near-field acceleration (3 per sorted particle)
+
+    // scratch
+    DevBuf scratch;               // scans and sorts
+    DevBuf scratch2;
+
+    // timing
+    bool timing = false;
+    hipEvent_t ev[8] = {};
+    bool ev_ready = false;
+    bool have_times = false;
+};
+
+// ---- scans (scan.hip) -----------------------------------------------------
+struct U3 {
+    uint32_t a, b, c;
+};
+size_t scan_scratch_bytes(int64_t n);
+// Exclusive scan of n values; writes the total to *total_dev (device).
+void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
+                        uint32_t* total_dev, hipStream_t s);
+void exclusive_scan_u3(const U3* in, U3* out, int64_t n, void* scratch, U3* total_dev,
+                       hipStream_t s);
+
+// ---- radix sort (sort.hip) ----------------------------------------------------
+size_t sort_scratch_bytes(int64_t n);
+// Stable LSD sort of (key, value) by the low `bits` bits of key; result ends in
+// keys/vals (alt buffers are scratch of the same size).
+void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
+                    int64_t n, int bits, void* scratch, hipStream_t s);
+void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
+                    int64_t n, int bits, void* scratch, hipStream_t s);
+
+// ---- phases ---------------------------------------------------------------
+void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s);
+void walk_tree(Tree& t, double theta, hipStream_t s);
+void compute_moments(Tree& t, int p, hipStream_t s);
+void prepare_sources(Tree& t, int precision, hipStream_t s);
+void run_m2l(Tree& t, int p, int variant, int precision, double eps2, hipStream_t s);
+void run_p2p(Tree& t, int precision, double eps2, hipStream_t s);
+void run_l2l(Tree& t, int p, int variant, hipStream_t s);
+void run_l2p(Tree& t, int p, int variant, double G, double* force, hipStream_t s);
+void run_diagnostics(int64_t n, const double* pos, const double* vel, const double* mass,
+                     const double* force, double* out_host, Ctx* ctx, hipStream_t s);
+
+// number of FP64 local values per node for a variant
+inline int n_local(int p, int variant) {
+    return variant == TFMM_CONSERVING ? 4 * c_le(p - 1) : c_le(p);
+}
+
+}  // namespace tfmm
+
+struct tfmm_ctx : tfmm::Ctx {};
+struct tfmm_tree : tfmm::Tree {};

@@ -1,0 +1,299 @@
+"""Generates expansions_gen.h: straight-line Cartesian-tensor FMM operators.
+
+The GPU kernels need, for every expansion order P = 1..8, fully unrolled code
+for (notation of Korobkin et al., arXiv:2107.07166, Sec. 2):
+
+* the derivative tensors of the softened kernels at R (the D tensors of the
+  paper, generalised to any order and to softening),
+    phi(r) = -(|r|^2 + eps^2)^(-1/2),  g(r) = (|r|^2 + eps^2)^(-3/2) = F_1;
+  with F_n(s) = 2^n d^n/ds^n [-s^(-1/2)], s = |r|^2 + eps^2, the radial
+  functions satisfy F_0 = -s^(-1/2), F_{n+1} = -(2n+1) F_n / s, and
+  d_r F_n = r F_{n+1}.  The tensors A^(n)_k = d^k F_n then obey
+      A^(n)_{k+e_d} = R_d A^(n+1)_k + k_d A^(n+1)_{k-e_d},
+  so phi-derivatives are layer n = 0 and g-derivatives are layer n = 1;
+* the standard M2L contraction (the Taylor series of Eq. taylor summed over
+  the source node, as in Eqs. potential / g_acc_BtoA):
+      L_j += sum_{|i| <= P-|j|} D_{i+j} W_i,  W_i = (-1)^|i| M_i / i!;
+* the conserving M2L contraction (realigned force, Eq. realign, with the
+  projection scalar kept to degree P-1): the far field of B at x is
+      a_e(x) = -(R_e + x_e) P(x) + Q_e(x),
+      P_j  = sum_{|i| <= P-1-|j|} G_{i+j} W_i,
+      Q_ej = sum_{|i| <= P-1-|j|} (-1)^|i| G_{i+j} M_{i+e} / i!
+           = -sum (i_e + 1) G_{i+j} W_{i+e};
+  the -R_e P term is folded in per pair, so the node accumulates P and
+  Q'_e = Q_e - R_e P;
+* the exact polynomial shift of local expansions (L2L) and the evaluation at
+  a particle (L2P).
+
+Multi-indices k = (kx, ky, kz) are stored in graded order: all |k| = n after
+all |k| < n, and within a degree by a = ky + kz ascending, then kz ascending:
+    idx(k) = n(n+1)(n+2)/6 + a(a+1)/2 + kz.
+Dipole moments about the centre of mass vanish, so W_i with |i| = 1 is never
+read.
+
+Run:  python gen_expansions.py  (writes expansions_gen.h next to this file).
+"""
+
+import os
+import sys
+
+PMAX = 8
+
+
+def c_le(n):
+    return (n + 1) * (n + 2) * (n + 3) // 6 if n >= 0 else 0
+
+
+def idx(k):
+    kx, ky, kz = k
+    n = kx + ky + kz
+    a = ky + kz
+    return c_le(n - 1) + a * (a + 1) // 2 + kz
+
+
+def multi(n):
+    out = []
+    for a in range(n + 1):
+        for kz in range(a + 1):
+            out.append((n - a, a - kz, kz))
+    return out
+
+
+def all_upto(p):
+    out = []
+    for n in range(p + 1):
+        out.extend(multi(n))
+    return out
+
+
+def add(a, b):
+    return (a[0] + b[0], a[1] + b[1], a[2] + b[2])
+
+
+E = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+AX = "xyz"
+
+
+def fmt(c):
+    """A floating constant valid for both float and double (cast to T)."""
+    if float(c).is_integer():
+        return f"T({int(c)})"
+    return f"T({c!r})"
+
+
+def gen_layers(P, stop):
+    """Code computing A^(n)_k for n = P..stop, |k| <= P-n.  Returns lines and
+    the variable name of A^(stop)_k."""
+    lines = []
+    name = {}
+    for n in range(P, stop - 1, -1):
+        for k in all_upto(P - n):
+            v = f"a{n}_{idx(k)}"
+            name[(n, k)] = v
+            if sum(k) == 0:
+                lines.append(f"const T {v} = F[{n}];")
+                continue
+            d = 0 if k[0] else (1 if k[1] else 2)
+            k1 = list(k)
+            k1[d] -= 1
+            k1 = tuple(k1)
+            r = "xyz"[d]
+            term = f"R{r} * {name[(n + 1, k1)]}"
+            if k[d] >= 2:
+                k2 = list(k1)
+                k2[d] -= 1
+                k2 = tuple(k2)
+                coef = k[d] - 1
+                if coef == 1:
+                    term = f"fma(R{r}, {name[(n + 1, k1)]}, {name[(n + 1, k2)]})"
+                else:
+                    term = f"fma(R{r}, {name[(n + 1, k1)]}, {fmt(coef)} * {name[(n + 1, k2)]})"
+            lines.append(f"const T {v} = {term};")
+    return lines, name
+
+
+def gen_struct(P):
+    NC = c_le(P)
+    NC1 = c_le(P - 1)
+    out = [f"template <> struct Expansion<{P}> {{",
+           f"  static constexpr int P = {P};",
+           f"  static constexpr int NC = {NC};",
+           f"  static constexpr int NC1 = {NC1};"]
+
+    # phi derivatives (layer 0), |k| <= P
+    lines, name = gen_layers(P, 0)
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void phi_derivs(T Rx, T Ry, T Rz, const T* F, T* D) {")
+    out += ["    " + s for s in lines]
+    for k in all_upto(P):
+        out.append(f"    D[{idx(k)}] = {name[(0, k)]};")
+    out.append("  }")
+
+    # g derivatives (layer 1), |k| <= P-1
+    lines, name = gen_layers(P, 1)
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void g_derivs(T Rx, T Ry, T Rz, const T* F, T* G) {")
+    out += ["    " + s for s in lines]
+    for k in all_upto(P - 1):
+        out.append(f"    G[{idx(k)}] = {name[(1, k)]};")
+    out.append("  }")
+
+    # standard M2L: L_j += sum_i D_{i+j} W_i, 1 <= |j| <= P (|j| = 0 only with WITH_POT)
+    out.append("  template <typename T, bool WITH_POT>")
+    out.append("  __device__ __forceinline__ static void m2l_std(const T* D, const T* W, T* L) {")
+    for j in all_upto(P):
+        if sum(j) == 0:
+            out.append("    if (WITH_POT) {")
+            pre = "      "
+        else:
+            pre = "    "
+        terms = [(idx(add(i, j)), idx(i)) for i in all_upto(P - sum(j)) if sum(i) != 1]
+        expr = f"L[{idx(j)}]"
+        for di, wi in terms:
+            expr = f"fma(D[{di}], W[{wi}], {expr})"
+        out.append(f"{pre}L[{idx(j)}] = {expr};")
+        if sum(j) == 0:
+            out.append("    }")
+    out.append("  }")
+
+    # conserving M2L: P_j and Q'_ej = Q_ej - R_e P_j(pair)
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void m2l_cons(const T* G, const T* W, T Rx, T Ry, T Rz,"
+               " T* Pa, T* Qa) {")
+    for j in all_upto(P - 1):
+        terms = [(idx(add(i, j)), idx(i)) for i in all_upto(P - 1 - sum(j)) if sum(i) != 1]
+        expr = None
+        for gi, wi in terms:
+            expr = f"G[{gi}] * W[{wi}]" if expr is None else f"fma(G[{gi}], W[{wi}], {expr})"
+        if expr is None:
+            expr = "T(0)"
+        out.append(f"    {{ const T pj = {expr};")
+        out.append(f"      Pa[{idx(j)}] += pj;")
+        for e in range(3):
+            qterms = []
+            for i in all_upto(P - 1 - sum(j)):
+                if sum(i) == 0:
+                    continue  # W_e (dipole) vanishes
+                qterms.append((idx(add(i, j)), idx(add(i, E[e])), i[e] + 1))
+            expr_q = f"-R{AX[e]} * pj"
+            qa = f"Qa[{e * NC1 + idx(j)}]"
+            # Q'_ej += sum -(i_e+1) G W  - R_e pj
+            acc = None
+            for gi, wi, c in qterms:
+                t = f"G[{gi}] * W[{wi}]" if c == 1 else f"{fmt(c)} * (G[{gi}] * W[{wi}])"
+                acc = t if acc is None else f"{acc} + {t}"
+            if acc is None:
+                out.append(f"      {qa} = fma(-R{AX[e]}, pj, {qa});")
+            else:
+                out.append(f"      {qa} = {qa} - (({acc}) + R{AX[e]} * pj);")
+        out.append("    }")
+    out.append("  }")
+
+    # monomials x^j / j! for |j| <= Q (into Mo)
+    def mono_lines(Q, var="Mo", dx="dx", dy="dy", dz="dz"):
+        ls = [f"{var}[0] = T(1);"]
+        for k in all_upto(Q)[1:]:
+            d = 0 if k[0] else (1 if k[1] else 2)
+            k1 = list(k)
+            k1[d] -= 1
+            dv = (dx, dy, dz)[d]
+            if k[d] == 1:
+                ls.append(f"{var}[{idx(k)}] = {var}[{idx(tuple(k1))}] * {dv};")
+            else:
+                ls.append(f"{var}[{idx(k)}] = {var}[{idx(tuple(k1))}] * ({dv} * {fmt(1.0 / k[d])});")
+        return ls
+
+    # L2L (standard): Ld_j += sum_{|i| <= P-|j|} Ls_{i+j} d^i/i!
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void shift_std(const T* Ls, T dx, T dy, T dz, T* Ld) {")
+    out.append(f"    T Mo[{NC}];")
+    out += ["    " + s for s in mono_lines(P)]
+    for j in all_upto(P):
+        terms = [(idx(add(i, j)), idx(i)) for i in all_upto(P - sum(j))]
+        expr = f"Ld[{idx(j)}]"
+        for li, mi in terms:
+            expr = f"fma(Ls[{li}], Mo[{mi}], {expr})"
+        out.append(f"    Ld[{idx(j)}] = {expr};")
+    out.append("  }")
+
+    # L2L (conserving): P' = shift(P); Q'_e = shift(Q_e) - d_e shift(P)   (degree P-1)
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void shift_cons(const T* Ps, const T* Qs, T dx, T dy, T dz,"
+               " T* Pd, T* Qd) {")
+    out.append(f"    T Mo[{max(NC1, 1)}];")
+    out += ["    " + s for s in mono_lines(P - 1)]
+    for j in all_upto(P - 1):
+        terms = [(idx(add(i, j)), idx(i)) for i in all_upto(P - 1 - sum(j))]
+        sp = None
+        for li, mi in terms:
+            sp = f"Ps[{li}] * Mo[{mi}]" if sp is None else f"fma(Ps[{li}], Mo[{mi}], {sp})"
+        out.append(f"    {{ const T sp = {sp};")
+        out.append(f"      Pd[{idx(j)}] += sp;")
+        for e in range(3):
+            sq = None
+            for li, mi in terms:
+                sq = f"Qs[{e * NC1 + li}] * Mo[{mi}]" if sq is None else f"fma(Qs[{e * NC1 + li}], Mo[{mi}], {sq})"
+            d = ("dx", "dy", "dz")[e]
+            out.append(f"      Qd[{e * NC1 + idx(j)}] += fma(-{d}, sp, {sq});")
+        out.append("    }")
+    out.append("  }")
+
+    # L2P (standard): a_e = -sum_{|j| <= P-1} L_{j+e} x^j/j!
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void l2p_std(const T* L, T dx, T dy, T dz, T* a) {")
+    out.append(f"    T Mo[{max(NC1, 1)}];")
+    out += ["    " + s for s in mono_lines(P - 1)]
+    for e in range(3):
+        expr = None
+        for j in all_upto(P - 1):
+            t = (idx(add(j, E[e])), idx(j))
+            expr = f"L[{t[0]}] * Mo[{t[1]}]" if expr is None else f"fma(L[{t[0]}], Mo[{t[1]}], {expr})"
+        out.append(f"    a[{e}] = -({expr});")
+    out.append("  }")
+
+    # L2P (conserving): a_e = -x_e P(x) + Q'_e(x)
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void l2p_cons(const T* Pl, const T* Ql, T dx, T dy, T dz, T* a) {")
+    out.append(f"    T Mo[{max(NC1, 1)}];")
+    out += ["    " + s for s in mono_lines(P - 1)]
+    expr = None
+    for j in all_upto(P - 1):
+        expr = f"Pl[{idx(j)}] * Mo[{idx(j)}]" if expr is None else f"fma(Pl[{idx(j)}], Mo[{idx(j)}], {expr})"
+    out.append(f"    const T pv = {expr};")
+    for e in range(3):
+        q = None
+        for j in all_upto(P - 1):
+            q = (f"Ql[{e * NC1 + idx(j)}] * Mo[{idx(j)}]" if q is None
+                 else f"fma(Ql[{e * NC1 + idx(j)}], Mo[{idx(j)}], {q})")
+        d = ("dx", "dy", "dz")[e]
+        out.append(f"    a[{e}] = fma(-{d}, pv, {q});")
+    out.append("  }")
+
+    out.append("};")
+    return out
+
+
+def main(path=None):
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = path or os.path.join(here, "expansions_gen.h")
+    lines = ["// Generated by gen_expansions.py -- do not edit.",
+             "// Cartesian-tensor FMM operators for orders P = 1..%d (see the generator's docstring)." % PMAX,
+             "#pragma once",
+             "",
+             "namespace tfmm {",
+             "",
+             "template <int P> struct Expansion;",
+             ""]
+    for P in range(1, PMAX + 1):
+        lines += gen_struct(P)
+        lines.append("")
+    lines.append("}  // namespace tfmm")
+    text = "\n".join(lines) + "\n"
+    with open(path + ".tmp", "w") as f:
+        f.write(text)
+    os.replace(path + ".tmp", path)
+    return path
+
+
+if __name__ == "__main__":
+    print(main(sys.argv[1] if len(sys.argv) > 1 else None))

@@ -1,0 +1,140 @@
+// Far field, multipole to local (M2L), standard and conserving.
+//
+// For a far pair of nodes (target A, source B) with R = Z_A - Z_B the kernel
+// builds the derivative tensors of the softened kernel at R (generalised D
+// tensors of Eqs. D..Dijkl) with the radial recurrence of expansions_gen.h,
+// then contracts them with B's moments:
+//   standard  : L_j(A) += sum_i D_{i+j}(R) W_i(B)    (Taylor series of Eq. taylor)
+//   conserving: P_j(A) += sum_i G_{i+j}(R) W_i(B), Q'_ej(A) += Q_ej - R_e P_j
+//               (realigned force, Eq. realign, scalar kept to degree p-1).
+// One wavefront owns one target node: its lanes stride over the target's
+// source list, each lane accumulating a private local expansion, and a
+// butterfly reduction across the wave produces the node's locals (written
+// once, no atomics, fixed order -> reproducible).
+#include "common.h"
+#include "expansions_gen.h"
+
+namespace tfmm {
+namespace {
+
+constexpr int MB = 256;  // threads per block = 4 waves = 4 target nodes
+
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <int P, int VAR, typename T>
+__global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets, const int32_t* __restrict__ targets,
+                                                 const uint32_t* __restrict__ off,
+                                                 const int32_t* __restrict__ src,
+                                                 const double4* __restrict__ Z, const T* __restrict__ W,
+                                                 double eps2, double* __restrict__ loc) {
+    using E = Expansion<P>;
+    constexpr int NC = E::NC;
+    constexpr int NC1 = E::NC1;
+    constexpr int NCP = (NC + 3) / 4 * 4;
+    constexpr int NOUT = (VAR == TFMM_CONSERVING) ? 4 * NC1 : NC;
+    const int64_t wave = ((int64_t)blockIdx.x * MB + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (wave >= n_targets) return;
+    const int32_t A = targets[wave];
+    const double4 za = Z[A];
+    T acc[NOUT];
+#pragma unroll
+    for (int k = 0; k < NOUT; ++k) acc[k] = T(0);
+    const uint32_t q1 = off[A + 1];
+    for (uint32_t q = off[A] + lane; q < q1; q += kWave) {
+        const int32_t B = src[q];
+        const double4 zb = Z[B];
+        const T Rx = (T)(za.x - zb.x), Ry = (T)(za.y - zb.y), Rz = (T)(za.z - zb.z);
+        const T s = Rx * Rx + Ry * Ry + Rz * Rz + (T)eps2;
+        const T rinv = rsqrt_t(s);
+        const T inv_s = rinv * rinv;
+        T F[P + 1];
+        F[0] = -rinv;
+#pragma unroll
+        for (int n = 1; n <= P; ++n) F[n] = (T)(-(2 * n - 1)) * F[n - 1] * inv_s;
+        T w[NCP];
+        const typename Vec4<T>::type* wb = reinterpret_cast<const typename Vec4<T>::type*>(W + (int64_t)B * NCP);
+#pragma unroll
+        for (int k = 0; k < NCP / 4; ++k) {
+            const typename Vec4<T>::type v = wb[k];
+            w[4 * k] = v.x;
+            w[4 * k + 1] = v.y;
+            w[4 * k + 2] = v.z;
+            w[4 * k + 3] = v.w;
+        }
+        if constexpr (VAR == TFMM_CONSERVING) {
+            T G[NC1];
+            E::g_derivs(Rx, Ry, Rz, F, G);
+            E::m2l_cons(G, w, Rx, Ry, Rz, acc, acc + NC1);
+        } else {
+            T D[NC];
+            E::phi_derivs(Rx, Ry, Rz, F, D);
+            E::template m2l_std<T, false>(D, w, acc);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NOUT; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+        double* out = loc + (int64_t)A * NOUT;
+#pragma unroll
+        for (int k = 0; k < NOUT; ++k) out[k] = (double)acc[k];
+    }
+}
+
+__global__ void zero_f64_kernel(double* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+template <int P, int VAR, typename T>
+void launch(Tree& t, double eps2, hipStream_t s) {
+    const int64_t nt = t.n_m2l_targets;
+    if (nt <= 0) return;
+    const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
+    hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), dim3((unsigned)cdiv(nt * kWave, MB)), dim3(MB), 0, s, nt,
+                       t.m2l_targets.as<int32_t>(), t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(),
+                       t.nd_Z.as<double4>(), W, eps2, t.loc.as<double>());
+    TFMM_LAUNCHED();
+}
+
+template <int P>
+void dispatch_var(Tree& t, int variant, int precision, double eps2, hipStream_t s) {
+    if (variant == TFMM_CONSERVING) {
+        if (precision == TFMM_MIXED32) launch<P, TFMM_CONSERVING, float>(t, eps2, s);
+        else launch<P, TFMM_CONSERVING, double>(t, eps2, s);
+    } else {
+        if (precision == TFMM_MIXED32) launch<P, TFMM_STANDARD, float>(t, eps2, s);
+        else launch<P, TFMM_STANDARD, double>(t, eps2, s);
+    }
+}
+
+}  // namespace
+
+void run_m2l(Tree& t, int p, int variant, int precision, double eps2, hipStream_t s) {
+    const int nloc = n_local(p, variant);
+    const int64_t tot = t.n_nodes * (int64_t)nloc;
+    t.loc.ensure(t.ctx, (size_t)tot * 8);
+    hipLaunchKernelGGL(zero_f64_kernel, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, t.loc.as<double>(), tot);
+    TFMM_LAUNCHED();
+    switch (p) {
+        case 1: dispatch_var<1>(t, variant, precision, eps2, s); break;
+        case 2: dispatch_var<2>(t, variant, precision, eps2, s); break;
+        case 3: dispatch_var<3>(t, variant, precision, eps2, s); break;
+        case 4: dispatch_var<4>(t, variant, precision, eps2, s); break;
+        case 5: dispatch_var<5>(t, variant, precision, eps2, s); break;
+        case 6: dispatch_var<6>(t, variant, precision, eps2, s); break;
+        case 7: dispatch_var<7>(t, variant, precision, eps2, s); break;
+        case 8: dispatch_var<8>(t, variant, precision, eps2, s); break;
+        default: fail(TFMM_EINVAL, "p must be in 1..8");
+    }
+}
+
+}  // namespace tfmm

@@ -1,0 +1,507 @@
+// Octree construction on the GPU.
+//
+// Every quantity that feeds the multipole acceptance criterion (keys, centres
+// of mass, r_max) is computed in FP64 in one fixed operation order, without
+// contraction, so the node table and the interaction lists are reproducible
+// bit for bit:
+//   keys   q_d = min(2^21 - 1, floor((X_d - lo_d) * scale)), 21 bits per axis
+//          interleaved x, y, z from the most significant bit;
+//   order  stable sort by key;
+//   nodes  (level l, prefix = key >> 3(21 - l)), split while count > n_leaf
+//          and l < 21, numbered level by level in Morton order;
+//   M, S   leaf: left-to-right sums over its sorted particles of m and m X;
+//          inner node: sums over its children in digit order; Z = S / M;
+//   r_max  sqrt of the largest ((dx*dx + dy*dy) + dz*dz) over the node's
+//          particles, d = X - Z (the r_max of Eq. mac_criterion).
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace tfmm {
+namespace {
+
+constexpr int TB = 256;
+constexpr uint32_t QMAX = (1u << kLevels) - 1u;
+
+__global__ __launch_bounds__(TB) void bbox_partial_kernel(const double* __restrict__ pos, int64_t n,
+                                                          double* __restrict__ part) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t a = (int64_t)blockIdx.x * TB + threadIdx.x; a < n; a += (int64_t)gridDim.x * TB) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double v = pos[3 * a + d];
+            lo[d] = v < lo[d] ? v : lo[d];
+            hi[d] = v > hi[d] ? v : hi[d];
+        }
+    }
+    __shared__ double sh[6][TB];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        sh[d][threadIdx.x] = lo[d];
+        sh[3 + d][threadIdx.x] = hi[d];
+    }
+    __syncthreads();
+    for (int s = TB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double a = sh[d][threadIdx.x + s], b = sh[3 + d][threadIdx.x + s];
+                if (a < sh[d][threadIdx.x]) sh[d][threadIdx.x] = a;
+                if (b > sh[3 + d][threadIdx.x]) sh[3 + d][threadIdx.x] = b;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(TB) void bbox_final_kernel(const double* __restrict__ part, int nb,
+                                                        double* __restrict__ out) {
+    if (threadIdx.x < 6) {
+        const int d = threadIdx.x;
+        double v = part[d];
+        for (int b = 1; b < nb; ++b) {
+            const double x = part[6 * b + d];
+            if (d < 3 ? (x < v) : (x > v)) v = x;
+        }
+        out[d] = v;
+    }
+}
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ __launch_bounds__(TB) void morton_kernel(const double* __restrict__ pos, int64_t n, double lox,
+                                                    double loy, double loz, double scale,
+                                                    uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
+    const int64_t a = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (a >= n) return;
+    const double lo[3] = {lox, loy, loz};
+    uint32_t q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double f = floor((pos[3 * a + d] - lo[d]) * scale);
+        q[d] = (f >= (double)QMAX) ? QMAX : (uint32_t)f;
+    }
+    keys[a] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    idx[a] = (int32_t)a;
+}
+
+// Sorted FP64 particles and the level at which a key boundary appears in front
+// of each sorted position (22 = equal keys, never a boundary).
+__global__ __launch_bounds__(TB) void gather_kernel(const double* __restrict__ pos,
+                                                    const double* __restrict__ mass,
+                                                    const uint64_t* __restrict__ keys,
+                                                    const int32_t* __restrict__ perm, int64_t n,
+                                                    double4* __restrict__ Xm, uint8_t* __restrict__ lvlb,
+                                                    int32_t* __restrict__ owner) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= n) return;
+    const int64_t a = perm[j];
+    Xm[j] = make_double4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], mass[a]);
+    uint8_t lb = 0;
+    if (j > 0) {
+        const uint64_t x = keys[j - 1] ^ keys[j];
+        lb = (x == 0) ? (uint8_t)(kLevels + 1) : (uint8_t)(kLevels - (63 - __clzll((long long)x)) / 3);
+    }
+    lvlb[j] = lb;
+    owner[j] = 0;
+}
+
+struct NodeArrays {
+    int32_t* level;
+    uint64_t* prefix;
+    int32_t* first;
+    int32_t* count;
+    int32_t* child_first;
+    int32_t* nchild;
+    int32_t* parent;
+};
+
+__global__ void root_kernel(NodeArrays nd, int32_t n) {
+    nd.level[0] = 0;
+    nd.prefix[0] = 0;
+    nd.first[0] = 0;
+    nd.count[0] = n;
+    nd.child_first[0] = -1;
+    nd.nchild[0] = 0;
+    nd.parent[0] = -1;
+}
+
+// Level l: which sorted positions start a child of a node that splits.
+__global__ __launch_bounds__(TB) void level_flag_kernel(NodeArrays nd, int64_t n, int lvl, int n_leaf,
+                                                        const uint8_t* __restrict__ lvlb,
+                                                        int32_t* __restrict__ owner,
+                                                        int32_t* __restrict__ leaf_of,
+                                                        uint32_t* __restrict__ flag) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= n) return;
+    const int32_t o = owner[j];
+    uint32_t f = 0;
+    if (o >= 0) {
+        if (nd.count[o] > n_leaf && lvl < kLevels) {
+            f = (j == nd.first[o] || lvlb[j] == lvl + 1) ? 1u : 0u;
+        } else {
+            leaf_of[j] = o;
+            owner[j] = -1;
+        }
+    }
+    flag[j] = f;
+}
+
+__global__ __launch_bounds__(TB) void level_create_kernel(NodeArrays nd, int64_t n, int lvl, int32_t le,
+                                                          const uint64_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ flag,
+                                                          const uint32_t* __restrict__ excl,
+                                                          int32_t* __restrict__ owner) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= n) return;
+    const int32_t o = owner[j];
+    if (o < 0) return;
+    const int32_t c = le + (int32_t)(excl[j] + flag[j]) - 1;
+    if (flag[j]) {
+        nd.level[c] = lvl + 1;
+        nd.prefix[c] = keys[j] >> (3 * (kLevels - (lvl + 1)));
+        nd.first[c] = (int32_t)j;
+        nd.parent[c] = o;
+        nd.child_first[c] = -1;
+        nd.nchild[c] = 0;
+    }
+    owner[j] = c;
+}
+
+__global__ __launch_bounds__(TB) void level_finish_kernel(NodeArrays nd, int32_t le, int32_t cnt) {
+    const int32_t i = blockIdx.x * TB + threadIdx.x;
+    if (i >= cnt) return;
+    const int32_t c = le + i;
+    const int32_t P = nd.parent[c];
+    const int32_t end = (i + 1 < cnt && nd.parent[c + 1] == P) ? nd.first[c + 1] : nd.first[P] + nd.count[P];
+    nd.count[c] = end - nd.first[c];
+    if (nd.first[c] == nd.first[P]) nd.child_first[P] = c;
+    atomicAdd(&nd.nchild[P], 1);
+}
+
+__global__ __launch_bounds__(TB) void leaf_flag_kernel(const int32_t* __restrict__ nchild, int64_t nn,
+                                                       uint32_t* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < nn) flag[i] = nchild[i] == 0 ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(TB) void leaf_compact_kernel(const uint32_t* __restrict__ flag,
+                                                          const uint32_t* __restrict__ excl, int64_t nn,
+                                                          int32_t* __restrict__ leaves) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < nn && flag[i]) leaves[excl[i]] = (int32_t)i;
+}
+
+// Mass and centre of mass of the nodes of one level (children done before).
+__global__ __launch_bounds__(TB) void geometry_level_kernel(const int32_t* __restrict__ first,
+                                                            const int32_t* __restrict__ count,
+                                                            const int32_t* __restrict__ child_first,
+                                                            const int32_t* __restrict__ nchild,
+                                                            const double4* __restrict__ Xm, int32_t lb,
+                                                            int32_t le, double4* __restrict__ S,
+                                                            double4* __restrict__ Z) {
+    const int32_t i = lb + blockIdx.x * TB + threadIdx.x;
+    if (i >= le) return;
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    const int32_t nc = nchild[i];
+    if (nc == 0) {
+        const int32_t s0 = first[i], s1 = s0 + count[i];
+        for (int32_t s = s0; s < s1; ++s) {
+            const double4 p = Xm[s];
+            M = M + p.w;
+            sx = sx + p.w * p.x;
+            sy = sy + p.w * p.y;
+            sz = sz + p.w * p.z;
+        }
+    } else {
+        const int32_t c0 = child_first[i];
+        for (int32_t c = c0; c < c0 + nc; ++c) {
+            const double4 q = S[c];
+            M = M + q.w;
+            sx = sx + q.x;
+            sy = sy + q.y;
+            sz = sz + q.z;
+        }
+    }
+    S[i] = make_double4(sx, sy, sz, M);
+    Z[i] = make_double4(sx / M, sy / M, sz / M, M);
+}
+
+__global__ __launch_bounds__(TB) void fill_u64_kernel(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Exact r_max: every particle offers its squared distance to each ancestor's
+// centre of mass; the maximum is order independent (atomicMax on the bits of
+// non-negative doubles), so the result is deterministic.  Levels are walked
+// from the deepest up so that a whole wave often shares a node and reduces
+// before a single atomic.
+__global__ __launch_bounds__(TB) void rmax_kernel(const double4* __restrict__ Xm,
+                                                  const int32_t* __restrict__ leaf_of,
+                                                  const int32_t* __restrict__ level,
+                                                  const int32_t* __restrict__ parent,
+                                                  const double4* __restrict__ Z, int64_t n, int max_level,
+                                                  unsigned long long* __restrict__ r2bits) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    const bool valid = j < n;
+    double4 x = make_double4(0, 0, 0, 0);
+    int32_t cur = -1;
+    if (valid) {
+        x = Xm[j];
+        cur = leaf_of[j];
+    }
+    for (int L = max_level; L >= 0; --L) {
+        const bool act = cur >= 0 && level[cur] == L;
+        double d2 = 0.0;
+        if (act) {
+            const double4 z = Z[cur];
+            const double dx = x.x - z.x, dy = x.y - z.y, dz = x.z - z.z;
+            d2 = (dx * dx + dy * dy) + dz * dz;
+        }
+        const uint64_t am = __ballot(act);
+        const int32_t c0 = __shfl(cur, 0, kWave);
+        const uint64_t same = __ballot(act && cur == c0);
+        if (am == ~0ull && same == ~0ull) {
+            double m = d2;
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                const double u = __shfl_xor(m, o, kWave);
+                m = u > m ? u : m;
+            }
+            if ((threadIdx.x & (kWave - 1)) == 0)
+                atomicMax(&r2bits[c0], (unsigned long long)__double_as_longlong(m));
+        } else if (act) {
+            atomicMax(&r2bits[cur], (unsigned long long)__double_as_longlong(d2));
+        }
+        if (act) cur = parent[cur];
+    }
+}
+
+__global__ __launch_bounds__(TB) void rmax_final_kernel(const unsigned long long* __restrict__ r2bits,
+                                                        int64_t nn, double* __restrict__ rmax) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < nn) rmax[i] = sqrt(__longlong_as_double((long long)r2bits[i]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(TB) void sources_kernel(const double4* __restrict__ Xm,
+                                                     const int32_t* __restrict__ leaf_of,
+                                                     const double4* __restrict__ Z, int64_t n,
+                                                     typename Vec4<T>::type* __restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= n) return;
+    const double4 x = Xm[j];
+    const double4 z = Z[leaf_of[j]];
+    typename Vec4<T>::type r;
+    r.x = (T)(x.x - z.x);
+    r.y = (T)(x.y - z.y);
+    r.z = (T)(x.z - z.z);
+    r.w = (T)x.w;
+    out[j] = r;
+}
+
+unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, TB); }
+
+NodeArrays node_arrays(Tree& t) {
+    return NodeArrays{t.nd_level.as<int32_t>(), t.nd_prefix.as<uint64_t>(), t.nd_first.as<int32_t>(),
+                      t.nd_count.as<int32_t>(), t.nd_child_first.as<int32_t>(), t.nd_nchild.as<int32_t>(),
+                      t.nd_parent.as<int32_t>()};
+}
+
+void ensure_nodes(Tree& t, int64_t cap, int64_t keep, hipStream_t s) {
+    (void)keep;
+    const size_t c = (size_t)cap;
+    t.nd_level.ensure_keep(t.ctx, c * 4, s);
+    t.nd_prefix.ensure_keep(t.ctx, c * 8, s);
+    t.nd_first.ensure_keep(t.ctx, c * 4, s);
+    t.nd_count.ensure_keep(t.ctx, c * 4, s);
+    t.nd_child_first.ensure_keep(t.ctx, c * 4, s);
+    t.nd_nchild.ensure_keep(t.ctx, c * 4, s);
+    t.nd_parent.ensure_keep(t.ctx, c * 4, s);
+}
+
+template <typename V>
+V read_back(Ctx* ctx, const V* dev, hipStream_t s) {
+    TFMM_HIP(hipMemcpyAsync(ctx->pinned, dev, sizeof(V), hipMemcpyDeviceToHost, s));
+    TFMM_HIP(hipStreamSynchronize(s));
+    V v;
+    std::memcpy(&v, ctx->pinned, sizeof(V));
+    return v;
+}
+
+}  // namespace
+
+void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
+    Ctx* ctx = t.ctx;
+    const int64_t n = t.n;
+    const size_t un = (size_t)n;
+
+    // bounding cube (host computes ext and scale exactly as the key definition says)
+    const int nbb = (int)std::min<int64_t>(1024, cdiv(n, TB));
+    t.scratch.ensure(ctx, std::max<size_t>({(size_t)nbb * 6 * 8 + 64, sort_scratch_bytes(n) + 256,
+                                            scan_scratch_bytes(n) + 256}));
+    double* part = t.scratch.as<double>();
+    double* bb = part + 6 * nbb;
+    hipLaunchKernelGGL(bbox_partial_kernel, dim3(nbb), dim3(TB), 0, s, pos, n, part);
+    TFMM_LAUNCHED();
+    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(64), 0, s, (const double*)part, nbb, bb);
+    TFMM_LAUNCHED();
+    TFMM_HIP(hipMemcpyAsync(ctx->pinned, bb, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    TFMM_HIP(hipStreamSynchronize(s));
+    double lohi[6];
+    std::memcpy(lohi, ctx->pinned, sizeof(lohi));
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const volatile double e = lohi[3 + d] - lohi[d];
+        if (e > ext) ext = e;
+    }
+    if (ext == 0.0) ext = 1.0;
+    const volatile double scale = 2097152.0 / ext;
+    t.bbox[0] = lohi[0];
+    t.bbox[1] = lohi[1];
+    t.bbox[2] = lohi[2];
+    t.bbox[3] = ext;
+    t.bbox[4] = scale;
+    if (!std::isfinite(ext) || !std::isfinite((double)scale))
+        fail(TFMM_EINVAL, "positions contain non-finite values");
+
+    // keys and stable order
+    t.keys.ensure(ctx, un * 8);
+    t.keys2.ensure(ctx, un * 8);
+    t.perm.ensure(ctx, un * 4);
+    t.perm2.ensure(ctx, un * 4);
+    hipLaunchKernelGGL(morton_kernel, dim3(grid(n)), dim3(TB), 0, s, pos, n, lohi[0], lohi[1], lohi[2],
+                       (double)scale, t.keys.as<uint64_t>(), t.perm.as<int32_t>());
+    TFMM_LAUNCHED();
+    radix_sort_u64(t.keys.as<uint64_t>(), t.perm.as<int32_t>(), t.keys2.as<uint64_t>(), t.perm2.as<int32_t>(),
+                   n, 3 * kLevels, t.scratch.p, s);
+
+    // sorted particles, boundary levels
+    t.Xm.ensure(ctx, un * 32);
+    t.lvlb.ensure(ctx, un);
+    t.owner.ensure(ctx, un * 4);
+    t.leaf_of.ensure(ctx, un * 4);
+    t.flags.ensure(ctx, un * 4 * 2);
+    hipLaunchKernelGGL(gather_kernel, dim3(grid(n)), dim3(TB), 0, s, pos, mass, t.keys.as<uint64_t>(),
+                       t.perm.as<int32_t>(), n, t.Xm.as<double4>(), t.lvlb.as<uint8_t>(), t.owner.as<int32_t>());
+    TFMM_LAUNCHED();
+
+    // octree, level by level
+    int64_t cap = std::max<int64_t>(1024, 4 * n / std::max(1, t.n_leaf) + 64);
+    ensure_nodes(t, cap, 0, s);
+    NodeArrays nd = node_arrays(t);
+    hipLaunchKernelGGL(root_kernel, dim3(1), dim3(1), 0, s, nd, (int32_t)n);
+    TFMM_LAUNCHED();
+    uint32_t* flag = t.flags.as<uint32_t>();
+    uint32_t* excl = flag + n;
+    t.scratch2.ensure(ctx, 256);
+    uint32_t* total = t.scratch2.as<uint32_t>();
+    void* scan_scr = t.scratch.p;
+    t.level_begin.assign(1, 0);
+    int64_t lb = 0, le = 1;
+    int lvl = 0;
+    for (;; ++lvl) {
+        t.level_begin.push_back(le);
+        hipLaunchKernelGGL(level_flag_kernel, dim3(grid(n)), dim3(TB), 0, s, nd, n, lvl, t.n_leaf,
+                           t.lvlb.as<uint8_t>(), t.owner.as<int32_t>(), t.leaf_of.as<int32_t>(), flag);
+        TFMM_LAUNCHED();
+        if (lvl >= kLevels) break;
+        exclusive_scan_u32(flag, excl, n, scan_scr, total, s);
+        const uint32_t T = read_back(ctx, total, s);
+        if (T == 0) break;
+        if (le + (int64_t)T > cap) {
+            cap = std::max<int64_t>(2 * cap, le + T);
+            ensure_nodes(t, cap, le, s);
+            nd = node_arrays(t);
+        }
+        hipLaunchKernelGGL(level_create_kernel, dim3(grid(n)), dim3(TB), 0, s, nd, n, lvl, (int32_t)le,
+                           t.keys.as<uint64_t>(), (const uint32_t*)flag, (const uint32_t*)excl,
+                           t.owner.as<int32_t>());
+        TFMM_LAUNCHED();
+        hipLaunchKernelGGL(level_finish_kernel, dim3(grid(T)), dim3(TB), 0, s, nd, (int32_t)le, (int32_t)T);
+        TFMM_LAUNCHED();
+        lb = le;
+        le += T;
+    }
+    (void)lb;
+    t.n_nodes = le;
+    t.max_level = lvl;
+    // level_begin holds the start of levels 0..max_level and the end
+    t.level_begin.resize((size_t)t.max_level + 2);
+    t.level_begin[(size_t)t.max_level + 1] = le;
+    const int64_t nn = t.n_nodes;
+
+    // leaves
+    t.flags.ensure(ctx, (size_t)std::max<int64_t>(n, nn) * 4 * 2);
+    t.scratch.ensure(ctx, scan_scratch_bytes(std::max<int64_t>(n, nn)) + 256);
+    scan_scr = t.scratch.p;
+    flag = t.flags.as<uint32_t>();
+    excl = flag + std::max<int64_t>(n, nn);
+    hipLaunchKernelGGL(leaf_flag_kernel, dim3(grid(nn)), dim3(TB), 0, s, nd.nchild, nn, flag);
+    TFMM_LAUNCHED();
+    exclusive_scan_u32(flag, excl, nn, scan_scr, total, s);
+    t.n_leaves = read_back(ctx, total, s);
+    t.leaves.ensure(ctx, (size_t)t.n_leaves * 4);
+    hipLaunchKernelGGL(leaf_compact_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)flag,
+                       (const uint32_t*)excl, nn, t.leaves.as<int32_t>());
+    TFMM_LAUNCHED();
+
+    // geometry, deepest level first
+    t.nd_S.ensure(ctx, (size_t)nn * 32);
+    t.nd_Z.ensure(ctx, (size_t)nn * 32);
+    for (int L = t.max_level; L >= 0; --L) {
+        const int32_t b = (int32_t)t.level_begin[L], e = (int32_t)t.level_begin[L + 1];
+        if (e <= b) continue;
+        hipLaunchKernelGGL(geometry_level_kernel, dim3(grid(e - b)), dim3(TB), 0, s, nd.first, nd.count,
+                           nd.child_first, nd.nchild, t.Xm.as<double4>(), b, e, t.nd_S.as<double4>(),
+                           t.nd_Z.as<double4>());
+        TFMM_LAUNCHED();
+    }
+    t.nd_r2bits.ensure(ctx, (size_t)nn * 8);
+    t.nd_rmax.ensure(ctx, (size_t)nn * 8);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid(nn)), dim3(TB), 0, s, t.nd_r2bits.as<uint64_t>(), nn,
+                       (uint64_t)0);
+    TFMM_LAUNCHED();
+    hipLaunchKernelGGL(rmax_kernel, dim3(grid(n)), dim3(TB), 0, s, t.Xm.as<double4>(), t.leaf_of.as<int32_t>(),
+                       nd.level, nd.parent, t.nd_Z.as<double4>(), n, t.max_level,
+                       t.nd_r2bits.as<unsigned long long>());
+    TFMM_LAUNCHED();
+    hipLaunchKernelGGL(rmax_final_kernel, dim3(grid(nn)), dim3(TB), 0, s, t.nd_r2bits.as<unsigned long long>(),
+                       nn, t.nd_rmax.as<double>());
+    TFMM_LAUNCHED();
+
+    t.walk_valid = false;
+    t.mom_p = -1;
+    t.src_prec = -1;
+}
+
+void prepare_sources(Tree& t, int precision, hipStream_t s) {
+    if (t.src_prec == precision) return;
+    const int64_t n = t.n;
+    if (precision == TFMM_MIXED32) {
+        t.src4.ensure(t.ctx, (size_t)n * 16);
+        hipLaunchKernelGGL(sources_kernel<float>, dim3(grid(n)), dim3(TB), 0, s, t.Xm.as<double4>(),
+                           t.leaf_of.as<int32_t>(), t.nd_Z.as<double4>(), n, t.src4.as<float4>());
+    } else {
+        t.src4.ensure(t.ctx, (size_t)n * 32);
+        hipLaunchKernelGGL(sources_kernel<double>, dim3(grid(n)), dim3(TB), 0, s, t.Xm.as<double4>(),
+                           t.leaf_of.as<int32_t>(), t.nd_Z.as<double4>(), n, t.src4.as<double4>());
+    }
+    TFMM_LAUNCHED();
+    t.src_prec = precision;
+}
+
+}  // namespace tfmm

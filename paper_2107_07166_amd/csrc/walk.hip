@@ -1,0 +1,359 @@
+// Mutual dual-tree walk and per-target interaction lists.
+//
+// The walk processes a frontier of unordered node pairs level-synchronously
+// from (root, root).  For each pair:
+//   A == B : a leaf gives a near (P2P) self pair; otherwise the children
+//            pairs (c_i, c_j), i <= j, join the next frontier;
+//   A != B : R = sqrt((dx*dx + dy*dy) + dz*dz), d = Z_A - Z_B.  The pair is a
+//            far (M2L) pair iff R > 0 and r_A + r_B <= theta * R
+//            (Eq. mac_criterion with theta = tan of the MAC angle); else two
+//            leaves give a near pair; else one node is split (the non-leaf
+//            if one is a leaf, else the larger r_max, then the lower level,
+//            then the lower index) and its children are paired with the other.
+// Counts are compacted with prefix sums, so the emitted lists are in a fixed
+// order and the pair sets do not depend on scheduling.  FP64 without
+// contraction so that every decision is reproducible.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace tfmm {
+namespace {
+
+constexpr int TB = 256;
+
+struct WalkNodes {
+    const int32_t* level;
+    const int32_t* child_first;
+    const int32_t* nchild;
+    const double4* Z;
+    const double* rmax;
+};
+
+struct Decision {
+    int kind;      // 0 near, 1 far, 2 expand self, 3 split S against O
+    int32_t S, O;  // for kind 3
+    uint32_t nnew;
+};
+
+__device__ __forceinline__ Decision decide(const WalkNodes& w, int32_t A, int32_t B, double theta) {
+    Decision d{0, -1, -1, 0u};
+    if (A == B) {
+        const int32_t nc = w.nchild[A];
+        if (nc == 0) {
+            d.kind = 0;
+        } else {
+            d.kind = 2;
+            d.nnew = (uint32_t)(nc * (nc + 1) / 2);
+        }
+        return d;
+    }
+    const double4 za = w.Z[A], zb = w.Z[B];
+    const double dx = za.x - zb.x, dy = za.y - zb.y, dz = za.z - zb.z;
+    const double R = sqrt((dx * dx + dy * dy) + dz * dz);
+    const double ra = w.rmax[A], rb = w.rmax[B];
+    if (R > 0.0 && ra + rb <= theta * R) {
+        d.kind = 1;
+        return d;
+    }
+    const int32_t na = w.nchild[A], nb = w.nchild[B];
+    if (na == 0 && nb == 0) {
+        d.kind = 0;
+        return d;
+    }
+    int32_t S;
+    if (na == 0) S = B;
+    else if (nb == 0) S = A;
+    else if (ra > rb) S = A;
+    else if (rb > ra) S = B;
+    else if (w.level[A] < w.level[B]) S = A;
+    else if (w.level[B] < w.level[A]) S = B;
+    else S = A < B ? A : B;
+    d.kind = 3;
+    d.S = S;
+    d.O = (S == A) ? B : A;
+    d.nnew = (uint32_t)w.nchild[S];
+    return d;
+}
+
+__global__ __launch_bounds__(TB) void walk_count_kernel(WalkNodes w, const int2* __restrict__ fr, int64_t nf,
+                                                        double theta, U3* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= nf) return;
+    const int2 pr = fr[i];
+    const Decision d = decide(w, pr.x, pr.y, theta);
+    U3 c{0u, 0u, 0u};
+    if (d.kind == 0) c.c = 1u;
+    else if (d.kind == 1) c.b = 1u;
+    else c.a = d.nnew;
+    cnt[i] = c;
+}
+
+__global__ __launch_bounds__(TB) void walk_emit_kernel(WalkNodes w, const int2* __restrict__ fr, int64_t nf,
+                                                       double theta, const U3* __restrict__ off,
+                                                       int2* __restrict__ next, int2* __restrict__ far,
+                                                       int64_t far_base, int2* __restrict__ near,
+                                                       int64_t near_base) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= nf) return;
+    const int2 pr = fr[i];
+    const Decision d = decide(w, pr.x, pr.y, theta);
+    const U3 o = off[i];
+    const int32_t lo = pr.x < pr.y ? pr.x : pr.y, hi = pr.x < pr.y ? pr.y : pr.x;
+    if (d.kind == 0) {
+        near[near_base + o.c] = make_int2(lo, hi);
+    } else if (d.kind == 1) {
+        far[far_base + o.b] = make_int2(lo, hi);
+    } else if (d.kind == 2) {
+        const int32_t c0 = w.child_first[pr.x], nc = w.nchild[pr.x];
+        uint32_t k = o.a;
+        for (int32_t a = 0; a < nc; ++a)
+            for (int32_t b = a; b < nc; ++b) next[k++] = make_int2(c0 + a, c0 + b);
+    } else {
+        const int32_t c0 = w.child_first[d.S], nc = w.nchild[d.S];
+        for (int32_t a = 0; a < nc; ++a) next[o.a + a] = make_int2(c0 + a, d.O);
+    }
+}
+
+// Directed entries of the far list: (A <- B) and (B <- A).
+__global__ __launch_bounds__(TB) void far_entries_kernel(const int2* __restrict__ pairs, int64_t np,
+                                                         uint32_t* __restrict__ tgt, int32_t* __restrict__ src,
+                                                         int32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= np) return;
+    const int2 p = pairs[i];
+    tgt[2 * i] = (uint32_t)p.x;
+    src[2 * i] = p.y;
+    tgt[2 * i + 1] = (uint32_t)p.y;
+    src[2 * i + 1] = p.x;
+    atomicAdd(&cnt[p.x], 1);
+    atomicAdd(&cnt[p.y], 1);
+}
+
+__global__ __launch_bounds__(TB) void near_count_kernel(const int2* __restrict__ pairs, int64_t np,
+                                                        uint32_t* __restrict__ c) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= np) return;
+    const int2 p = pairs[i];
+    c[i] = p.x == p.y ? 1u : 2u;
+}
+
+__global__ __launch_bounds__(TB) void near_entries_kernel(const int2* __restrict__ pairs, int64_t np,
+                                                          const uint32_t* __restrict__ off,
+                                                          uint32_t* __restrict__ tgt, int32_t* __restrict__ src,
+                                                          int32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= np) return;
+    const int2 p = pairs[i];
+    const uint32_t o = off[i];
+    tgt[o] = (uint32_t)p.x;
+    src[o] = p.y;
+    atomicAdd(&cnt[p.x], 1);
+    if (p.x != p.y) {
+        tgt[o + 1] = (uint32_t)p.y;
+        src[o + 1] = p.x;
+        atomicAdd(&cnt[p.y], 1);
+    }
+}
+
+__global__ __launch_bounds__(TB) void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(TB) void nonempty_flag_kernel(const int32_t* __restrict__ cnt, int64_t n,
+                                                           uint32_t* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < n) flag[i] = cnt[i] > 0 ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(TB) void compact_kernel(const uint32_t* __restrict__ flag,
+                                                     const uint32_t* __restrict__ excl, int64_t n,
+                                                     int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < n && flag[i]) out[excl[i]] = (int32_t)i;
+}
+
+// Directed near particle interactions: sum over directed leaf pairs of
+// n_t * n_s (self pairs n (n - 1)).
+__global__ __launch_bounds__(TB) void near_work_kernel(const uint32_t* __restrict__ tgt,
+                                                       const int32_t* __restrict__ src, int64_t ne,
+                                                       const int32_t* __restrict__ count,
+                                                       unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long sh[TB];
+    unsigned long long s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < ne; i += (int64_t)gridDim.x * TB) {
+        const int32_t a = (int32_t)tgt[i], b = src[i];
+        const unsigned long long na = (unsigned long long)count[a];
+        s += (a == b) ? na * (na - 1) : na * (unsigned long long)count[b];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = TB / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, sh[0]);
+}
+
+unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, TB); }
+
+int bits_for(int64_t n) {
+    int b = 1;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+template <typename V>
+V read_back(Ctx* ctx, const V* dev, hipStream_t s) {
+    TFMM_HIP(hipMemcpyAsync(ctx->pinned, dev, sizeof(V), hipMemcpyDeviceToHost, s));
+    TFMM_HIP(hipStreamSynchronize(s));
+    V v;
+    std::memcpy(&v, ctx->pinned, sizeof(V));
+    return v;
+}
+
+// Stable sort of directed (target, source) entries by target and CSR offsets.
+void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& cntbuf, DevBuf& off,
+               DevBuf& srcout, hipStream_t s) {
+    Ctx* ctx = t.ctx;
+    const int64_t nn = t.n_nodes;
+    // sort by target
+    t.scratch2.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8 + 256);
+    uint32_t* kalt = t.scratch2.as<uint32_t>();
+    int32_t* valt = reinterpret_cast<int32_t*>(kalt + std::max<int64_t>(ne, 1));
+    t.scratch.ensure(ctx, std::max(sort_scratch_bytes(ne), scan_scratch_bytes(nn + 1)) + 1024);
+    radix_sort_u32(tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(), kalt, valt, ne, bits_for(nn), t.scratch.p, s);
+    // offsets from counts
+    off.ensure(ctx, (size_t)(nn + 1) * 4);
+    uint32_t* cnt = cntbuf.as<uint32_t>();
+    uint32_t* tot = reinterpret_cast<uint32_t*>(t.scratch.as<char>() + scan_scratch_bytes(nn + 1));
+    exclusive_scan_u32(cnt, off.as<uint32_t>(), nn + 1, t.scratch.p, tot, s);
+    srcout.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
+    if (ne > 0)
+        TFMM_HIP(hipMemcpyAsync(srcout.p, srcbuf.p, (size_t)ne * 4, hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace
+
+void walk_tree(Tree& t, double theta, hipStream_t s) {
+    Ctx* ctx = t.ctx;
+    const int64_t nn = t.n_nodes;
+    WalkNodes w{t.nd_level.as<int32_t>(), t.nd_child_first.as<int32_t>(), t.nd_nchild.as<int32_t>(),
+                t.nd_Z.as<double4>(), t.nd_rmax.as<double>()};
+
+    // frontier buffers (int2), counts (U3) and offsets (U3)
+    DevBuf fr, fr2, cnt, off;
+    fr.ensure(ctx, 4096 * 8);
+    int64_t cap_far = std::max<int64_t>(4096, 64 * nn), cap_near = std::max<int64_t>(4096, 16 * nn);
+    t.m2l_pairs.ensure(ctx, (size_t)cap_far * 8);
+    t.p2p_pairs.ensure(ctx, (size_t)cap_near * 8);
+    t.scratch2.ensure(ctx, 256);
+    const int2 root = make_int2(0, 0);
+    TFMM_HIP(hipMemcpyAsync(fr.p, &root, sizeof(int2), hipMemcpyHostToDevice, s));
+    int64_t nf = 1, n_far = 0, n_near = 0;
+    while (nf > 0) {
+        // every buffer resized here is idle: the previous iteration ended with a sync
+        cnt.ensure(ctx, (size_t)nf * sizeof(U3));
+        off.ensure(ctx, (size_t)nf * sizeof(U3));
+        t.scratch.ensure(ctx, scan_scratch_bytes(nf) + 256);
+        hipLaunchKernelGGL(walk_count_kernel, dim3(grid(nf)), dim3(TB), 0, s, w, fr.as<int2>(), nf, theta,
+                           cnt.as<U3>());
+        TFMM_LAUNCHED();
+        U3* tot = t.scratch2.as<U3>();
+        exclusive_scan_u3(cnt.as<U3>(), off.as<U3>(), nf, t.scratch.p, tot, s);
+        const U3 T = read_back(ctx, tot, s);
+        if (n_far + (int64_t)T.b > cap_far) {
+            cap_far = std::max<int64_t>(2 * cap_far, n_far + T.b);
+            t.m2l_pairs.ensure_keep(ctx, (size_t)cap_far * 8, s);
+        }
+        if (n_near + (int64_t)T.c > cap_near) {
+            cap_near = std::max<int64_t>(2 * cap_near, n_near + T.c);
+            t.p2p_pairs.ensure_keep(ctx, (size_t)cap_near * 8, s);
+        }
+        fr2.ensure(ctx, (size_t)std::max<uint32_t>(T.a, 1) * 8);
+        hipLaunchKernelGGL(walk_emit_kernel, dim3(grid(nf)), dim3(TB), 0, s, w, fr.as<int2>(), nf, theta,
+                           off.as<U3>(), fr2.as<int2>(), t.m2l_pairs.as<int2>(), n_far, t.p2p_pairs.as<int2>(),
+                           n_near);
+        TFMM_LAUNCHED();
+        TFMM_HIP(hipStreamSynchronize(s));
+        n_far += T.b;
+        n_near += T.c;
+        nf = T.a;
+        std::swap(fr.p, fr2.p);
+        std::swap(fr.cap, fr2.cap);
+    }
+    t.n_m2l = n_far;
+    t.n_p2p = n_near;
+
+    // far lists: directed, by target
+    {
+        const int64_t ne = 2 * n_far;
+        DevBuf tg, sr, cn;
+        tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
+        sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
+        cn.ensure(ctx, (size_t)(nn + 1) * 4);
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(grid(nn + 1)), dim3(TB), 0, s, cn.as<int32_t>(), nn + 1, 0);
+        TFMM_LAUNCHED();
+        if (n_far > 0) {
+            hipLaunchKernelGGL(far_entries_kernel, dim3(grid(n_far)), dim3(TB), 0, s, t.m2l_pairs.as<int2>(),
+                               n_far, tg.as<uint32_t>(), sr.as<int32_t>(), cn.as<int32_t>());
+            TFMM_LAUNCHED();
+        }
+        build_csr(t, tg, sr, ne, cn, t.m2l_off, t.m2l_src, s);
+        // targets with a non-empty far list
+        DevBuf fl;
+        fl.ensure(ctx, (size_t)(nn + 1) * 8);
+        uint32_t* flag = fl.as<uint32_t>();
+        uint32_t* ex = flag + nn + 1;
+        hipLaunchKernelGGL(nonempty_flag_kernel, dim3(grid(nn)), dim3(TB), 0, s, cn.as<int32_t>(), nn, flag);
+        TFMM_LAUNCHED();
+        t.scratch.ensure(ctx, scan_scratch_bytes(nn) + 256);
+        uint32_t* tot = t.scratch2.as<uint32_t>();
+        exclusive_scan_u32(flag, ex, nn, t.scratch.p, tot, s);
+        t.n_m2l_targets = read_back(ctx, tot, s);
+        t.m2l_targets.ensure(ctx, (size_t)std::max<int64_t>(t.n_m2l_targets, 1) * 4);
+        hipLaunchKernelGGL(compact_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)flag,
+                           (const uint32_t*)ex, nn, t.m2l_targets.as<int32_t>());
+        TFMM_LAUNCHED();
+        TFMM_HIP(hipStreamSynchronize(s));
+    }
+    // near lists
+    {
+        DevBuf c, o, tg, sr, cn;
+        c.ensure(ctx, (size_t)std::max<int64_t>(n_near, 1) * 4);
+        o.ensure(ctx, (size_t)std::max<int64_t>(n_near, 1) * 4);
+        hipLaunchKernelGGL(near_count_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near,
+                           c.as<uint32_t>());
+        TFMM_LAUNCHED();
+        t.scratch.ensure(ctx, scan_scratch_bytes(n_near) + 256);
+        uint32_t* tot = t.scratch2.as<uint32_t>();
+        exclusive_scan_u32(c.as<uint32_t>(), o.as<uint32_t>(), n_near, t.scratch.p, tot, s);
+        const int64_t ne = read_back(ctx, tot, s);
+        tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
+        sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
+        cn.ensure(ctx, (size_t)(nn + 1) * 4);
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(grid(nn + 1)), dim3(TB), 0, s, cn.as<int32_t>(), nn + 1, 0);
+        TFMM_LAUNCHED();
+        hipLaunchKernelGGL(near_entries_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near,
+                           (const uint32_t*)o.as<uint32_t>(), tg.as<uint32_t>(), sr.as<int32_t>(), cn.as<int32_t>());
+        TFMM_LAUNCHED();
+        build_csr(t, tg, sr, ne, cn, t.p2p_off, t.p2p_src, s);
+        // work count
+        t.scratch2.ensure(ctx, 256);
+        unsigned long long* acc = t.scratch2.as<unsigned long long>();
+        TFMM_HIP(hipMemsetAsync(acc, 0, 8, s));
+        const unsigned nb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(ne, TB)));
+        hipLaunchKernelGGL(near_work_kernel, dim3(nb), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
+                           (const int32_t*)sr.as<int32_t>(), ne, t.nd_count.as<int32_t>(), acc);
+        TFMM_LAUNCHED();
+        t.n_near_int = (int64_t)read_back(ctx, acc, s);
+    }
+    t.walk_valid = true;
+    t.walk_theta = theta;
+}
+
+}  // namespace tfmm

@@ -1,0 +1,218 @@
+"""GPU parity against the FP64 oracle, through the C ABI.
+
+Bit-exact: Morton keys, sorted order, the node table (levels, prefixes,
+ranges, links, FP64 masses, centres of mass and r_max) and the far/near pair
+sets.  Floating point: FP64 path rms relative force error <= 1e-12, mixed
+(FP32 P2P/M2L) path <= 2e-6; net force and, for the conserving variant, net
+torque at roundoff.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_07166_amd.generators import WORKLOADS, plummer, uniform_ball
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+TOL_MIXED = 2e-6
+TORQUE_MIXED = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_07166_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _gpu_tree(ctx, pos, m, n_leaf):
+    from paper_2107_07166_amd import api
+    return api.Tree(ctx, _dev(pos), _dev(m), n_leaf=n_leaf)
+
+
+def _erms(f, ref):
+    return float(np.sqrt(np.mean(((f - ref) ** 2).sum(1) / (ref ** 2).sum(1))))
+
+
+def _degenerate(kind):
+    rng = np.random.default_rng(5)
+    if kind == "single":
+        return np.array([[0.3, -0.2, 0.1]]), np.array([1.0])
+    if kind == "pair":
+        return np.array([[0.0, 0.0, 0.0], [1.0, 0.5, 0.25]]), np.array([0.4, 0.6])
+    if kind == "coincident":
+        return np.full((100, 3), 0.25), np.full(100, 0.01)
+    if kind == "coplanar_dups":
+        pos = rng.random((3000, 3))
+        pos[:, 2] = 0.5
+        pos[1000:1200] = pos[17]
+        return pos, rng.uniform(0.5, 1.0, 3000)
+    raise ValueError(kind)
+
+
+TREE_CASES = [
+    ("ball2k", 64), ("ball2k", 8), ("plummer20k", 16), ("plummer20k", 1),
+    ("single", 4), ("pair", 1), ("coincident", 8), ("coplanar_dups", 16),
+]
+
+
+def _case(name):
+    if name == "ball2k":
+        return uniform_ball(2048, 210707166)
+    if name == "plummer20k":
+        return plummer(20000, 210707167)
+    return _degenerate(name)
+
+
+@pytest.mark.parametrize("name,n_leaf", TREE_CASES)
+def test_tree_bitexact(ctx, name, n_leaf):
+    pos, m = _case(name)
+    ot = oracle.Tree(pos, m, n_leaf=n_leaf, theta=0.5)
+    gt = _gpu_tree(ctx, pos, m, n_leaf)
+    g = gt.export()
+    ok, oo = ot.keys()
+    assert np.array_equal(g["keys"], ok)
+    assert np.array_equal(g["order"].astype(np.int64), oo)
+    on = ot.nodes()
+    assert gt.info()["nodes"] == ot.n_nodes
+    for k in ("level", "prefix", "first", "count", "child_first", "nchild", "parent"):
+        assert np.array_equal(g[k].astype(np.int64), on[k].astype(np.int64)), k
+    for k in ("com", "mass", "rmax"):
+        assert np.array_equal(g[k], on[k]), k
+    gt.close()
+
+
+def _pairset(a):
+    a = np.asarray(a, dtype=np.int64).reshape(-1, 2)
+    return np.unique(a[:, 0] * (1 << 32) + a[:, 1])
+
+
+@pytest.mark.parametrize("name,n_leaf", TREE_CASES)
+@pytest.mark.parametrize("theta", [0.0, 0.5, 0.8])
+def test_lists_bitexact(ctx, name, n_leaf, theta):
+    pos, m = _case(name)
+    ot = oracle.Tree(pos, m, n_leaf=n_leaf, theta=theta)
+    gt = _gpu_tree(ctx, pos, m, n_leaf)
+    gt.walk(theta)
+    gf, gn = gt.lists()
+    of, on = ot.lists()
+    assert len(gf) == len(of) and len(gn) == len(on)
+    assert np.array_equal(_pairset(gf), _pairset(of))
+    assert np.array_equal(_pairset(gn), _pairset(on))
+    gt.close()
+
+
+_oracle_cache = {}
+
+
+def _oracle_forces(name, n_leaf, theta, p, eps, variant):
+    key = (name, n_leaf, theta, p, eps, variant)
+    if key not in _oracle_cache:
+        pos, m = _case(name)
+        _oracle_cache[key] = oracle.Tree(pos, m, n_leaf=n_leaf, theta=theta).forces(p, eps, variant)
+    return _oracle_cache[key]
+
+
+FORCE_CASES = [
+    ("ball2k", 64, 0.5, 2, 1e-3), ("ball2k", 8, 0.5, 4, 1e-3), ("ball2k", 8, 0.8, 6, 1e-3),
+    ("ball2k", 16, 0.6, 1, 0.0), ("ball2k", 16, 0.4, 3, 0.05), ("ball2k", 16, 0.7, 5, 1e-3),
+    ("ball2k", 16, 0.7, 7, 1e-3), ("ball2k", 16, 0.7, 8, 1e-3),
+    ("plummer20k", 16, 0.5, 4, 1e-3), ("coplanar_dups", 16, 0.6, 3, 1e-2),
+]
+
+
+@pytest.mark.parametrize("variant", ["standard", "conserving"])
+@pytest.mark.parametrize("name,n_leaf,theta,p,eps", FORCE_CASES)
+def test_forces_fp64(ctx, name, n_leaf, theta, p, eps, variant):
+    pos, m = _case(name)
+    ref = _oracle_forces(name, n_leaf, theta, p, eps, variant)
+    gt = _gpu_tree(ctx, pos, m, n_leaf)
+    f = gt.evaluate(p=p, theta=theta, eps=eps, variant=variant, precision="fp64").cpu().numpy()
+    gt.close()
+    assert _erms(f, ref) <= TOL_FP64
+
+
+@pytest.mark.parametrize("variant", ["standard", "conserving"])
+@pytest.mark.parametrize("name,n_leaf,theta,p,eps", FORCE_CASES)
+def test_forces_mixed(ctx, name, n_leaf, theta, p, eps, variant):
+    pos, m = _case(name)
+    ref = _oracle_forces(name, n_leaf, theta, p, eps, variant)
+    gt = _gpu_tree(ctx, pos, m, n_leaf)
+    ft = gt.evaluate(p=p, theta=theta, eps=eps, variant=variant, precision="mixed32")
+    f = ft.cpu().numpy()
+    d = ctx.diagnostics(_dev(pos), _dev(m), ft)
+    gt.close()
+    assert _erms(f, ref) <= TOL_MIXED
+    if variant == "conserving":
+        assert d[19] <= TORQUE_MIXED
+
+
+def test_direct_limit_theta0(ctx):
+    pos, m = uniform_ball(1500, 3)
+    ref = oracle.direct(pos, m, 1e-3)
+    gt = _gpu_tree(ctx, pos, m, 8)
+    for prec, tol in (("fp64", 1e-12), ("mixed32", 2e-6)):
+        f = gt.evaluate(p=3, theta=0.0, eps=1e-3, variant="conserving", precision=prec).cpu().numpy()
+        assert _erms(f, ref) <= tol, prec
+    gt.close()
+
+
+def test_repeatable_bitwise(ctx):
+    pos, m = plummer(30000, 9)
+    gt = _gpu_tree(ctx, pos, m, 32)
+    a = gt.evaluate(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32").cpu().numpy()
+    b = gt.evaluate(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32").cpu().numpy()
+    gt.rebuild(_dev(pos), _dev(m))
+    c = gt.evaluate(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32").cpu().numpy()
+    gt.close()
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_diagnostics_match_oracle(ctx):
+    pos, m, v = WORKLOADS["plummer1m"].make(n=5000, velocities=True)
+    f = _oracle_forces("ball2k", 64, 0.5, 2, 1e-3, "standard")
+    pos, m, v = pos[:2048], m[:2048], v[:2048]
+    ref = oracle.diagnostics(pos, m, f, vel=v)
+    d = ctx.diagnostics(_dev(pos), _dev(m), _dev(f), vel=_dev(v))
+    np.testing.assert_allclose(d, ref, rtol=1e-10, atol=1e-14 * np.abs(ref).max())
+
+
+def test_full_size_plummer_1m(ctx):
+    """The benchmark workload (Plummer, N = 2^20, p = 4, theta = 0.5) at full size:
+    keys, order, node table and lists bit-exact; forces on a sample of particles
+    against the oracle evaluated particle by particle."""
+    w = WORKLOADS["plummer1m"]
+    pos, m = w.make()
+    n_leaf = 64
+    ot = oracle.Tree(pos, m, n_leaf=n_leaf, theta=w.theta)
+    gt = _gpu_tree(ctx, pos, m, n_leaf)
+    g = gt.export()
+    ok, oo = ot.keys()
+    assert np.array_equal(g["keys"], ok) and np.array_equal(g["order"].astype(np.int64), oo)
+    on = ot.nodes()
+    for k in ("level", "first", "count", "parent"):
+        assert np.array_equal(g[k].astype(np.int64), on[k].astype(np.int64)), k
+    for k in ("com", "rmax"):
+        assert np.array_equal(g[k], on[k]), k
+    gt.walk(w.theta)
+    gf, gn = gt.lists()
+    of, onr = ot.lists()
+    assert np.array_equal(_pairset(gf), _pairset(of))
+    assert np.array_equal(_pairset(gn), _pairset(onr))
+    sample = np.random.default_rng(1).choice(len(m), 48, replace=False)
+    for variant in ("standard", "conserving"):
+        ref = ot.forces(w.p, w.eps, variant, targets=sample)
+        for prec, tol in (("fp64", TOL_FP64), ("mixed32", TOL_MIXED)):
+            f = gt.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision=prec).cpu().numpy()
+            assert _erms(f[sample], ref) <= tol, (variant, prec, _erms(f[sample], ref))
+    gt.close()
