@@ -109,10 +109,16 @@ struct Tree {
     DevBuf p2p_off, p2p_src;
     DevBuf m2l_targets;           // nodes with a non-empty far list
     int64_t n_m2l_targets = 0;
+    DevBuf w_fr, w_fr2, w_cnt, w_off, w_tg, w_sr, w_fl, w_c;  // walk and list-building scratch
+    // near-field work items: a target leaf's list cut into pieces of bounded
+    // source count, each run by one wavefront into its own partial sums
+    int64_t n_items = 0, n_partial = 0;
+    DevBuf it_leaf, it_q0, it_q1, it_pbase;  // per item: leaf, entry range, partial offset
+    DevBuf leaf_item0;                        // per node: first item of a leaf (nodes + 1 entries)
+    DevBuf partial;                           // FP64 partial near-field sums, 3 per (item, target)
 
     // expansions
     int mom_p = -1;
-    DevBuf mom;                   // FP64 raw moments, NC per node
     DevBuf W32, W64;              // (-1)^|k| M_k / k!, NCP per node (FP32 / FP64 copies)
     DevBuf loc;                   // FP64 M2L locals per node (NLOC per node)
     DevBuf loc_leaf;              // FP64 gathered locals per leaf

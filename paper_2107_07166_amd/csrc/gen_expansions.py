@@ -269,6 +269,33 @@ def gen_struct(P):
         out.append(f"    a[{e}] = fma(-{d}, pv, {q});")
     out.append("  }")
 
+    # P2M in the W form: W_k += m (-y)^k / k!   (W_k = (-1)^|k| M_k / k!)
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void p2m(T m, T dx, T dy, T dz, T* W) {")
+    out.append(f"    T Mo[{NC}];")
+    out += ["    " + s for s in mono_lines(P)]
+    for k in all_upto(P):
+        out.append(f"    W[{idx(k)}] = fma(m, Mo[{idx(k)}], W[{idx(k)}]);")
+    out.append("  }")
+
+    # M2M in the W form: W_k(parent) += sum_{i+j=k} W_i(child) (-d)^j / j!,  d = Z_child - Z_parent
+    # (called with dx = -d so that Mo holds (-d)^j / j!)
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void m2m(const T* Ws, T dx, T dy, T dz, T* Wd) {")
+    out.append(f"    T Mo[{NC}];")
+    out += ["    " + s for s in mono_lines(P)]
+    for k in all_upto(P):
+        terms = []
+        for i in all_upto(sum(k)):
+            if i[0] <= k[0] and i[1] <= k[1] and i[2] <= k[2]:
+                j = (k[0] - i[0], k[1] - i[1], k[2] - i[2])
+                terms.append((idx(i), idx(j)))
+        expr = f"Wd[{idx(k)}]"
+        for wi, mi in terms:
+            expr = f"fma(Ws[{wi}], Mo[{mi}], {expr})"
+        out.append(f"    Wd[{idx(k)}] = {expr};")
+    out.append("  }")
+
     out.append("};")
     return out
 

@@ -40,7 +40,9 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets, const int32_
     constexpr int NC1 = E::NC1;
     constexpr int NCP = (NC + 3) / 4 * 4;
     constexpr int NOUT = (VAR == TFMM_CONSERVING) ? 4 * NC1 : NC;
-    const int64_t wave = ((int64_t)blockIdx.x * MB + threadIdx.x) / kWave;
+    // wave index through readfirstlane: the compiler then keeps the target's
+    // list bounds in scalar registers
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (MB / kWave) + threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     if (wave >= n_targets) return;
     const int32_t A = targets[wave];

@@ -2,20 +2,26 @@
 // of every near pair of leaves, both directions, self pairs included (the
 // gradient of Eq. jia with -(r^2 + eps^2)^(-1/2)).
 //
-// One wavefront owns one target leaf.  Its nt <= 64 targets sit on NT = the
-// next power of two >= nt lanes, replicated G = 64 / NT times; replica g
-// takes every G-th source particle, so small leaves still fill the wave, and
-// the replicas are summed by a butterfly at the end.  Coordinates are relative
-// to each particle's own leaf centre of mass (FP32 in the mixed path), the
-// leaf-to-leaf offset Z_B - Z_A is formed in FP64 and rounded once per source
-// leaf, and each source leaf's FP32 partial sum is added into an FP64
-// accumulator.
+// One wavefront (= one workgroup) owns one target leaf.  Its nt <= 64 target
+// particles are replicated G = floor(64 / nt) times across the lanes; replica
+// g takes every G-th staged source, so small leaves still fill the wave.
+// Source leaves are staged into an LDS chunk already expressed in the target
+// leaf's frame: the leaf-to-leaf offset Z_B - Z_A is applied in FP64 and the
+// result rounded once (FP32 in the mixed path), so the inner loop is a uniform
+// stream of LDS broadcasts and FMAs.  Each chunk's FP32 partial sums go into
+// FP64 per-lane accumulators; the replicas are summed through LDS at the end.
+// A leaf's list is cut into work items of bounded source count (a leaf in a
+// sparse halo can be near almost every particle); every item writes its own
+// partial sums and a second kernel adds a leaf's items in order.
+#include <algorithm>
+
 #include "common.h"
 
 namespace tfmm {
 namespace {
 
-constexpr int PB = 256;  // 4 waves per block, one target leaf per wave
+constexpr int CH = 256;   // staged source particles per chunk
+constexpr int UNR = 4;    // inner-loop unroll
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) {
@@ -29,90 +35,209 @@ __device__ __forceinline__ double rsqrt_t(double x) {
     return y;
 }
 
+template <typename T>
+__device__ __forceinline__ T far_away();
+template <> __device__ __forceinline__ float far_away<float>() { return 1.0e18f; }
+template <> __device__ __forceinline__ double far_away<double>() { return 1.0e100; }
+
 template <typename T, bool SAFE>
-__global__ __launch_bounds__(PB) void p2p_kernel(int64_t n_leaves, const int32_t* __restrict__ leaves,
-                                                 const int32_t* __restrict__ first,
-                                                 const int32_t* __restrict__ count,
-                                                 const uint32_t* __restrict__ off,
-                                                 const int32_t* __restrict__ src,
-                                                 const double4* __restrict__ Z,
-                                                 const typename Vec4<T>::type* __restrict__ P, T eps2,
-                                                 double* __restrict__ near) {
-    using V4 = typename Vec4<T>::type;
-    const int64_t wave = ((int64_t)blockIdx.x * PB + threadIdx.x) / kWave;
+__device__ __forceinline__ void interact(const typename Vec4<T>::type& s, T tx, T ty, T tz, T eps2, T& ax,
+                                         T& ay, T& az) {
+    const T dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
+    const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+    const T ri = rsqrt_t(r2);
+    T w = s.w * ri * (ri * ri);
+    if (SAFE) w = (r2 > T(0)) ? w : T(0);
+    ax = fma(w, dx, ax);
+    ay = fma(w, dy, ay);
+    az = fma(w, dz, az);
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
     const int lane = threadIdx.x & (kWave - 1);
-    if (wave >= n_leaves) return;
-    const int32_t A = leaves[wave];
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int u = __shfl_up(v, d, kWave);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+template <typename T, bool SAFE>
+__global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ it_leaf,
+                                                    const uint32_t* __restrict__ it_q0,
+                                                    const uint32_t* __restrict__ it_q1,
+                                                    const uint32_t* __restrict__ it_pbase,
+                                                    const int32_t* __restrict__ first,
+                                                    const int32_t* __restrict__ count,
+                                                    const int32_t* __restrict__ src,
+                                                    const double4* __restrict__ Z,
+                                                    const typename Vec4<T>::type* __restrict__ P, T eps2,
+                                                    double* __restrict__ partial) {
+    using V4 = typename Vec4<T>::type;
+    constexpr int SPL = CH / kWave;  // staged sources per lane per chunk
+    __shared__ V4 stage[CH + kWave];
+    __shared__ int e_start[kWave];
+    __shared__ int e_first[kWave];
+    __shared__ double e_off[3][kWave];
+    __shared__ double red[3][kWave];
+    const int lane = threadIdx.x;
+    const int32_t A = it_leaf[blockIdx.x];
     const int32_t fa = first[A], na = count[A];
     const double4 za = Z[A];
-    const uint32_t q0 = off[A], q1 = off[A + 1];
+    const uint32_t q0 = it_q0[blockIdx.x], q1 = it_q1[blockIdx.x];
+    double* out = partial + 3 * (int64_t)it_pbase[blockIdx.x];
+    V4 pad;
+    pad.x = far_away<T>();
+    pad.y = far_away<T>();
+    pad.z = far_away<T>();
+    pad.w = T(0);
+
     for (int32_t tc = 0; tc < na; tc += kWave) {
         const int nt = (na - tc) < kWave ? (na - tc) : kWave;
-        int lg = 0;
-        while ((1 << lg) < nt) ++lg;
-        const int NT = 1 << lg;
-        const int G = kWave >> lg;
-        const int tl = lane & (NT - 1);
-        const int g = lane >> lg;
-        const bool act = tl < nt;
-        V4 me;
-        if (act) me = P[fa + tc + tl];
-        else { me.x = T(0); me.y = T(0); me.z = T(0); me.w = T(0); }
+        const int G = kWave / nt;
+        const int tl = lane % nt;
+        const int g = lane / nt;
+        const bool act = g < G;
+        const V4 me = P[fa + tc + tl];
         double ax = 0.0, ay = 0.0, az = 0.0;
-        for (uint32_t q = q0; q < q1; ++q) {
-            const int32_t B = src[q];
-            const int32_t fb = first[B], nb = count[B];
-            const double4 zb = Z[B];
-            const T tx = me.x - (T)(zb.x - za.x);
-            const T ty = me.y - (T)(zb.y - za.y);
-            const T tz = me.z - (T)(zb.z - za.z);
-            T sx = T(0), sy = T(0), sz = T(0);
-            if (act) {
-                for (int k = g; k < nb; k += G) {
-                    const V4 sp = P[fb + k];
-                    const T dx = sp.x - tx, dy = sp.y - ty, dz = sp.z - tz;
-                    const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-                    const T ri = rsqrt_t(r2);
-                    T w = sp.w * ri * (ri * ri);
-                    if (SAFE) w = (r2 > T(0)) ? w : T(0);
-                    sx = fma(w, dx, sx);
-                    sy = fma(w, dy, sy);
-                    sz = fma(w, dz, sz);
-                }
+
+        for (uint32_t qb = q0; qb < q1; qb += kWave) {
+            // one list entry per lane: source leaf, its range and its offset
+            const int ne = (int)((q1 - qb) < (uint32_t)kWave ? (q1 - qb) : (uint32_t)kWave);
+            int nb = 0;
+            if (lane < ne) {
+                const int32_t B = src[qb + lane];
+                const double4 zb = Z[B];
+                nb = count[B];
+                e_first[lane] = first[B];
+                e_off[0][lane] = zb.x - za.x;
+                e_off[1][lane] = zb.y - za.y;
+                e_off[2][lane] = zb.z - za.z;
             }
-            ax += (double)sx;
-            ay += (double)sy;
-            az += (double)sz;
+            const int incl = wave_incl_scan(nb);
+            const int total = __shfl(incl, kWave - 1, kWave);
+            e_start[lane] = (lane < ne) ? incl - nb : 0x7fffffff;
+            __syncthreads();
+
+            for (int c0 = 0; c0 < total; c0 += CH) {
+                const int cnt = (total - c0) < CH ? (total - c0) : CH;
+                // stage: lane takes sources c0 + lane + 64 k; entry by binary search
+                int idx[SPL], ent[SPL];
+#pragma unroll
+                for (int k = 0; k < SPL; ++k) {
+                    const int sidx = c0 + lane + kWave * k;
+                    int lo = 0;
+#pragma unroll
+                    for (int st = kWave / 2; st > 0; st >>= 1)
+                        if (e_start[lo + st] <= sidx) lo += st;
+                    ent[k] = lo;
+                    idx[k] = e_first[lo] + (sidx - e_start[lo]);
+                }
+                V4 v[SPL];
+#pragma unroll
+                for (int k = 0; k < SPL; ++k)
+                    if (lane + kWave * k < cnt) v[k] = P[idx[k]];
+#pragma unroll
+                for (int k = 0; k < SPL; ++k) {
+                    if (lane + kWave * k < cnt) {
+                        V4 w;
+                        w.x = (T)((double)v[k].x + e_off[0][ent[k]]);
+                        w.y = (T)((double)v[k].y + e_off[1][ent[k]]);
+                        w.z = (T)((double)v[k].z + e_off[2][ent[k]]);
+                        w.w = v[k].w;
+                        stage[lane + kWave * k] = w;
+                    }
+                }
+                // pad to a multiple of G, then run: replica g takes g, g+G, ...
+                const int cp = (cnt + G - 1) / G * G;
+                if (cnt + lane < cp) stage[cnt + lane] = pad;
+                __syncthreads();
+                T sx = T(0), sy = T(0), sz = T(0);
+                if (act) {
+                    const int step = G * UNR;
+                    const int cmain = cp / step * step;
+                    int k = g;
+                    for (; k < cmain; k += step) {
+#pragma unroll
+                        for (int u = 0; u < UNR; ++u)
+                            interact<T, SAFE>(stage[k + u * G], me.x, me.y, me.z, eps2, sx, sy, sz);
+                    }
+                    for (; k < cp; k += G) interact<T, SAFE>(stage[k], me.x, me.y, me.z, eps2, sx, sy, sz);
+                }
+                ax += (double)sx;
+                ay += (double)sy;
+                az += (double)sz;
+                __syncthreads();
+            }
         }
-        for (int o = NT; o < kWave; o <<= 1) {
-            ax += __shfl_xor(ax, o, kWave);
-            ay += __shfl_xor(ay, o, kWave);
-            az += __shfl_xor(az, o, kWave);
+
+        red[0][lane] = ax;
+        red[1][lane] = ay;
+        red[2][lane] = az;
+        __syncthreads();
+        if (lane < nt) {
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int r = 0; r < G; ++r) {
+                sx += red[0][r * nt + lane];
+                sy += red[1][r * nt + lane];
+                sz += red[2][r * nt + lane];
+            }
+            const int64_t j = (int64_t)(tc + lane);
+            out[3 * j] = sx;
+            out[3 * j + 1] = sy;
+            out[3 * j + 2] = sz;
         }
-        if (act && g == 0) {
-            const int64_t j = (int64_t)(fa + tc + tl);
-            near[3 * j] = ax;
-            near[3 * j + 1] = ay;
-            near[3 * j + 2] = az;
-        }
+        __syncthreads();
     }
+}
+
+// near[j] = sum over the work items of j's leaf, in item order.
+__global__ __launch_bounds__(256) void p2p_reduce_kernel(int64_t n, int64_t n_items,
+                                                         const int32_t* __restrict__ leaf_of,
+                                                         const int32_t* __restrict__ first,
+                                                         const int32_t* __restrict__ leaf_item0,
+                                                         const int32_t* __restrict__ it_leaf,
+                                                         const uint32_t* __restrict__ it_pbase,
+                                                         const double* __restrict__ partial,
+                                                         double* __restrict__ near) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const int32_t L = leaf_of[j];
+    const int64_t r = j - first[L];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int64_t i = leaf_item0[L]; i < n_items && it_leaf[i] == L; ++i) {
+        const double* p = partial + 3 * ((int64_t)it_pbase[i] + r);
+        sx += p[0];
+        sy += p[1];
+        sz += p[2];
+    }
+    near[3 * j] = sx;
+    near[3 * j + 1] = sy;
+    near[3 * j + 2] = sz;
 }
 
 template <typename T>
 void launch(Tree& t, double eps2, hipStream_t s) {
     using V4 = typename Vec4<T>::type;
-    const int64_t nl = t.n_leaves;
-    const dim3 g((unsigned)cdiv(nl * kWave, PB));
+    const int64_t ni = t.n_items;
+    if (ni <= 0) return;
+    const dim3 g((unsigned)ni);
     if (eps2 > 0.0)
-        hipLaunchKernelGGL((p2p_kernel<T, false>), g, dim3(PB), 0, s, nl, t.leaves.as<int32_t>(),
-                           t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(), t.p2p_off.as<uint32_t>(),
-                           t.p2p_src.as<int32_t>(), t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2,
-                           t.near3.as<double>());
+        hipLaunchKernelGGL((p2p_kernel<T, false>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
+                           t.it_q0.as<uint32_t>(), t.it_q1.as<uint32_t>(), t.it_pbase.as<uint32_t>(),
+                           t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(), t.p2p_src.as<int32_t>(),
+                           t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.partial.as<double>());
     else
-        hipLaunchKernelGGL((p2p_kernel<T, true>), g, dim3(PB), 0, s, nl, t.leaves.as<int32_t>(),
-                           t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(), t.p2p_off.as<uint32_t>(),
-                           t.p2p_src.as<int32_t>(), t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2,
-                           t.near3.as<double>());
+        hipLaunchKernelGGL((p2p_kernel<T, true>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
+                           t.it_q0.as<uint32_t>(), t.it_q1.as<uint32_t>(), t.it_pbase.as<uint32_t>(),
+                           t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(), t.p2p_src.as<int32_t>(),
+                           t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.partial.as<double>());
+    TFMM_LAUNCHED();
+    hipLaunchKernelGGL(p2p_reduce_kernel, dim3((unsigned)cdiv(t.n, 256)), dim3(256), 0, s, t.n, ni,
+                       t.leaf_of.as<int32_t>(), t.nd_first.as<int32_t>(), t.leaf_item0.as<int32_t>(),
+                       t.it_leaf.as<int32_t>(), t.it_pbase.as<uint32_t>(), t.partial.as<double>(),
+                       t.near3.as<double>());
     TFMM_LAUNCHED();
 }
 
@@ -120,6 +245,7 @@ void launch(Tree& t, double eps2, hipStream_t s) {
 
 void run_p2p(Tree& t, int precision, double eps2, hipStream_t s) {
     t.near3.ensure(t.ctx, (size_t)t.n * 24);
+    t.partial.ensure(t.ctx, (size_t)std::max<int64_t>(t.n_partial, 1) * 24);
     if (precision == TFMM_MIXED32) launch<float>(t, eps2, s);
     else launch<double>(t, eps2, s);
 }

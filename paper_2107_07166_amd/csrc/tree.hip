@@ -60,15 +60,31 @@ __global__ __launch_bounds__(TB) void bbox_partial_kernel(const double* __restri
 
 __global__ __launch_bounds__(TB) void bbox_final_kernel(const double* __restrict__ part, int nb,
                                                         double* __restrict__ out) {
-    if (threadIdx.x < 6) {
-        const int d = threadIdx.x;
-        double v = part[d];
-        for (int b = 1; b < nb; ++b) {
-            const double x = part[6 * b + d];
-            if (d < 3 ? (x < v) : (x > v)) v = x;
+    __shared__ double sh[6][TB];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nb; b += TB) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double lo = part[6 * b + d], hi = part[6 * b + 3 + d];
+            v[d] = lo < v[d] ? lo : v[d];
+            v[3 + d] = hi > v[3 + d] ? hi : v[3 + d];
         }
-        out[d] = v;
     }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) sh[d][threadIdx.x] = v[d];
+    __syncthreads();
+    for (int s = TB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double a = sh[d][threadIdx.x + s], b = sh[3 + d][threadIdx.x + s];
+                if (a < sh[d][threadIdx.x]) sh[d][threadIdx.x] = a;
+                if (b > sh[3 + d][threadIdx.x]) sh[3 + d][threadIdx.x] = b;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v) {
@@ -247,8 +263,9 @@ __global__ __launch_bounds__(TB) void fill_u64_kernel(uint64_t* __restrict__ p, 
 // Exact r_max: every particle offers its squared distance to each ancestor's
 // centre of mass; the maximum is order independent (atomicMax on the bits of
 // non-negative doubles), so the result is deterministic.  Levels are walked
-// from the deepest up so that a whole wave often shares a node and reduces
-// before a single atomic.
+// from the deepest up; at each level the lanes of a wave (consecutive sorted
+// particles, so a node's lanes are contiguous) take a segmented maximum and
+// only the last lane of each segment issues the atomic.
 __global__ __launch_bounds__(TB) void rmax_kernel(const double4* __restrict__ Xm,
                                                   const int32_t* __restrict__ leaf_of,
                                                   const int32_t* __restrict__ level,
@@ -271,21 +288,18 @@ __global__ __launch_bounds__(TB) void rmax_kernel(const double4* __restrict__ Xm
             const double dx = x.x - z.x, dy = x.y - z.y, dz = x.z - z.z;
             d2 = (dx * dx + dy * dy) + dz * dz;
         }
-        const uint64_t am = __ballot(act);
-        const int32_t c0 = __shfl(cur, 0, kWave);
-        const uint64_t same = __ballot(act && cur == c0);
-        if (am == ~0ull && same == ~0ull) {
-            double m = d2;
+        const int lane = threadIdx.x & (kWave - 1);
+        const int32_t key = act ? cur : -1;
+        double m = d2;
 #pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) {
-                const double u = __shfl_xor(m, o, kWave);
-                m = u > m ? u : m;
-            }
-            if ((threadIdx.x & (kWave - 1)) == 0)
-                atomicMax(&r2bits[c0], (unsigned long long)__double_as_longlong(m));
-        } else if (act) {
-            atomicMax(&r2bits[cur], (unsigned long long)__double_as_longlong(d2));
+        for (int o = 1; o < kWave; o <<= 1) {
+            const double u = __shfl_up(m, o, kWave);
+            const int32_t ku = __shfl_up(key, o, kWave);
+            if (lane >= o && ku == key) m = u > m ? u : m;
         }
+        const int32_t knext = __shfl_down(key, 1, kWave);
+        if (act && (lane == kWave - 1 || knext != key))
+            atomicMax(&r2bits[cur], (unsigned long long)__double_as_longlong(m));
         if (act) cur = parent[cur];
     }
 }
@@ -357,7 +371,7 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     double* bb = part + 6 * nbb;
     hipLaunchKernelGGL(bbox_partial_kernel, dim3(nbb), dim3(TB), 0, s, pos, n, part);
     TFMM_LAUNCHED();
-    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(64), 0, s, (const double*)part, nbb, bb);
+    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(TB), 0, s, (const double*)part, nbb, bb);
     TFMM_LAUNCHED();
     TFMM_HIP(hipMemcpyAsync(ctx->pinned, bb, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
     TFMM_HIP(hipStreamSynchronize(s));

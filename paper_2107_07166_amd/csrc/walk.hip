@@ -120,8 +120,7 @@ __global__ __launch_bounds__(TB) void walk_emit_kernel(WalkNodes w, const int2* 
 
 // Directed entries of the far list: (A <- B) and (B <- A).
 __global__ __launch_bounds__(TB) void far_entries_kernel(const int2* __restrict__ pairs, int64_t np,
-                                                         uint32_t* __restrict__ tgt, int32_t* __restrict__ src,
-                                                         int32_t* __restrict__ cnt) {
+                                                         uint32_t* __restrict__ tgt, int32_t* __restrict__ src) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i >= np) return;
     const int2 p = pairs[i];
@@ -129,8 +128,6 @@ __global__ __launch_bounds__(TB) void far_entries_kernel(const int2* __restrict_
     src[2 * i] = p.y;
     tgt[2 * i + 1] = (uint32_t)p.y;
     src[2 * i + 1] = p.x;
-    atomicAdd(&cnt[p.x], 1);
-    atomicAdd(&cnt[p.y], 1);
 }
 
 __global__ __launch_bounds__(TB) void near_count_kernel(const int2* __restrict__ pairs, int64_t np,
@@ -143,31 +140,39 @@ __global__ __launch_bounds__(TB) void near_count_kernel(const int2* __restrict__
 
 __global__ __launch_bounds__(TB) void near_entries_kernel(const int2* __restrict__ pairs, int64_t np,
                                                           const uint32_t* __restrict__ off,
-                                                          uint32_t* __restrict__ tgt, int32_t* __restrict__ src,
-                                                          int32_t* __restrict__ cnt) {
+                                                          uint32_t* __restrict__ tgt, int32_t* __restrict__ src) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i >= np) return;
     const int2 p = pairs[i];
     const uint32_t o = off[i];
     tgt[o] = (uint32_t)p.x;
     src[o] = p.y;
-    atomicAdd(&cnt[p.x], 1);
     if (p.x != p.y) {
         tgt[o + 1] = (uint32_t)p.y;
         src[o + 1] = p.x;
-        atomicAdd(&cnt[p.y], 1);
     }
+}
+
+// CSR offsets from targets sorted ascending: off[t] = first entry with target
+// >= t, for t = 0..nn (each t written by exactly one thread).
+__global__ __launch_bounds__(TB) void csr_offsets_kernel(const uint32_t* __restrict__ keys, int64_t ne,
+                                                         int64_t nn, uint32_t* __restrict__ off) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i > ne) return;
+    const int64_t lo = (i == 0) ? 0 : (int64_t)keys[i - 1] + 1;
+    const int64_t hi = (i == ne) ? nn : (int64_t)keys[i];
+    for (int64_t t = lo; t <= hi; ++t) off[t] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(TB) void nonempty_from_off_kernel(const uint32_t* __restrict__ off, int64_t n,
+                                                               uint32_t* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < n) flag[i] = off[i + 1] > off[i] ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(TB) void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i < n) p[i] = v;
-}
-
-__global__ __launch_bounds__(TB) void nonempty_flag_kernel(const int32_t* __restrict__ cnt, int64_t n,
-                                                           uint32_t* __restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i < n) flag[i] = cnt[i] > 0 ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(TB) void compact_kernel(const uint32_t* __restrict__ flag,
@@ -199,6 +204,57 @@ __global__ __launch_bounds__(TB) void near_work_kernel(const uint32_t* __restric
     if (threadIdx.x == 0) atomicAdd(out, sh[0]);
 }
 
+
+// ---- near-field work items -------------------------------------------------
+// A target leaf's near list is cut before entry q when the number of source
+// particles preceding q in that list crosses a multiple of kItemSources, so no
+// wavefront receives more than about kItemSources sources per target.  (The
+// prefix is taken modulo 2^32; only differences inside one list are used.)
+constexpr uint32_t kItemSources = 4096;
+
+__global__ __launch_bounds__(TB) void entry_sources_kernel(const int32_t* __restrict__ src, int64_t ne,
+                                                           const int32_t* __restrict__ count,
+                                                           uint32_t* __restrict__ c) {
+    const int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (q < ne) c[q] = (uint32_t)count[src[q]];
+}
+
+__global__ __launch_bounds__(TB) void item_flag_kernel(const uint32_t* __restrict__ tgt,
+                                                       const uint32_t* __restrict__ P,
+                                                       const uint32_t* __restrict__ off, int64_t ne,
+                                                       uint32_t* __restrict__ flag) {
+    const int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (q >= ne) return;
+    const uint32_t q0 = off[tgt[q]];
+    uint32_t f = 1u;
+    if ((uint32_t)q != q0) f = ((P[q] - P[q0]) / kItemSources != (P[q - 1] - P[q0]) / kItemSources) ? 1u : 0u;
+    flag[q] = f;
+}
+
+__global__ __launch_bounds__(TB) void item_build_kernel(const uint32_t* __restrict__ flag,
+                                                        const uint32_t* __restrict__ excl,
+                                                        const uint32_t* __restrict__ tgt, int64_t ne,
+                                                        int32_t* __restrict__ it_leaf, uint32_t* __restrict__ it_q0) {
+    const int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (q >= ne || !flag[q]) return;
+    const uint32_t i = excl[q];
+    it_q0[i] = (uint32_t)q;
+    it_leaf[i] = (int32_t)tgt[q];
+}
+
+__global__ __launch_bounds__(TB) void item_finish_kernel(int64_t T, int64_t ne, const uint32_t* __restrict__ it_q0,
+                                                         const int32_t* __restrict__ it_leaf,
+                                                         const int32_t* __restrict__ count,
+                                                         uint32_t* __restrict__ it_q1, uint32_t* __restrict__ pc,
+                                                         int32_t* __restrict__ leaf_item0) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= T) return;
+    it_q1[i] = (i + 1 < T) ? it_q0[i + 1] : (uint32_t)ne;
+    const int32_t L = it_leaf[i];
+    pc[i] = (uint32_t)count[L];
+    if (i == 0 || it_leaf[i - 1] != L) leaf_item0[L] = (int32_t)i;
+}
+
 unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, TB); }
 
 int bits_for(int64_t n) {
@@ -216,25 +272,25 @@ V read_back(Ctx* ctx, const V* dev, hipStream_t s) {
     return v;
 }
 
-// Stable sort of directed (target, source) entries by target and CSR offsets.
-void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& cntbuf, DevBuf& off,
-               DevBuf& srcout, hipStream_t s) {
+// Stable sort of directed (target, source) entries by target, then CSR
+// offsets from the sorted targets.  The sources of every target stay in the
+// walk's emission order.
+void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& off, DevBuf& srcout,
+               hipStream_t s) {
     Ctx* ctx = t.ctx;
     const int64_t nn = t.n_nodes;
-    // sort by target
     t.scratch2.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8 + 256);
     uint32_t* kalt = t.scratch2.as<uint32_t>();
     int32_t* valt = reinterpret_cast<int32_t*>(kalt + std::max<int64_t>(ne, 1));
-    t.scratch.ensure(ctx, std::max(sort_scratch_bytes(ne), scan_scratch_bytes(nn + 1)) + 1024);
+    t.scratch.ensure(ctx, sort_scratch_bytes(ne) + 1024);
     radix_sort_u32(tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(), kalt, valt, ne, bits_for(nn), t.scratch.p, s);
-    // offsets from counts
     off.ensure(ctx, (size_t)(nn + 1) * 4);
-    uint32_t* cnt = cntbuf.as<uint32_t>();
-    uint32_t* tot = reinterpret_cast<uint32_t*>(t.scratch.as<char>() + scan_scratch_bytes(nn + 1));
-    exclusive_scan_u32(cnt, off.as<uint32_t>(), nn + 1, t.scratch.p, tot, s);
-    srcout.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
-    if (ne > 0)
-        TFMM_HIP(hipMemcpyAsync(srcout.p, srcbuf.p, (size_t)ne * 4, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(csr_offsets_kernel, dim3(grid(ne + 1)), dim3(TB), 0, s, (const uint32_t*)tgtbuf.as<uint32_t>(),
+                       ne, nn, off.as<uint32_t>());
+    TFMM_LAUNCHED();
+    std::swap(srcbuf.p, srcout.p);
+    std::swap(srcbuf.cap, srcout.cap);
+    std::swap(srcbuf.ctx, srcout.ctx);
 }
 
 }  // namespace
@@ -245,12 +301,21 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
     WalkNodes w{t.nd_level.as<int32_t>(), t.nd_child_first.as<int32_t>(), t.nd_nchild.as<int32_t>(),
                 t.nd_Z.as<double4>(), t.nd_rmax.as<double>()};
 
-    // frontier buffers (int2), counts (U3) and offsets (U3)
-    DevBuf fr, fr2, cnt, off;
+    // frontier (int2), per-pair counts and offsets (U3); all tree-owned, grow-only
+    DevBuf& fr = t.w_fr;
+    DevBuf& fr2 = t.w_fr2;
+    DevBuf& cnt = t.w_cnt;
+    DevBuf& off = t.w_off;
     fr.ensure(ctx, 4096 * 8);
-    int64_t cap_far = std::max<int64_t>(4096, 64 * nn), cap_near = std::max<int64_t>(4096, 16 * nn);
-    t.m2l_pairs.ensure(ctx, (size_t)cap_far * 8);
-    t.p2p_pairs.ensure(ctx, (size_t)cap_near * 8);
+    int64_t cap_far = (int64_t)(t.m2l_pairs.cap / 8), cap_near = (int64_t)(t.p2p_pairs.cap / 8);
+    if (cap_far < 4096) {
+        cap_far = std::max<int64_t>(4096, 64 * nn);
+        t.m2l_pairs.ensure(ctx, (size_t)cap_far * 8);
+    }
+    if (cap_near < 4096) {
+        cap_near = std::max<int64_t>(4096, 16 * nn);
+        t.p2p_pairs.ensure(ctx, (size_t)cap_near * 8);
+    }
     t.scratch2.ensure(ctx, 256);
     const int2 root = make_int2(0, 0);
     TFMM_HIP(hipMemcpyAsync(fr.p, &root, sizeof(int2), hipMemcpyHostToDevice, s));
@@ -279,37 +344,35 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
                            off.as<U3>(), fr2.as<int2>(), t.m2l_pairs.as<int2>(), n_far, t.p2p_pairs.as<int2>(),
                            n_near);
         TFMM_LAUNCHED();
-        TFMM_HIP(hipStreamSynchronize(s));
         n_far += T.b;
         n_near += T.c;
         nf = T.a;
         std::swap(fr.p, fr2.p);
         std::swap(fr.cap, fr2.cap);
+        std::swap(fr.ctx, fr2.ctx);
     }
     t.n_m2l = n_far;
     t.n_p2p = n_near;
 
+    DevBuf& tg = t.w_tg;
+    DevBuf& sr = t.w_sr;
     // far lists: directed, by target
     {
         const int64_t ne = 2 * n_far;
-        DevBuf tg, sr, cn;
         tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
-        cn.ensure(ctx, (size_t)(nn + 1) * 4);
-        hipLaunchKernelGGL(fill_i32_kernel, dim3(grid(nn + 1)), dim3(TB), 0, s, cn.as<int32_t>(), nn + 1, 0);
-        TFMM_LAUNCHED();
         if (n_far > 0) {
             hipLaunchKernelGGL(far_entries_kernel, dim3(grid(n_far)), dim3(TB), 0, s, t.m2l_pairs.as<int2>(),
-                               n_far, tg.as<uint32_t>(), sr.as<int32_t>(), cn.as<int32_t>());
+                               n_far, tg.as<uint32_t>(), sr.as<int32_t>());
             TFMM_LAUNCHED();
         }
-        build_csr(t, tg, sr, ne, cn, t.m2l_off, t.m2l_src, s);
+        build_csr(t, tg, sr, ne, t.m2l_off, t.m2l_src, s);
         // targets with a non-empty far list
-        DevBuf fl;
-        fl.ensure(ctx, (size_t)(nn + 1) * 8);
-        uint32_t* flag = fl.as<uint32_t>();
+        t.w_fl.ensure(ctx, (size_t)(nn + 1) * 8);
+        uint32_t* flag = t.w_fl.as<uint32_t>();
         uint32_t* ex = flag + nn + 1;
-        hipLaunchKernelGGL(nonempty_flag_kernel, dim3(grid(nn)), dim3(TB), 0, s, cn.as<int32_t>(), nn, flag);
+        hipLaunchKernelGGL(nonempty_from_off_kernel, dim3(grid(nn)), dim3(TB), 0, s,
+                           (const uint32_t*)t.m2l_off.as<uint32_t>(), nn, flag);
         TFMM_LAUNCHED();
         t.scratch.ensure(ctx, scan_scratch_bytes(nn) + 256);
         uint32_t* tot = t.scratch2.as<uint32_t>();
@@ -319,38 +382,68 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         hipLaunchKernelGGL(compact_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)flag,
                            (const uint32_t*)ex, nn, t.m2l_targets.as<int32_t>());
         TFMM_LAUNCHED();
-        TFMM_HIP(hipStreamSynchronize(s));
     }
-    // near lists
+    // near lists: directed (self pairs once), by target
     {
-        DevBuf c, o, tg, sr, cn;
-        c.ensure(ctx, (size_t)std::max<int64_t>(n_near, 1) * 4);
-        o.ensure(ctx, (size_t)std::max<int64_t>(n_near, 1) * 4);
-        hipLaunchKernelGGL(near_count_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near,
-                           c.as<uint32_t>());
+        t.w_c.ensure(ctx, (size_t)std::max<int64_t>(n_near, 1) * 8);
+        uint32_t* c = t.w_c.as<uint32_t>();
+        uint32_t* o = c + std::max<int64_t>(n_near, 1);
+        hipLaunchKernelGGL(near_count_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near, c);
         TFMM_LAUNCHED();
         t.scratch.ensure(ctx, scan_scratch_bytes(n_near) + 256);
         uint32_t* tot = t.scratch2.as<uint32_t>();
-        exclusive_scan_u32(c.as<uint32_t>(), o.as<uint32_t>(), n_near, t.scratch.p, tot, s);
+        exclusive_scan_u32(c, o, n_near, t.scratch.p, tot, s);
         const int64_t ne = read_back(ctx, tot, s);
         tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
-        cn.ensure(ctx, (size_t)(nn + 1) * 4);
-        hipLaunchKernelGGL(fill_i32_kernel, dim3(grid(nn + 1)), dim3(TB), 0, s, cn.as<int32_t>(), nn + 1, 0);
-        TFMM_LAUNCHED();
         hipLaunchKernelGGL(near_entries_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near,
-                           (const uint32_t*)o.as<uint32_t>(), tg.as<uint32_t>(), sr.as<int32_t>(), cn.as<int32_t>());
+                           (const uint32_t*)o, tg.as<uint32_t>(), sr.as<int32_t>());
         TFMM_LAUNCHED();
-        build_csr(t, tg, sr, ne, cn, t.p2p_off, t.p2p_src, s);
-        // work count
-        t.scratch2.ensure(ctx, 256);
-        unsigned long long* acc = t.scratch2.as<unsigned long long>();
-        TFMM_HIP(hipMemsetAsync(acc, 0, 8, s));
+        build_csr(t, tg, sr, ne, t.p2p_off, t.p2p_src, s);
+        // directed near particle interactions (for throughput accounting)
+        unsigned long long* acc = reinterpret_cast<unsigned long long*>(t.scratch2.as<char>() + 128);
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(TB), 0, s, reinterpret_cast<int32_t*>(acc), 2, 0);
+        TFMM_LAUNCHED();
         const unsigned nb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(ne, TB)));
         hipLaunchKernelGGL(near_work_kernel, dim3(nb), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
-                           (const int32_t*)sr.as<int32_t>(), ne, t.nd_count.as<int32_t>(), acc);
+                           (const int32_t*)t.p2p_src.as<int32_t>(), ne, t.nd_count.as<int32_t>(), acc);
         TFMM_LAUNCHED();
         t.n_near_int = (int64_t)read_back(ctx, acc, s);
+
+        // work items over the sorted near entries (tg holds the sorted targets)
+        t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 16);
+        uint32_t* ec = t.w_c.as<uint32_t>();
+        uint32_t* P = ec + std::max<int64_t>(ne, 1);
+        uint32_t* fl = P + std::max<int64_t>(ne, 1);
+        uint32_t* ex = fl + std::max<int64_t>(ne, 1);
+        t.scratch.ensure(ctx, scan_scratch_bytes(ne) + 256);
+        hipLaunchKernelGGL(entry_sources_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const int32_t*)t.p2p_src.as<int32_t>(),
+                           ne, t.nd_count.as<int32_t>(), ec);
+        TFMM_LAUNCHED();
+        uint32_t* tot2 = t.scratch2.as<uint32_t>();
+        exclusive_scan_u32(ec, P, ne, t.scratch.p, tot2, s);
+        hipLaunchKernelGGL(item_flag_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
+                           (const uint32_t*)P, (const uint32_t*)t.p2p_off.as<uint32_t>(), ne, fl);
+        TFMM_LAUNCHED();
+        exclusive_scan_u32(fl, ex, ne, t.scratch.p, tot2, s);
+        const int64_t T = read_back(ctx, tot2, s);
+        t.n_items = T;
+        t.it_leaf.ensure(ctx, (size_t)std::max<int64_t>(T, 1) * 4);
+        t.it_q0.ensure(ctx, (size_t)std::max<int64_t>(T, 1) * 4);
+        t.it_q1.ensure(ctx, (size_t)std::max<int64_t>(T, 1) * 4);
+        t.it_pbase.ensure(ctx, (size_t)std::max<int64_t>(T, 1) * 4);
+        t.leaf_item0.ensure(ctx, (size_t)(nn + 1) * 4);
+        hipLaunchKernelGGL(item_build_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)fl, (const uint32_t*)ex,
+                           (const uint32_t*)tg.as<uint32_t>(), ne, t.it_leaf.as<int32_t>(), t.it_q0.as<uint32_t>());
+        TFMM_LAUNCHED();
+        // per-item partial sizes reuse the entry-count scratch
+        hipLaunchKernelGGL(item_finish_kernel, dim3(grid(T)), dim3(TB), 0, s, T, ne,
+                           (const uint32_t*)t.it_q0.as<uint32_t>(), (const int32_t*)t.it_leaf.as<int32_t>(),
+                           t.nd_count.as<int32_t>(), t.it_q1.as<uint32_t>(), ec, t.leaf_item0.as<int32_t>());
+        TFMM_LAUNCHED();
+        t.scratch.ensure(ctx, scan_scratch_bytes(T) + 256);
+        exclusive_scan_u32(ec, t.it_pbase.as<uint32_t>(), T, t.scratch.p, tot2, s);
+        t.n_partial = read_back(ctx, tot2, s);
     }
     t.walk_valid = true;
     t.walk_theta = theta;
