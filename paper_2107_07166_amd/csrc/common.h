@@ -99,6 +99,7 @@ struct Tree {
     DevBuf nd_r2bits;          // uint64 bits of max squared distance (atomicMax target)
     DevBuf nd_rmax;            // double
     DevBuf leaves;             // int32 node ids of the leaves
+    DevBuf rmax_items;         // int2 (node, chunk) work items of the r_max pass
 
     // walk and per-target interaction lists
     bool walk_valid = false;
@@ -114,7 +115,7 @@ struct Tree {
     // source count, each run by one wavefront into its own partial sums
     int64_t n_items = 0, n_partial = 0;
     DevBuf it_leaf, it_q0, it_q1, it_pbase;  // per item: leaf, entry range, partial offset
-    DevBuf leaf_item0;                        // per node: first item of a leaf (nodes + 1 entries)
+    DevBuf leaf_item0, leaf_nitems;           // per node: first item and item count of a leaf
     DevBuf partial;                           // FP64 partial near-field sums, 3 per (item, target)
 
     // expansions

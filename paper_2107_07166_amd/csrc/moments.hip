@@ -35,9 +35,14 @@ __global__ __launch_bounds__(TB) void p2m_kernel(int64_t n_leaves, const int32_t
 #pragma unroll
     for (int k = 0; k < NC; ++k) w[k] = 0.0;
     const int32_t s0 = first[node], s1 = s0 + count[node];
-    for (int32_t s = s0; s < s1; ++s) {
-        const double4 p = Xm[s];
-        E::p2m(p.w, z.x - p.x, z.y - p.y, z.z - p.z, w);
+    for (int32_t s = s0; s < s1; s += 4) {
+        double4 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (s + u < s1) p[u] = Xm[s + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (s + u < s1) E::p2m(p[u].w, z.x - p[u].x, z.y - p[u].y, z.z - p[u].z, w);
     }
     double* o64 = W64 + (int64_t)node * NCP;
     float* o32 = W32 + (int64_t)node * NCP;

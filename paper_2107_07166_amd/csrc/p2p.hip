@@ -73,7 +73,8 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ src,
                                                     const double4* __restrict__ Z,
                                                     const typename Vec4<T>::type* __restrict__ P, T eps2,
-                                                    double* __restrict__ partial) {
+                                                    const int32_t* __restrict__ leaf_nitems,
+                                                    double* __restrict__ partial, double* __restrict__ near) {
     using V4 = typename Vec4<T>::type;
     constexpr int SPL = CH / kWave;  // staged sources per lane per chunk
     __shared__ V4 stage[CH + kWave];
@@ -86,7 +87,8 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
     const int32_t fa = first[A], na = count[A];
     const double4 za = Z[A];
     const uint32_t q0 = it_q0[blockIdx.x], q1 = it_q1[blockIdx.x];
-    double* out = partial + 3 * (int64_t)it_pbase[blockIdx.x];
+    // a leaf served by one item writes the result, otherwise its own partial slot
+    double* out = (leaf_nitems[A] == 1) ? near + 3 * (int64_t)fa : partial + 3 * (int64_t)it_pbase[blockIdx.x];
     V4 pad;
     pad.x = far_away<T>();
     pad.y = far_away<T>();
@@ -192,29 +194,32 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
     }
 }
 
-// near[j] = sum over the work items of j's leaf, in item order.
-__global__ __launch_bounds__(256) void p2p_reduce_kernel(int64_t n, int64_t n_items,
-                                                         const int32_t* __restrict__ leaf_of,
-                                                         const int32_t* __restrict__ first,
-                                                         const int32_t* __restrict__ leaf_item0,
-                                                         const int32_t* __restrict__ it_leaf,
-                                                         const uint32_t* __restrict__ it_pbase,
-                                                         const double* __restrict__ partial,
-                                                         double* __restrict__ near) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const int32_t L = leaf_of[j];
-    const int64_t r = j - first[L];
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int64_t i = leaf_item0[L]; i < n_items && it_leaf[i] == L; ++i) {
-        const double* p = partial + 3 * ((int64_t)it_pbase[i] + r);
-        sx += p[0];
-        sy += p[1];
-        sz += p[2];
+// Leaves served by several items: one wavefront per such leaf (launched on its
+// first item) adds the items' partial sums in item order.
+__global__ __launch_bounds__(kWave) void p2p_reduce_kernel(const int32_t* __restrict__ it_leaf,
+                                                           const int32_t* __restrict__ leaf_item0,
+                                                           const int32_t* __restrict__ leaf_nitems,
+                                                           const int32_t* __restrict__ first,
+                                                           const int32_t* __restrict__ count,
+                                                           const uint32_t* __restrict__ it_pbase,
+                                                           const double* __restrict__ partial,
+                                                           double* __restrict__ near) {
+    const int32_t L = it_leaf[blockIdx.x];
+    const int32_t ni = leaf_nitems[L];
+    if (ni == 1 || leaf_item0[L] != (int32_t)blockIdx.x) return;
+    const int32_t fa = first[L], na = count[L];
+    for (int32_t r = threadIdx.x; r < na; r += kWave) {
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int32_t i = 0; i < ni; ++i) {
+            const double* p = partial + 3 * ((int64_t)it_pbase[blockIdx.x + i] + r);
+            sx += p[0];
+            sy += p[1];
+            sz += p[2];
+        }
+        near[3 * (int64_t)(fa + r)] = sx;
+        near[3 * (int64_t)(fa + r) + 1] = sy;
+        near[3 * (int64_t)(fa + r) + 2] = sz;
     }
-    near[3 * j] = sx;
-    near[3 * j + 1] = sy;
-    near[3 * j + 2] = sz;
 }
 
 template <typename T>
@@ -227,17 +232,18 @@ void launch(Tree& t, double eps2, hipStream_t s) {
         hipLaunchKernelGGL((p2p_kernel<T, false>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
                            t.it_q0.as<uint32_t>(), t.it_q1.as<uint32_t>(), t.it_pbase.as<uint32_t>(),
                            t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(), t.p2p_src.as<int32_t>(),
-                           t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.partial.as<double>());
+                           t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.leaf_nitems.as<int32_t>(),
+                           t.partial.as<double>(), t.near3.as<double>());
     else
         hipLaunchKernelGGL((p2p_kernel<T, true>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
                            t.it_q0.as<uint32_t>(), t.it_q1.as<uint32_t>(), t.it_pbase.as<uint32_t>(),
                            t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(), t.p2p_src.as<int32_t>(),
-                           t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.partial.as<double>());
+                           t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.leaf_nitems.as<int32_t>(),
+                           t.partial.as<double>(), t.near3.as<double>());
     TFMM_LAUNCHED();
-    hipLaunchKernelGGL(p2p_reduce_kernel, dim3((unsigned)cdiv(t.n, 256)), dim3(256), 0, s, t.n, ni,
-                       t.leaf_of.as<int32_t>(), t.nd_first.as<int32_t>(), t.leaf_item0.as<int32_t>(),
-                       t.it_leaf.as<int32_t>(), t.it_pbase.as<uint32_t>(), t.partial.as<double>(),
-                       t.near3.as<double>());
+    hipLaunchKernelGGL(p2p_reduce_kernel, g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(), t.leaf_item0.as<int32_t>(),
+                       t.leaf_nitems.as<int32_t>(), t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(),
+                       t.it_pbase.as<uint32_t>(), t.partial.as<double>(), t.near3.as<double>());
     TFMM_LAUNCHED();
 }
 

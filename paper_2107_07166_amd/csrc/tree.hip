@@ -233,13 +233,22 @@ __global__ __launch_bounds__(TB) void geometry_level_kernel(const int32_t* __res
     double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     const int32_t nc = nchild[i];
     if (nc == 0) {
+        // loads issued eight at a time, sums kept strictly left to right
         const int32_t s0 = first[i], s1 = s0 + count[i];
-        for (int32_t s = s0; s < s1; ++s) {
-            const double4 p = Xm[s];
-            M = M + p.w;
-            sx = sx + p.w * p.x;
-            sy = sy + p.w * p.y;
-            sz = sz + p.w * p.z;
+        for (int32_t s = s0; s < s1; s += 8) {
+            double4 p[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (s + u < s1) p[u] = Xm[s + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (s + u < s1) {
+                    M = M + p[u].w;
+                    sx = sx + p[u].w * p[u].x;
+                    sy = sy + p[u].w * p[u].y;
+                    sz = sz + p[u].w * p[u].z;
+                }
+            }
         }
     } else {
         const int32_t c0 = child_first[i];
@@ -260,48 +269,52 @@ __global__ __launch_bounds__(TB) void fill_u64_kernel(uint64_t* __restrict__ p, 
     if (i < n) p[i] = v;
 }
 
-// Exact r_max: every particle offers its squared distance to each ancestor's
-// centre of mass; the maximum is order independent (atomicMax on the bits of
-// non-negative doubles), so the result is deterministic.  Levels are walked
-// from the deepest up; at each level the lanes of a wave (consecutive sorted
-// particles, so a node's lanes are contiguous) take a segmented maximum and
-// only the last lane of each segment issues the atomic.
-__global__ __launch_bounds__(TB) void rmax_kernel(const double4* __restrict__ Xm,
-                                                  const int32_t* __restrict__ leaf_of,
-                                                  const int32_t* __restrict__ level,
-                                                  const int32_t* __restrict__ parent,
-                                                  const double4* __restrict__ Z, int64_t n, int max_level,
-                                                  unsigned long long* __restrict__ r2bits) {
-    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
-    const bool valid = j < n;
-    double4 x = make_double4(0, 0, 0, 0);
-    int32_t cur = -1;
-    if (valid) {
-        x = Xm[j];
-        cur = leaf_of[j];
+// Exact r_max: the maximum squared distance of a node's particles from its
+// centre of mass.  Work items are (node, chunk of at most RCH particles) so the
+// root does not serialise on one wavefront; each item reduces its chunk across
+// the wave and issues one atomicMax on the bits of the (non-negative) double.
+// A maximum does not depend on the order of the atomics: deterministic.
+constexpr int RCH = 4096;
+
+__global__ __launch_bounds__(TB) void rmax_chunks_kernel(const int32_t* __restrict__ count, int64_t nn,
+                                                         uint32_t* __restrict__ c) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < nn) c[i] = (uint32_t)((count[i] + RCH - 1) / RCH);
+}
+
+__global__ __launch_bounds__(TB) void rmax_items_kernel(int64_t nn, const uint32_t* __restrict__ c,
+                                                        const uint32_t* __restrict__ base,
+                                                        int2* __restrict__ items) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= nn) return;
+    for (uint32_t k = 0; k < c[i]; ++k) items[base[i] + k] = make_int2((int32_t)i, (int32_t)k);
+}
+
+__global__ __launch_bounds__(kWave) void rmax_kernel(const uint32_t* __restrict__ n_items,
+                                                     const int2* __restrict__ items,
+                                                     const int32_t* __restrict__ first,
+                                                     const int32_t* __restrict__ count,
+                                                     const double4* __restrict__ Xm, const double4* __restrict__ Z,
+                                                     unsigned long long* __restrict__ r2bits) {
+    if (blockIdx.x >= *n_items) return;
+    const int2 it = items[blockIdx.x];
+    const int32_t s0 = first[it.x] + it.y * RCH;
+    const int32_t e = first[it.x] + count[it.x];
+    const int32_t s1 = (s0 + RCH < e) ? s0 + RCH : e;
+    const double4 z = Z[it.x];
+    double m = 0.0;
+    for (int32_t s = s0 + (int32_t)threadIdx.x; s < s1; s += kWave) {
+        const double4 x = Xm[s];
+        const double dx = x.x - z.x, dy = x.y - z.y, dz = x.z - z.z;
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        m = d2 > m ? d2 : m;
     }
-    for (int L = max_level; L >= 0; --L) {
-        const bool act = cur >= 0 && level[cur] == L;
-        double d2 = 0.0;
-        if (act) {
-            const double4 z = Z[cur];
-            const double dx = x.x - z.x, dy = x.y - z.y, dz = x.z - z.z;
-            d2 = (dx * dx + dy * dy) + dz * dz;
-        }
-        const int lane = threadIdx.x & (kWave - 1);
-        const int32_t key = act ? cur : -1;
-        double m = d2;
 #pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const double u = __shfl_up(m, o, kWave);
-            const int32_t ku = __shfl_up(key, o, kWave);
-            if (lane >= o && ku == key) m = u > m ? u : m;
-        }
-        const int32_t knext = __shfl_down(key, 1, kWave);
-        if (act && (lane == kWave - 1 || knext != key))
-            atomicMax(&r2bits[cur], (unsigned long long)__double_as_longlong(m));
-        if (act) cur = parent[cur];
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double u = __shfl_xor(m, o, kWave);
+        m = u > m ? u : m;
     }
+    if (threadIdx.x == 0) atomicMax(&r2bits[it.x], (unsigned long long)__double_as_longlong(m));
 }
 
 __global__ __launch_bounds__(TB) void rmax_final_kernel(const unsigned long long* __restrict__ r2bits,
@@ -489,10 +502,24 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     hipLaunchKernelGGL(fill_u64_kernel, dim3(grid(nn)), dim3(TB), 0, s, t.nd_r2bits.as<uint64_t>(), nn,
                        (uint64_t)0);
     TFMM_LAUNCHED();
-    hipLaunchKernelGGL(rmax_kernel, dim3(grid(n)), dim3(TB), 0, s, t.Xm.as<double4>(), t.leaf_of.as<int32_t>(),
-                       nd.level, nd.parent, t.nd_Z.as<double4>(), n, t.max_level,
-                       t.nd_r2bits.as<unsigned long long>());
-    TFMM_LAUNCHED();
+    {
+        // items (node, chunk); the launch covers an upper bound and reads the count on the device
+        const int64_t ub = nn + (int64_t)n * (t.max_level + 1) / RCH + 1;
+        t.flags.ensure(ctx, (size_t)std::max<int64_t>(n, nn) * 4 * 2);
+        uint32_t* c = t.flags.as<uint32_t>();
+        uint32_t* base = c + std::max<int64_t>(n, nn);
+        t.rmax_items.ensure(ctx, (size_t)ub * 8);
+        hipLaunchKernelGGL(rmax_chunks_kernel, dim3(grid(nn)), dim3(TB), 0, s, nd.count, nn, c);
+        TFMM_LAUNCHED();
+        exclusive_scan_u32(c, base, nn, t.scratch.p, total, s);
+        hipLaunchKernelGGL(rmax_items_kernel, dim3(grid(nn)), dim3(TB), 0, s, nn, (const uint32_t*)c,
+                           (const uint32_t*)base, t.rmax_items.as<int2>());
+        TFMM_LAUNCHED();
+        hipLaunchKernelGGL(rmax_kernel, dim3((unsigned)ub), dim3(kWave), 0, s, (const uint32_t*)total,
+                           (const int2*)t.rmax_items.as<int2>(), nd.first, nd.count, t.Xm.as<double4>(),
+                           t.nd_Z.as<double4>(), t.nd_r2bits.as<unsigned long long>());
+        TFMM_LAUNCHED();
+    }
     hipLaunchKernelGGL(rmax_final_kernel, dim3(grid(nn)), dim3(TB), 0, s, t.nd_r2bits.as<unsigned long long>(),
                        nn, t.nd_rmax.as<double>());
     TFMM_LAUNCHED();

@@ -251,8 +251,20 @@ __global__ __launch_bounds__(TB) void item_finish_kernel(int64_t T, int64_t ne, 
     if (i >= T) return;
     it_q1[i] = (i + 1 < T) ? it_q0[i + 1] : (uint32_t)ne;
     const int32_t L = it_leaf[i];
-    pc[i] = (uint32_t)count[L];
-    if (i == 0 || it_leaf[i - 1] != L) leaf_item0[L] = (int32_t)i;
+    const bool first_of_leaf = (i == 0 || it_leaf[i - 1] != L);
+    const bool last_of_leaf = (i + 1 == T || it_leaf[i + 1] != L);
+    // a leaf with a single item writes its result directly: no partial space
+    pc[i] = (first_of_leaf && last_of_leaf) ? 0u : (uint32_t)count[L];
+    if (first_of_leaf) leaf_item0[L] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(TB) void item_count_kernel(int64_t T, const int32_t* __restrict__ it_leaf,
+                                                        const int32_t* __restrict__ leaf_item0,
+                                                        int32_t* __restrict__ leaf_nitems) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= T) return;
+    const int32_t L = it_leaf[i];
+    if (i + 1 == T || it_leaf[i + 1] != L) leaf_nitems[L] = (int32_t)(i + 1 - leaf_item0[L]);
 }
 
 unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, TB); }
@@ -440,6 +452,10 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         hipLaunchKernelGGL(item_finish_kernel, dim3(grid(T)), dim3(TB), 0, s, T, ne,
                            (const uint32_t*)t.it_q0.as<uint32_t>(), (const int32_t*)t.it_leaf.as<int32_t>(),
                            t.nd_count.as<int32_t>(), t.it_q1.as<uint32_t>(), ec, t.leaf_item0.as<int32_t>());
+        TFMM_LAUNCHED();
+        t.leaf_nitems.ensure(ctx, (size_t)(nn + 1) * 4);
+        hipLaunchKernelGGL(item_count_kernel, dim3(grid(T)), dim3(TB), 0, s, T, (const int32_t*)t.it_leaf.as<int32_t>(),
+                           (const int32_t*)t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>());
         TFMM_LAUNCHED();
         t.scratch.ensure(ctx, scan_scratch_bytes(T) + 256);
         exclusive_scan_u32(ec, t.it_pbase.as<uint32_t>(), T, t.scratch.p, tot2, s);
