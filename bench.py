@@ -31,6 +31,21 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_FP32_NOPK_TFLOPS = 78.6  # the same without packed FP32 (256 CU x 64 FMA/clk x 2 x 2.4 GHz)
 P2P_FLOP_PER_PAIR = 20        # per directed particle interaction (convention)
 
+# HBM bytes per P2P launch at this workload, from rocprofv3 FETCH_SIZE (x2, the
+# factor a plain copy of known size reads) and WRITE_SIZE (x1); see
+# profiles/p2p_plummer1m_counters.md.  Valid only for the kernel source the
+# counters were taken with (first 16 hex digits of its sha256).
+P2P_TRAFFIC_BYTES = (2 * 256200 + 32009) * 1024
+P2P_TRAFFIC_SOURCE_SHA = "6c53744775858ce3"
+
+
+def _p2p_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2107_07166_amd", "csrc", "p2p.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return P2P_TRAFFIC_BYTES if sha == P2P_TRAFFIC_SOURCE_SHA else None
+
 
 def _erms(f, ref):
     return float(np.sqrt(np.mean(((f - ref) ** 2).sum(1) / (ref ** 2).sum(1))))
@@ -164,7 +179,7 @@ def main():
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "peak_without_packed_fp32": PEAK_FP32_NOPK_TFLOPS,
                      "flop_per_unit": P2P_FLOP_PER_PAIR, "units_per_launch": n_int,
-                     "avg_launch_ms": p2p_ms, "traffic": None},
+                     "avg_launch_ms": p2p_ms, "traffic": _p2p_traffic()},
         "standard_variant": {"value": w.n / g["t_std"], "ms_per_step": g["t_std"] * 1e3},
         "conserving_overhead": g["t_cons"] / g["t_std"] - 1.0,
         "fp64_path": {"value": w.n / g["t_fp64"], "ms_per_step": g["t_fp64"] * 1e3},

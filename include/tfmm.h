@@ -98,10 +98,11 @@ size_t tfmm_ctx_bytes_in_use(const tfmm_ctx *ctx);
 int tfmm_build_tree(tfmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
                     int n_leaf, void *stream, tfmm_tree **out);
 
-/* Rebuild an existing tree in place for new positions (same n, same masses
- * pointer semantics as tfmm_build_tree); reuses its device buffers.
- * Synchronising.  Errors: EINVAL, ENOMEM, EDEVICE. */
-int tfmm_tree_rebuild(tfmm_tree *tree, const double *pos, const double *mass, void *stream);
+/* Rebuild an existing tree in place for a particle set of n particles (n may
+ * differ from the previous build; pos and mass as in tfmm_build_tree).  Device
+ * buffers are grow-only, so a tree reused for sets of similar size allocates
+ * nothing.  Synchronising.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int tfmm_tree_rebuild(tfmm_tree *tree, int64_t n, const double *pos, const double *mass, void *stream);
 
 /* Run the mutual dual-tree walk for `theta` (Eq. mac_criterion) and build the
  * per-target interaction lists.  tfmm_evaluate_forces calls it when theta
@@ -122,6 +123,20 @@ int tfmm_evaluate_forces(tfmm_tree *tree, const tfmm_params *params, double *for
  * Synchronising.  Errors: as tfmm_build_tree and tfmm_evaluate_forces. */
 int tfmm_evaluate_forces_oneshot(tfmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
                                  int n_leaf, const tfmm_params *params, double *force, void *stream);
+
+/* nsteps kick-drift-kick leapfrog steps on resident state (gravity-only
+ * analogue of the paper's star evolution, Sec. 4): v += (F/m) dt/2;
+ * x += v dt; rebuild the tree and walk it; F = force(x); v += (F/m) dt/2.
+ * pos, vel, force: device n x 3 FP64 (updated in place); mass: device n FP64,
+ * the masses the tree was built with.  force must hold the forces at pos on
+ * entry when force_valid != 0, otherwise they are evaluated first; on return
+ * it holds the forces at the final positions.  The tree must have been built
+ * for n particles.  Synchronising (each rebuild reads sizes).
+ * Errors: EINVAL (bad pointers, nsteps < 0, non-finite dt, bad params),
+ * ENOMEM, EDEVICE. */
+int tfmm_leapfrog(tfmm_tree *tree, const tfmm_params *params, double *pos, double *vel,
+                  const double *mass, double *force, double dt, int nsteps, int force_valid,
+                  void *stream);
 
 /* Momentum diagnostics in FP64 (Eqs. netforce, total_torque summed over all
  * particles, about the system centre of mass).  pos, mass, force: device, as

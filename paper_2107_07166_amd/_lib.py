@@ -38,10 +38,11 @@ SIGNATURES = {
     "tfmm_last_error": (ctypes.c_char_p, [_vp]),
     "tfmm_ctx_bytes_in_use": (_sz, [_vp]),
     "tfmm_build_tree": (_int, [_vp, _i64, _vp, _vp, _int, _vp, ctypes.POINTER(_vp)]),
-    "tfmm_tree_rebuild": (_int, [_vp, _vp, _vp, _vp]),
+    "tfmm_tree_rebuild": (_int, [_vp, _i64, _vp, _vp, _vp]),
     "tfmm_tree_walk": (_int, [_vp, _d, _vp]),
     "tfmm_evaluate_forces": (_int, [_vp, ctypes.POINTER(Params), _vp, _vp, _vp]),
     "tfmm_evaluate_forces_oneshot": (_int, [_vp, _i64, _vp, _vp, _int, ctypes.POINTER(Params), _vp, _vp]),
+    "tfmm_leapfrog": (_int, [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _d, _int, _int, _vp]),
     "tfmm_momentum_diagnostics": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tfmm_tree_info": (_int, [_vp, _vp]),
     "tfmm_tree_export": (_int, [_vp] + [_vp] * 12),

@@ -106,10 +106,13 @@ class Tree:
         ctx._trees.add(self)
 
     def rebuild(self, pos: torch.Tensor, mass: torch.Tensor) -> None:
-        _check_vec(pos, "pos", (self.n, 3))
-        _check_vec(mass, "mass", (self.n,))
-        self.ctx.check(self.ctx.lib.tfmm_tree_rebuild(self.handle, pos.data_ptr(), mass.data_ptr(),
+        """Rebuild for new positions; the particle count may change (buffers are grow-only)."""
+        n = int(mass.shape[0])
+        _check_vec(pos, "pos", (n, 3))
+        _check_vec(mass, "mass", (n,))
+        self.ctx.check(self.ctx.lib.tfmm_tree_rebuild(self.handle, n, pos.data_ptr(), mass.data_ptr(),
                                                       _stream_handle(pos.device)))
+        self.n = n
 
     def walk(self, theta: float) -> None:
         self.ctx.check(self.ctx.lib.tfmm_tree_walk(self.handle, float(theta), _stream_handle(self.device)))

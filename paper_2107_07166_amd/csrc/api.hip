@@ -206,11 +206,13 @@ int tfmm_build_tree(tfmm_ctx* ctx, int64_t n, const double* pos, const double* m
     return TFMM_OK;
 }
 
-int tfmm_tree_rebuild(tfmm_tree* tree, const double* pos, const double* mass, void* stream) {
+int tfmm_tree_rebuild(tfmm_tree* tree, int64_t n, const double* pos, const double* mass, void* stream) {
     if (!tree) return TFMM_EINVAL;
     return guarded(tree->ctx, [&] {
+        if (n < 1 || n > (int64_t)INT32_MAX / 2) fail(TFMM_EINVAL, "n must be in 1..2^30");
         if (!pos || !mass) fail(TFMM_EINVAL, "pos and mass must be device pointers");
         set_device(tree->ctx);
+        tree->n = n;
         build_tree(*tree, pos, mass, (hipStream_t)stream);
     });
 }
@@ -250,6 +252,30 @@ int tfmm_evaluate_forces_oneshot(tfmm_ctx* ctx, int64_t n, const double* pos, co
     tfmm_tree_destroy(t);
     if (rc != TFMM_OK) ctx->err = keep;
     return rc;
+}
+
+int tfmm_leapfrog(tfmm_tree* tree, const tfmm_params* params, double* pos, double* vel, const double* mass,
+                  double* force, double dt, int nsteps, int force_valid, void* stream) {
+    if (!tree) return TFMM_EINVAL;
+    return guarded(tree->ctx, [&] {
+        check_params(params);
+        if (!pos || !vel || !mass || !force) fail(TFMM_EINVAL, "pos, vel, mass and force must be device pointers");
+        if (nsteps < 0 || !std::isfinite(dt)) fail(TFMM_EINVAL, "nsteps must be >= 0 and dt finite");
+        set_device(tree->ctx);
+        Tree& t = *tree;
+        const hipStream_t s = (hipStream_t)stream;
+        if (!force_valid) {
+            build_tree(t, pos, mass, s);
+            evaluate(t, params, force, s);
+        }
+        for (int k = 0; k < nsteps; ++k) {
+            run_kick(t.n, vel, force, mass, 0.5 * dt, s);
+            run_drift(t.n, pos, vel, dt, s);
+            build_tree(t, pos, mass, s);
+            evaluate(t, params, force, s);
+            run_kick(t.n, vel, force, mass, 0.5 * dt, s);
+        }
+    });
 }
 
 int tfmm_momentum_diagnostics(tfmm_ctx* ctx, int64_t n, const double* pos, const double* vel, const double* mass,

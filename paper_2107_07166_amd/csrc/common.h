@@ -167,6 +167,8 @@ void run_l2l(Tree& t, int p, int variant, hipStream_t s);
 void run_l2p(Tree& t, int p, int variant, double G, double* force, hipStream_t s);
 void run_diagnostics(int64_t n, const double* pos, const double* vel, const double* mass,
                      const double* force, double* out_host, Ctx* ctx, hipStream_t s);
+void run_kick(int64_t n, double* vel, const double* force, const double* mass, double h, hipStream_t s);
+void run_drift(int64_t n, double* pos, const double* vel, double dt, hipStream_t s);
 
 // number of FP64 local values per node for a variant
 inline int n_local(int p, int variant) {

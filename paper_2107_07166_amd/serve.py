@@ -1,0 +1,300 @@
+"""Continuous-batching server for gravity solves and resident leapfrog sessions.
+
+Requests arrive over time (a Poisson trace); each asks for the forces on one
+particle set (N, p, theta, variant) or for the next leapfrog step of one of
+the persistent sessions.  The server keeps `slots` workers busy: as soon as a
+worker is free and the request at the head of the queue fits in the device
+memory budget (tfmm_footprint_bytes), it is admitted, so requests that arrive
+while others run start as slots and memory free up.  Every worker owns a
+libtfmm context, its own HIP stream (default priority) and one reusable tree
+(device buffers are grow-only), so the work of several requests overlaps on
+the GPU.  Sessions keep particles and tree resident in HBM between steps and
+are re-queued after every step.
+
+Every solve is deterministic, so its result is the same alone and in a mix.
+Latency is arrival -> completion on the device.
+"""
+
+from __future__ import annotations
+
+import collections
+import math
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import api, generators
+from .session import Session, footprint_bytes as session_footprint
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                # seconds after the start of the trace
+    kind: str = "solve"           # "solve" or "step"
+    n: int = 0
+    gen: str = "plummer"
+    seed: int = 0
+    p: int = 4
+    theta: float = 0.5
+    eps: float = 1e-3
+    variant: str = "conserving"
+    session: int = -1
+    dt: float = 1e-3
+
+
+@dataclass
+class Record:
+    rid: int
+    kind: str
+    n: int
+    p: int
+    theta: float
+    variant: str
+    arrival: float
+    admitted: float = math.nan
+    done: float = math.nan
+    footprint: int = 0
+    worker: int = -1
+    sample: Optional[np.ndarray] = None  # forces at the first `sample_k` particles
+    full: Optional[np.ndarray] = None    # all forces (only when requested)
+    error: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def make_trace(n_requests: int = 512, rate: float = 100.0, seed: int = generators.SEED_BASE + 4,
+               n_min: float = 1e3, n_max: float = 5e5, p_choices=(2, 4, 6), theta_choices=(0.4, 0.6, 0.8),
+               kinds=("ball", "plummer", "disk"), variants=("standard", "conserving")) -> List[Request]:
+    """Poisson arrivals at `rate`/s; N log-uniform in [n_min, n_max]; generator,
+    p, theta and variant uniform over the given choices."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    out = []
+    for i in range(n_requests):
+        n = int(round(10 ** rng.uniform(math.log10(n_min), math.log10(n_max))))
+        out.append(Request(rid=i, arrival=float(t[i]), kind="solve", n=n, gen=str(rng.choice(kinds)),
+                           seed=int(rng.integers(1 << 30)), p=int(rng.choice(p_choices)),
+                           theta=float(rng.choice(theta_choices)), variant=str(rng.choice(variants))))
+    return out
+
+
+def make_inputs(req: Request):
+    """Pinned host copies of a request's particle set (the client's payload)."""
+    pos, mass = generators.generate(req.gen, req.n, req.seed)
+    hp = torch.empty((req.n, 3), dtype=torch.float64, pin_memory=True)
+    hm = torch.empty((req.n,), dtype=torch.float64, pin_memory=True)
+    hp.copy_(torch.from_numpy(pos))
+    hm.copy_(torch.from_numpy(mass))
+    return hp, hm
+
+
+class _Worker:
+    def __init__(self, wid: int, device: int, n_leaf: int):
+        self.wid = wid
+        self.ctx = api.Context(device)
+        self.stream = torch.cuda.Stream(device=device)
+        self.dev = torch.device("cuda", device)
+        self.n_leaf = n_leaf
+        self.tree: Optional[api.Tree] = None
+        self.pos = None
+        self.mass = None
+        self.force = None
+
+    def _buffers(self, n: int):
+        if self.pos is None or self.pos.shape[0] < n:
+            cap = max(n, 1024)
+            self.pos = torch.empty((cap, 3), dtype=torch.float64, device=self.dev)
+            self.mass = torch.empty((cap,), dtype=torch.float64, device=self.dev)
+            self.force = torch.empty((cap, 3), dtype=torch.float64, device=self.dev)
+        return self.pos[:n], self.mass[:n], self.force[:n]
+
+    def solve(self, req: Request, hp, hm, precision: str):
+        with torch.cuda.stream(self.stream):
+            pos, mass, force = self._buffers(req.n)
+            pos.copy_(hp, non_blocking=True)
+            mass.copy_(hm, non_blocking=True)
+            if self.tree is None:
+                self.tree = api.Tree(self.ctx, pos, mass, n_leaf=self.n_leaf)
+            else:
+                self.tree.rebuild(pos, mass)
+            self.tree.evaluate(p=req.p, theta=req.theta, eps=req.eps, variant=req.variant, precision=precision,
+                               out=force)
+            self.stream.synchronize()
+        return force
+
+    def close(self):
+        if self.tree is not None:
+            self.tree.close()
+        self.ctx.close()
+
+
+class Server:
+    def __init__(self, slots: int = 8, precision: str = "mixed32", budget_bytes: int = 64 << 30,
+                 n_leaf: int = 32, device: int = 0, sample_k: int = 16, keep_full: bool = False):
+        self.slots = int(slots)
+        self.precision = precision
+        self.budget = int(budget_bytes)
+        self.n_leaf = int(n_leaf)
+        self.device = int(device)
+        self.sample_k = int(sample_k)
+        self.keep_full = bool(keep_full)
+
+    def footprint(self, req: Request) -> int:
+        return api.footprint_bytes(req.n, req.p, self.n_leaf, self.precision) + 48 * req.n
+
+    def run(self, requests: List[Request], sessions: Optional[List[Session]] = None,
+            session_dt: float = 1e-3, inputs=None) -> List[Record]:
+        """Serve `requests` (sorted by arrival) and keep `sessions` stepping until
+        the last request is done.  Returns one record per solve and per session step."""
+        requests = sorted(requests, key=lambda r: r.arrival)
+        inputs = inputs if inputs is not None else {r.rid: make_inputs(r) for r in requests}
+        sessions = sessions or []
+        workers = [_Worker(i, self.device, self.n_leaf) for i in range(self.slots)]
+        lock = threading.Condition()
+        pending = collections.deque()
+        records: List[Record] = []
+        state = {"used": sum(session_footprint(s.n, s.params["p"], s.n_leaf, s.params["precision"])
+                             for s in sessions),
+                 "free_workers": list(range(self.slots)), "solves_left": len(requests), "next_step_id": 10**9,
+                 "stop": False, "error": None}
+        if state["used"] > self.budget:
+            raise MemoryError("the resident sessions alone exceed the memory budget")
+        t0 = time.perf_counter()
+        for k, s in enumerate(sessions):  # every session starts with one queued step
+            pending.append(Request(rid=state["next_step_id"] + k, arrival=0.0, kind="step", n=s.n, session=k,
+                                   p=s.params["p"], theta=s.params["theta"], variant=s.params["variant"],
+                                   dt=session_dt))
+        state["next_step_id"] += len(sessions)
+        busy_sessions = set()
+
+        def execute(wid: int, req: Request, admitted: float, fp: int):
+            rec = Record(req.rid, req.kind, req.n, req.p, req.theta, req.variant, req.arrival, admitted,
+                         footprint=fp, worker=wid)
+            try:
+                if req.kind == "solve":
+                    hp, hm = inputs[req.rid]
+                    f = workers[wid].solve(req, hp, hm, self.precision)
+                    rec.sample = f[: self.sample_k].cpu().numpy()
+                    if self.keep_full:
+                        rec.full = f.cpu().numpy()
+                else:
+                    s = sessions[req.session]
+                    s.step(req.dt, 1)
+                    rec.sample = s.force[: self.sample_k].cpu().numpy()
+            except Exception as e:  # recorded, the server keeps going
+                rec.error = repr(e)
+            rec.done = time.perf_counter() - t0
+            with lock:
+                records.append(rec)
+                if req.kind == "solve":
+                    state["used"] -= fp
+                    state["solves_left"] -= 1
+                else:
+                    busy_sessions.discard(req.session)
+                    if state["solves_left"] > 0:
+                        pending.append(Request(rid=state["next_step_id"], arrival=rec.done, kind="step",
+                                               n=req.n, session=req.session, p=req.p, theta=req.theta,
+                                               variant=req.variant, dt=req.dt))
+                        state["next_step_id"] += 1
+                state["free_workers"].append(wid)
+                lock.notify_all()
+
+        threads = []
+        nxt = 0
+        with lock:
+            while True:
+                now = time.perf_counter() - t0
+                while nxt < len(requests) and requests[nxt].arrival <= now:
+                    pending.append(requests[nxt])
+                    nxt += 1
+                # admit from the head while a worker is free and memory allows (FIFO)
+                while pending and state["free_workers"]:
+                    req = pending[0]
+                    if req.kind == "step" and req.session in busy_sessions:
+                        pending.rotate(-1)
+                        break
+                    fp = self.footprint(req) if req.kind == "solve" else 0
+                    if fp > self.budget:
+                        pending.popleft()
+                        records.append(Record(req.rid, req.kind, req.n, req.p, req.theta, req.variant, req.arrival,
+                                              error="footprint exceeds the budget"))
+                        state["solves_left"] -= 1
+                        continue
+                    if state["used"] + fp > self.budget:
+                        break
+                    pending.popleft()
+                    state["used"] += fp
+                    wid = state["free_workers"].pop()
+                    if req.kind == "step":
+                        busy_sessions.add(req.session)
+                    th = threading.Thread(target=execute, args=(wid, req, now, fp), daemon=True)
+                    threads.append(th)
+                    th.start()
+                if state["solves_left"] <= 0 and len(state["free_workers"]) == self.slots:
+                    break
+                wait = None
+                if nxt < len(requests):
+                    wait = max(0.0, requests[nxt].arrival - (time.perf_counter() - t0))
+                lock.wait(timeout=wait if wait is not None else 0.05)
+        for th in threads:
+            th.join()
+        for w in workers:
+            w.close()
+        return sorted(records, key=lambda r: (r.kind, r.rid))
+
+
+def make_sessions(count: int = 16, seed: int = generators.SEED_BASE + 4, n_min: float = 1e3, n_max: float = 5e5,
+                  precision: str = "mixed32", n_leaf: int = 32, device: int = 0,
+                  p_choices=(2, 4, 6), theta_choices=(0.4, 0.6, 0.8), kinds=("ball", "plummer", "disk"),
+                  variants=("standard", "conserving")) -> List[Session]:
+    """Persistent leapfrog sessions drawn like the requests; each has its own
+    context and stream so that different workers can step them concurrently."""
+    rng = np.random.default_rng(seed + 7919)
+    out = []
+    dev = torch.device("cuda", device)
+    for _ in range(count):
+        n = int(round(10 ** rng.uniform(math.log10(n_min), math.log10(n_max))))
+        kind = str(rng.choice(kinds))
+        w = generators.Workload(kind, int(rng.integers(1 << 20)), kind, n, 1, 0.5)
+        pos, mass, vel = w.make(velocities=True)
+        ctx = api.Context(device)
+        s = Session(ctx, torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev),
+                    torch.from_numpy(mass).to(dev), p=int(rng.choice(p_choices)),
+                    theta=float(rng.choice(theta_choices)), eps=1e-3, variant=str(rng.choice(variants)),
+                    precision=precision, n_leaf=n_leaf, stream=torch.cuda.Stream(device=device))
+        s._owned_ctx = ctx
+        out.append(s)
+    return out
+
+
+def close_sessions(sessions: List[Session]) -> None:
+    for s in sessions:
+        s.close()
+        ctx = getattr(s, "_owned_ctx", None)
+        if ctx is not None:
+            ctx.close()
+
+
+def summarize(records: List[Record]) -> dict:
+    solves = [r for r in records if r.kind == "solve" and not r.error]
+    steps = [r for r in records if r.kind == "step" and not r.error]
+    out = {"solves": len(solves), "session_steps": len(steps),
+           "errors": sum(1 for r in records if r.error)}
+    if solves:
+        lat = np.array([r.latency for r in solves])
+        t_first = min(r.arrival for r in solves)
+        t_last = max(r.done for r in solves)
+        out.update(solves_per_s=len(solves) / (t_last - t_first), p50_ms=float(np.percentile(lat, 50) * 1e3),
+                   p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
+                   particles_per_s=float(sum(r.n for r in solves) / (t_last - t_first)))
+    if steps:
+        lat = np.array([r.done - r.admitted for r in steps])
+        out.update(step_p50_ms=float(np.percentile(lat, 50) * 1e3), step_p99_ms=float(np.percentile(lat, 99) * 1e3))
+    return out

@@ -1,0 +1,143 @@
+"""Measurement studies beyond the headline benchmark (one JSON line each).
+
+    python -m paper_2107_07166_amd.studies binary [--n N] [--steps 200] [--dt 1e-3]
+        Two n=1 polytropes on a circular orbit (p=4, theta=0.7, mixed): the
+        angular momentum drift of the standard and the conserving variant over
+        leapfrog steps, and the time per step.
+    python -m paper_2107_07166_amd.studies disk [--n N]
+        Exponential disk (p=6, theta=0.8): time of both variants (the cost of
+        realignment), net torque, mixed vs FP64 force difference.
+    python -m paper_2107_07166_amd.studies serve [--requests 512] [--sessions 16]
+        Poisson trace of solves with N log-uniform in [1e3, 5e5], p in {2,4,6},
+        theta in {0.4,0.6,0.8}, plus persistent leapfrog sessions: FP32 mixed
+        with concurrent slots against FP64 one solve at a time, same trace;
+        solves/s and p50/p99 latency, and the per-request mixed-vs-FP64 error.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import api, generators
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def study_binary(n: int, steps: int, dt: float, n_leaf: int) -> dict:
+    from .session import Session
+    w = generators.WORKLOADS["binary4m"]
+    pos, mass, vel = w.make(n=n, velocities=True)
+    out = {"study": "binary", "n": n, "p": w.p, "theta": w.theta, "dt": dt, "steps": steps, "n_leaf": n_leaf}
+    for variant in ("standard", "conserving"):
+        ctx = api.Context(0)
+        s = Session(ctx, _dev(pos), _dev(vel), _dev(mass), p=w.p, theta=w.theta, eps=w.eps, variant=variant,
+                    precision="mixed32", n_leaf=n_leaf)
+        d0 = s.diagnostics()
+        L0 = d0["L"]
+        drift, torque = [], []
+        t_total = 0.0
+        for k in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(dt, 1)
+            torch.cuda.synchronize()
+            t_total += time.perf_counter() - t0
+            d = s.diagnostics()
+            drift.append(float(np.linalg.norm(d["L"] - L0) / np.linalg.norm(L0)))
+            torque.append(d["torque_rel"])
+        out[variant] = {"L_drift_final": drift[-1], "L_drift_max": max(drift),
+                        "L_drift_every_20": drift[19::20], "torque_rel_mean": float(np.mean(torque)),
+                        "P_final": [float(x) for x in d["P"]], "ms_per_step": 1e3 * t_total / steps}
+        s.close()
+        ctx.close()
+    return out
+
+
+def study_disk(n: int, n_leaf: int, reps: int) -> dict:
+    w = generators.WORKLOADS["disk4m"]
+    pos, mass = w.make(n=n)
+    pd, md = _dev(pos), _dev(mass)
+    ctx = api.Context(0)
+    tree = api.Tree(ctx, pd, md, n_leaf=n_leaf)
+    out = {"study": "disk", "n": n, "p": w.p, "theta": w.theta, "n_leaf": n_leaf}
+    forces = {}
+    for variant in ("standard", "conserving"):
+        for prec in ("mixed32", "fp64"):
+            f = tree.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision=prec)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                tree.rebuild(pd, md)
+                tree.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision=prec, out=f)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            d = ctx.diagnostics(pd, md, f)
+            forces[variant, prec] = f.cpu().numpy()
+            out[f"{variant}_{prec}"] = {"ms": 1e3 * float(np.median(ts)), "torque_rel": float(d[19]),
+                                         "force_rel": float(d[18]), "evals_per_s": n / float(np.median(ts))}
+    for variant in ("standard", "conserving"):
+        a, b = forces[variant, "mixed32"], forces[variant, "fp64"]
+        out[f"{variant}_mixed_vs_fp64_rms"] = float(np.sqrt(np.mean(((a - b) ** 2).sum(1) / (b ** 2).sum(1))))
+    out["conserving_overhead_mixed"] = out["conserving_mixed32"]["ms"] / out["standard_mixed32"]["ms"] - 1.0
+    out["tree"] = tree.info()
+    tree.close()
+    ctx.close()
+    return out
+
+
+def study_serve(n_requests: int, n_sessions: int, rate: float, slots: int, budget_gb: float) -> dict:
+    from .serve import Server, close_sessions, make_inputs, make_sessions, make_trace, summarize
+    trace = make_trace(n_requests, rate=rate)
+    inputs = {r.rid: make_inputs(r) for r in trace}
+    out = {"study": "serve", "requests": n_requests, "sessions": n_sessions, "rate_per_s": rate, "slots": slots,
+           "budget_GB": budget_gb}
+    res = {}
+    for name, prec, k in (("fp64_one_at_a_time", "fp64", 1), ("mixed32_batched", "mixed32", slots)):
+        sessions = make_sessions(n_sessions, precision=prec)
+        try:
+            recs = Server(slots=k, precision=prec, budget_bytes=int(budget_gb * (1 << 30))).run(
+                trace, sessions=sessions, inputs=inputs)
+        finally:
+            close_sessions(sessions)
+        res[name] = recs
+        out[name] = summarize(recs)
+    a = {r.rid: r.sample for r in res["mixed32_batched"] if r.kind == "solve" and not r.error}
+    b = {r.rid: r.sample for r in res["fp64_one_at_a_time"] if r.kind == "solve" and not r.error}
+    errs = [float(np.sqrt(np.mean(((a[i] - b[i]) ** 2).sum(1) / (b[i] ** 2).sum(1)))) for i in a if i in b]
+    out["mixed_vs_fp64_rms_per_request"] = {"max": max(errs), "median": float(np.median(errs))}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", choices=["binary", "disk", "serve"])
+    ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--n-leaf", type=int, default=32)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--sessions", type=int, default=16)
+    ap.add_argument("--rate", type=float, default=100.0)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    a = ap.parse_args()
+    if a.study == "binary":
+        r = study_binary(a.n or (1 << 22), a.steps, a.dt, a.n_leaf)
+    elif a.study == "disk":
+        r = study_disk(a.n or 4194304, a.n_leaf, a.reps)
+    else:
+        r = study_serve(a.requests, a.sessions, a.rate, a.slots, a.budget_gb)
+    print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()
