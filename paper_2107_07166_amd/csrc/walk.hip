@@ -79,43 +79,133 @@ __device__ __forceinline__ Decision decide(const WalkNodes& w, int32_t A, int32_
     return d;
 }
 
-__global__ __launch_bounds__(TB) void walk_count_kernel(WalkNodes w, const int2* __restrict__ fr, int64_t nf,
-                                                        double theta, U3* __restrict__ cnt) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i >= nf) return;
-    const int2 pr = fr[i];
+// Children of an expanded pair, in a fixed order: a self pair gives
+// (c_a, c_b) for a <= b (row major), a split gives (c_a, O).
+struct Kids {
+    int kind;  // 2 self, 3 split
+    int32_t c0, nc, O;
+};
+
+__device__ __forceinline__ Kids kids_of(const WalkNodes& w, int2 pr, const Decision& d) {
+    if (d.kind == 2) return Kids{2, w.child_first[pr.x], w.nchild[pr.x], -1};
+    return Kids{3, w.child_first[d.S], w.nchild[d.S], d.O};
+}
+
+// One walk step covers two tree levels: the pair's own decision and, when it
+// is expanded, the decisions of its children; only grandchildren go to the
+// next frontier.  Outputs are produced in a fixed order (children in order,
+// each child's own output or its children), so counting and emitting agree.
+template <bool EMIT>
+__device__ __forceinline__ void walk_step(const WalkNodes& w, int2 pr, double theta, U3& c, int2* next, int2* far,
+                                          int2* near) {
+    auto put_final = [&](int kind, int32_t A, int32_t B) {
+        const int32_t lo = A < B ? A : B, hi = A < B ? B : A;
+        if (kind == 0) {
+            if (EMIT) near[c.c] = make_int2(lo, hi);
+            c.c++;
+        } else {
+            if (EMIT) far[c.b] = make_int2(lo, hi);
+            c.b++;
+        }
+    };
+    auto put_kids = [&](int2 q, const Decision& d) {
+        const Kids k = kids_of(w, q, d);
+        if (k.kind == 2) {
+            for (int32_t a = 0; a < k.nc; ++a)
+                for (int32_t b = a; b < k.nc; ++b) {
+                    if (EMIT) next[c.a] = make_int2(k.c0 + a, k.c0 + b);
+                    c.a++;
+                }
+        } else {
+            for (int32_t a = 0; a < k.nc; ++a) {
+                if (EMIT) next[c.a] = make_int2(k.c0 + a, k.O);
+                c.a++;
+            }
+        }
+    };
     const Decision d = decide(w, pr.x, pr.y, theta);
+    if (d.kind <= 1) {
+        put_final(d.kind, pr.x, pr.y);
+        return;
+    }
+    const Kids k = kids_of(w, pr, d);
+    for (int32_t a = 0; a < k.nc; ++a) {
+        const int32_t bstart = (k.kind == 2) ? a : 0;
+        const int32_t bend = (k.kind == 2) ? k.nc : 1;
+        for (int32_t b = bstart; b < bend; ++b) {
+            const int2 q = (k.kind == 2) ? make_int2(k.c0 + a, k.c0 + b) : make_int2(k.c0 + a, k.O);
+            const Decision e = decide(w, q.x, q.y, theta);
+            if (e.kind <= 1) put_final(e.kind, q.x, q.y);
+            else put_kids(q, e);
+        }
+    }
+}
+
+__device__ __forceinline__ U3 u3add(U3 x, U3 y) { return {x.a + y.a, x.b + y.b, x.c + y.c}; }
+
+// Per-pair output counts, scanned inside the block: off[i] = exclusive prefix
+// within the block, bsum[block] = block total.
+__global__ __launch_bounds__(TB) void walk_count_kernel(WalkNodes w, const int2* __restrict__ fr, int64_t nf,
+                                                        double theta, U3* __restrict__ off, U3* __restrict__ bsum) {
+    __shared__ U3 wsum[TB / kWave];
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     U3 c{0u, 0u, 0u};
-    if (d.kind == 0) c.c = 1u;
-    else if (d.kind == 1) c.b = 1u;
-    else c.a = d.nnew;
-    cnt[i] = c;
+    if (i < nf) walk_step<false>(w, fr[i], theta, c, nullptr, nullptr, nullptr);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    U3 v = c;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        U3 u{(uint32_t)__shfl_up(v.a, d, kWave), (uint32_t)__shfl_up(v.b, d, kWave),
+             (uint32_t)__shfl_up(v.c, d, kWave)};
+        if (lane >= d) v = u3add(v, u);
+    }
+    if (lane == kWave - 1) wsum[wv] = v;
+    __syncthreads();
+    U3 base{0u, 0u, 0u}, tot{0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < TB / kWave; ++k) {
+        if (k < wv) base = u3add(base, wsum[k]);
+        tot = u3add(tot, wsum[k]);
+    }
+    if (i < nf) off[i] = U3{base.a + v.a - c.a, base.b + v.b - c.b, base.c + v.c - c.c};
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the block totals in place (one block), total in *total.
+__global__ __launch_bounds__(TB) void walk_top_kernel(U3* __restrict__ bsum, int64_t nb, U3* __restrict__ total) {
+    __shared__ U3 sh[TB];
+    U3 carry{0u, 0u, 0u};
+    for (int64_t c0 = 0; c0 < nb; c0 += TB) {
+        const int64_t i = c0 + threadIdx.x;
+        const U3 x = (i < nb) ? bsum[i] : U3{0u, 0u, 0u};
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int d = 1; d < TB; d <<= 1) {
+            const U3 y = (threadIdx.x >= (unsigned)d) ? sh[threadIdx.x - d] : U3{0u, 0u, 0u};
+            __syncthreads();
+            sh[threadIdx.x] = u3add(sh[threadIdx.x], y);
+            __syncthreads();
+        }
+        const U3 incl = sh[threadIdx.x];
+        if (i < nb) bsum[i] = U3{carry.a + incl.a - x.a, carry.b + incl.b - x.b, carry.c + incl.c - x.c};
+        const U3 last = sh[TB - 1];
+        __syncthreads();
+        carry = u3add(carry, last);
+    }
+    if (threadIdx.x == 0) *total = carry;
 }
 
 __global__ __launch_bounds__(TB) void walk_emit_kernel(WalkNodes w, const int2* __restrict__ fr, int64_t nf,
                                                        double theta, const U3* __restrict__ off,
-                                                       int2* __restrict__ next, int2* __restrict__ far,
-                                                       int64_t far_base, int2* __restrict__ near,
-                                                       int64_t near_base) {
+                                                       const U3* __restrict__ bsum, int2* __restrict__ next,
+                                                       int2* __restrict__ far, int64_t far_base,
+                                                       int2* __restrict__ near, int64_t near_base) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i >= nf) return;
-    const int2 pr = fr[i];
-    const Decision d = decide(w, pr.x, pr.y, theta);
-    const U3 o = off[i];
-    const int32_t lo = pr.x < pr.y ? pr.x : pr.y, hi = pr.x < pr.y ? pr.y : pr.x;
-    if (d.kind == 0) {
-        near[near_base + o.c] = make_int2(lo, hi);
-    } else if (d.kind == 1) {
-        far[far_base + o.b] = make_int2(lo, hi);
-    } else if (d.kind == 2) {
-        const int32_t c0 = w.child_first[pr.x], nc = w.nchild[pr.x];
-        uint32_t k = o.a;
-        for (int32_t a = 0; a < nc; ++a)
-            for (int32_t b = a; b < nc; ++b) next[k++] = make_int2(c0 + a, c0 + b);
-    } else {
-        const int32_t c0 = w.child_first[d.S], nc = w.nchild[d.S];
-        for (int32_t a = 0; a < nc; ++a) next[o.a + a] = make_int2(c0 + a, d.O);
-    }
+    const U3 o = off[i], b = bsum[blockIdx.x];
+    U3 c{0u, 0u, 0u};
+    walk_step<true>(w, fr[i], theta, c, next + (o.a + b.a), far + (far_base + o.b + b.b),
+                    near + (near_base + o.c + b.c));
 }
 
 // Directed entries of the far list: (A <- B) and (B <- A).
@@ -334,14 +424,15 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
     int64_t nf = 1, n_far = 0, n_near = 0;
     while (nf > 0) {
         // every buffer resized here is idle: the previous iteration ended with a sync
-        cnt.ensure(ctx, (size_t)nf * sizeof(U3));
-        off.ensure(ctx, (size_t)nf * sizeof(U3));
-        t.scratch.ensure(ctx, scan_scratch_bytes(nf) + 256);
-        hipLaunchKernelGGL(walk_count_kernel, dim3(grid(nf)), dim3(TB), 0, s, w, fr.as<int2>(), nf, theta,
-                           cnt.as<U3>());
+        const int64_t nb = cdiv(nf, TB);
+        cnt.ensure(ctx, (size_t)nf * sizeof(U3));   // per-pair offsets inside the block
+        off.ensure(ctx, (size_t)nb * sizeof(U3));   // block totals -> block offsets
+        hipLaunchKernelGGL(walk_count_kernel, dim3((unsigned)nb), dim3(TB), 0, s, w, fr.as<int2>(), nf, theta,
+                           cnt.as<U3>(), off.as<U3>());
         TFMM_LAUNCHED();
         U3* tot = t.scratch2.as<U3>();
-        exclusive_scan_u3(cnt.as<U3>(), off.as<U3>(), nf, t.scratch.p, tot, s);
+        hipLaunchKernelGGL(walk_top_kernel, dim3(1), dim3(TB), 0, s, off.as<U3>(), nb, tot);
+        TFMM_LAUNCHED();
         const U3 T = read_back(ctx, tot, s);
         if (n_far + (int64_t)T.b > cap_far) {
             cap_far = std::max<int64_t>(2 * cap_far, n_far + T.b);
@@ -352,9 +443,9 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
             t.p2p_pairs.ensure_keep(ctx, (size_t)cap_near * 8, s);
         }
         fr2.ensure(ctx, (size_t)std::max<uint32_t>(T.a, 1) * 8);
-        hipLaunchKernelGGL(walk_emit_kernel, dim3(grid(nf)), dim3(TB), 0, s, w, fr.as<int2>(), nf, theta,
-                           off.as<U3>(), fr2.as<int2>(), t.m2l_pairs.as<int2>(), n_far, t.p2p_pairs.as<int2>(),
-                           n_near);
+        hipLaunchKernelGGL(walk_emit_kernel, dim3((unsigned)nb), dim3(TB), 0, s, w, fr.as<int2>(), nf, theta,
+                           (const U3*)cnt.as<U3>(), (const U3*)off.as<U3>(), fr2.as<int2>(), t.m2l_pairs.as<int2>(),
+                           n_far, t.p2p_pairs.as<int2>(), n_near);
         TFMM_LAUNCHED();
         n_far += T.b;
         n_near += T.c;
