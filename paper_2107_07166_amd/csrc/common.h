@@ -111,6 +111,10 @@ struct Tree {
     DevBuf m2l_targets;           // nodes with a non-empty far list
     int64_t n_m2l_targets = 0;
     DevBuf w_fr, w_fr2, w_cnt, w_off, w_tg, w_sr, w_fl, w_c;  // walk and list-building scratch
+    DevBuf w_state, w_res, w_dec; // device-side walk counters, list totals, pair decisions
+    // sizes seen by the previous walk of this tree (capacity hints for the
+    // passes that run without host synchronisation; 0 = none yet)
+    int64_t walk_hint_fr = 0, walk_hint_far = 0, walk_hint_near = 0;
     // near-field work items: a target leaf's list cut into pieces of bounded
     // source count, each run by one wavefront into its own partial sums
     int64_t n_items = 0, n_partial = 0;

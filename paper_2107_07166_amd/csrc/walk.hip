@@ -79,78 +79,19 @@ __device__ __forceinline__ Decision decide(const WalkNodes& w, int32_t A, int32_
     return d;
 }
 
-// Children of an expanded pair, in a fixed order: a self pair gives
-// (c_a, c_b) for a <= b (row major), a split gives (c_a, O).
-struct Kids {
-    int kind;  // 2 self, 3 split
-    int32_t c0, nc, O;
-};
-
-__device__ __forceinline__ Kids kids_of(const WalkNodes& w, int2 pr, const Decision& d) {
-    if (d.kind == 2) return Kids{2, w.child_first[pr.x], w.nchild[pr.x], -1};
-    return Kids{3, w.child_first[d.S], w.nchild[d.S], d.O};
-}
-
-// One walk step covers two tree levels: the pair's own decision and, when it
-// is expanded, the decisions of its children; only grandchildren go to the
-// next frontier.  Outputs are produced in a fixed order (children in order,
-// each child's own output or its children), so counting and emitting agree.
-template <bool EMIT>
-__device__ __forceinline__ void walk_step(const WalkNodes& w, int2 pr, double theta, U3& c, int2* next, int2* far,
-                                          int2* near) {
-    auto put_final = [&](int kind, int32_t A, int32_t B) {
-        const int32_t lo = A < B ? A : B, hi = A < B ? B : A;
-        if (kind == 0) {
-            if (EMIT) near[c.c] = make_int2(lo, hi);
-            c.c++;
-        } else {
-            if (EMIT) far[c.b] = make_int2(lo, hi);
-            c.b++;
-        }
-    };
-    auto put_kids = [&](int2 q, const Decision& d) {
-        const Kids k = kids_of(w, q, d);
-        if (k.kind == 2) {
-            for (int32_t a = 0; a < k.nc; ++a)
-                for (int32_t b = a; b < k.nc; ++b) {
-                    if (EMIT) next[c.a] = make_int2(k.c0 + a, k.c0 + b);
-                    c.a++;
-                }
-        } else {
-            for (int32_t a = 0; a < k.nc; ++a) {
-                if (EMIT) next[c.a] = make_int2(k.c0 + a, k.O);
-                c.a++;
-            }
-        }
-    };
-    const Decision d = decide(w, pr.x, pr.y, theta);
-    if (d.kind <= 1) {
-        put_final(d.kind, pr.x, pr.y);
-        return;
-    }
-    const Kids k = kids_of(w, pr, d);
-    for (int32_t a = 0; a < k.nc; ++a) {
-        const int32_t bstart = (k.kind == 2) ? a : 0;
-        const int32_t bend = (k.kind == 2) ? k.nc : 1;
-        for (int32_t b = bstart; b < bend; ++b) {
-            const int2 q = (k.kind == 2) ? make_int2(k.c0 + a, k.c0 + b) : make_int2(k.c0 + a, k.O);
-            const Decision e = decide(w, q.x, q.y, theta);
-            if (e.kind <= 1) put_final(e.kind, q.x, q.y);
-            else put_kids(q, e);
-        }
-    }
-}
-
 __device__ __forceinline__ U3 u3add(U3 x, U3 y) { return {x.a + y.a, x.b + y.b, x.c + y.c}; }
 
-// Per-pair output counts, scanned inside the block: off[i] = exclusive prefix
-// within the block, bsum[block] = block total.
-__global__ __launch_bounds__(TB) void walk_count_kernel(WalkNodes w, const int2* __restrict__ fr, int64_t nf,
-                                                        double theta, U3* __restrict__ off, U3* __restrict__ bsum) {
-    __shared__ U3 wsum[TB / kWave];
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    U3 c{0u, 0u, 0u};
-    if (i < nf) walk_step<false>(w, fr[i], theta, c, nullptr, nullptr, nullptr);
+// Pass totals are carried in 64 bits so that a pass too large for 32-bit
+// offsets is detected instead of wrapping.
+struct U3L {
+    unsigned long long a, b, c;
+};
+__device__ __forceinline__ U3L u3ladd(U3L x, U3 y) { return {x.a + y.a, x.b + y.b, x.c + y.c}; }
+__device__ __forceinline__ U3L u3ladd(U3L x, U3L y) { return {x.a + y.a, x.b + y.b, x.c + y.c}; }
+
+// Exclusive scan over the block (every thread calls it); the block total is
+// returned in tot.  The shared array may be reused right after the call.
+__device__ __forceinline__ U3 block_excl_scan(U3 c, U3* wsum, U3& tot) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     U3 v = c;
 #pragma unroll
@@ -161,51 +102,182 @@ __global__ __launch_bounds__(TB) void walk_count_kernel(WalkNodes w, const int2*
     }
     if (lane == kWave - 1) wsum[wv] = v;
     __syncthreads();
-    U3 base{0u, 0u, 0u}, tot{0u, 0u, 0u};
+    U3 base{0u, 0u, 0u}, t{0u, 0u, 0u};
 #pragma unroll
     for (int k = 0; k < TB / kWave; ++k) {
         if (k < wv) base = u3add(base, wsum[k]);
-        tot = u3add(tot, wsum[k]);
+        t = u3add(t, wsum[k]);
     }
-    if (i < nf) off[i] = U3{base.a + v.a - c.a, base.b + v.b - c.b, base.c + v.c - c.c};
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    __syncthreads();
+    tot = t;
+    return U3{base.a + v.a - c.a, base.b + v.b - c.b, base.c + v.c - c.c};
 }
 
-// Exclusive scan of the block totals in place (one block), total in *total.
-__global__ __launch_bounds__(TB) void walk_top_kernel(U3* __restrict__ bsum, int64_t nb, U3* __restrict__ total) {
-    __shared__ U3 sh[TB];
-    U3 carry{0u, 0u, 0u};
-    for (int64_t c0 = 0; c0 < nb; c0 += TB) {
-        const int64_t i = c0 + threadIdx.x;
-        const U3 x = (i < nb) ? bsum[i] : U3{0u, 0u, 0u};
-        sh[threadIdx.x] = x;
-        __syncthreads();
-        for (int d = 1; d < TB; d <<= 1) {
-            const U3 y = (threadIdx.x >= (unsigned)d) ? sh[threadIdx.x - d] : U3{0u, 0u, 0u};
-            __syncthreads();
-            sh[threadIdx.x] = u3add(sh[threadIdx.x], y);
-            __syncthreads();
+// Sum over the block (every thread calls it and gets the total).
+__device__ __forceinline__ U3L block_sum(U3L x, U3L* wsum) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        x.a += __shfl_xor(x.a, d, kWave);
+        x.b += __shfl_xor(x.b, d, kWave);
+        x.c += __shfl_xor(x.c, d, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = x;
+    __syncthreads();
+    U3L t{0ull, 0ull, 0ull};
+#pragma unroll
+    for (int k = 0; k < TB / kWave; ++k) t = u3ladd(t, wsum[k]);
+    __syncthreads();
+    return t;
+}
+
+// ---- frontier passes ----------------------------------------------------------
+// A pass has two kernels.  The counting kernel decides every frontier pair,
+// stores the decision and scans the output counts (next-frontier pairs, far
+// pairs, near pairs) inside its block; the emitting kernel adds the totals of
+// the blocks before it and writes the outputs.  Block b of a pass takes a
+// contiguous range of frontier tiles, so the outputs follow the frontier
+// order whatever the grid: children of a pair in a fixed order (a self pair
+// gives (c_a, c_b) for a <= b, row major; a split gives (c_a, O)).
+//
+// The frontier size and the running list lengths live on the device, double
+// buffered by pass parity (a pass reads slot p and writes slot 1 - p), so
+// passes can be queued without reading anything back.  A pass whose outputs
+// would not fit sets a sticky flag and writes nothing; later passes then see
+// an empty frontier.
+struct WalkState {
+    uint32_t nf[2];
+    uint32_t overflow;
+    uint32_t passes;  // passes that found a non-empty frontier
+    uint32_t max_nf;  // largest frontier seen
+    uint32_t pad;
+    unsigned long long n_far[2], n_near[2];
+};
+constexpr int kWalkGrid = 1024;
+
+__device__ __forceinline__ void block_tiles(uint32_t nf, int64_t& t0, int64_t& t1) {
+    const int64_t tiles = ((int64_t)nf + TB - 1) / TB;
+    const int64_t per = (tiles + gridDim.x - 1) / gridDim.x;
+    t0 = (int64_t)blockIdx.x * per;
+    t1 = t0 + per < tiles ? t0 + per : tiles;
+}
+
+__global__ void walk_init_kernel(WalkState* __restrict__ st, int2* __restrict__ fr) {
+    if (threadIdx.x == 0) {
+        st->nf[0] = 1u;
+        st->nf[1] = 0u;
+        st->overflow = 0u;
+        st->passes = 0u;
+        st->max_nf = 1u;
+        st->pad = 0u;
+        st->n_far[0] = st->n_far[1] = 0ull;
+        st->n_near[0] = st->n_near[1] = 0ull;
+        fr[0] = make_int2(0, 0);
+    }
+}
+
+// Decision code: bits 0-1 kind (0 near, 1 far, 2 expand self, 3 split);
+// bit 2 set when the split node is the pair's second node.
+__global__ __launch_bounds__(TB) void walk_count_pass_kernel(WalkNodes w, const int2* __restrict__ fr,
+                                                             const WalkState* __restrict__ st, int parity,
+                                                             double theta, uint8_t* __restrict__ dec,
+                                                             U3* __restrict__ off, U3L* __restrict__ bsum) {
+    __shared__ U3 wsum[TB / kWave];
+    const uint32_t nf = st->overflow ? 0u : st->nf[parity];
+    int64_t t0, t1;
+    block_tiles(nf, t0, t1);
+    U3L carry{0ull, 0ull, 0ull};
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t i = t * TB + threadIdx.x;
+        U3 c{0u, 0u, 0u};
+        if (i < nf) {
+            const int2 pr = fr[i];
+            const Decision d = decide(w, pr.x, pr.y, theta);
+            if (d.kind == 0) c.c = 1u;
+            else if (d.kind == 1) c.b = 1u;
+            else c.a = d.nnew;
+            dec[i] = (uint8_t)(d.kind | ((d.kind == 3 && d.S == pr.y) ? 4 : 0));
         }
-        const U3 incl = sh[threadIdx.x];
-        if (i < nb) bsum[i] = U3{carry.a + incl.a - x.a, carry.b + incl.b - x.b, carry.c + incl.c - x.c};
-        const U3 last = sh[TB - 1];
-        __syncthreads();
-        carry = u3add(carry, last);
+        U3 tot;
+        const U3 e = block_excl_scan(c, wsum, tot);
+        if (i < nf) off[i] = U3{(uint32_t)carry.a + e.a, (uint32_t)carry.b + e.b, (uint32_t)carry.c + e.c};
+        carry = u3ladd(carry, tot);
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (threadIdx.x == 0) bsum[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(TB) void walk_emit_kernel(WalkNodes w, const int2* __restrict__ fr, int64_t nf,
-                                                       double theta, const U3* __restrict__ off,
-                                                       const U3* __restrict__ bsum, int2* __restrict__ next,
-                                                       int2* __restrict__ far, int64_t far_base,
-                                                       int2* __restrict__ near, int64_t near_base) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i >= nf) return;
-    const U3 o = off[i], b = bsum[blockIdx.x];
-    U3 c{0u, 0u, 0u};
-    walk_step<true>(w, fr[i], theta, c, next + (o.a + b.a), far + (far_base + o.b + b.b),
-                    near + (near_base + o.c + b.c));
+// Sum of the block totals of a pass (one block), for the host-sized passes.
+__global__ __launch_bounds__(TB) void walk_total_kernel(const U3L* __restrict__ bsum, int nb,
+                                                        U3L* __restrict__ total) {
+    __shared__ U3L wsum[TB / kWave];
+    U3L x{0ull, 0ull, 0ull};
+    for (int j = threadIdx.x; j < nb; j += TB) x = u3ladd(x, bsum[j]);
+    const U3L t = block_sum(x, wsum);
+    if (threadIdx.x == 0) *total = t;
+}
+
+// Every block sums the block totals itself (the pass total and its own
+// offset), so no scan launch sits between counting and emitting.
+__global__ __launch_bounds__(TB) void walk_emit_pass_kernel(WalkNodes w, const int2* __restrict__ fr,
+                                                            WalkState* __restrict__ st, int parity,
+                                                            const uint8_t* __restrict__ dec,
+                                                            const U3* __restrict__ off, const U3L* __restrict__ bsum,
+                                                            int2* __restrict__ next, int2* __restrict__ far,
+                                                            int2* __restrict__ near, uint32_t cap_next,
+                                                            unsigned long long cap_far,
+                                                            unsigned long long cap_near) {
+    __shared__ U3L wsum[TB / kWave];
+    U3L before{0ull, 0ull, 0ull}, all{0ull, 0ull, 0ull};
+    for (int j = threadIdx.x; j < (int)gridDim.x; j += TB) {
+        const U3L x = bsum[j];
+        all = u3ladd(all, x);
+        if (j < (int)blockIdx.x) before = u3ladd(before, x);
+    }
+    const U3L T = block_sum(all, wsum);
+    const U3L B = block_sum(before, wsum);
+    const uint32_t nf = st->overflow ? 0u : st->nf[parity];
+    const unsigned long long far0 = st->n_far[parity], near0 = st->n_near[parity];
+    const unsigned long long lim = 0xffffffffull;
+    const bool ovf = T.a > cap_next || T.b > lim || T.c > lim || far0 + T.b > cap_far || near0 + T.c > cap_near;
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    if (ovf) {
+        if (leader) {
+            st->overflow = 1u;
+            st->nf[parity ^ 1] = 0u;
+        }
+        return;
+    }
+    if (leader) {
+        st->nf[parity ^ 1] = (uint32_t)T.a;
+        st->n_far[parity ^ 1] = far0 + T.b;
+        st->n_near[parity ^ 1] = near0 + T.c;
+        if (nf > 0u) st->passes += 1u;
+        if ((uint32_t)T.a > st->max_nf) st->max_nf = (uint32_t)T.a;
+    }
+    int64_t t0, t1;
+    block_tiles(nf, t0, t1);
+    const int64_t iend = t1 * TB < (int64_t)nf ? t1 * TB : (int64_t)nf;
+    for (int64_t i = t0 * TB + threadIdx.x; i < iend; i += TB) {
+        const int2 pr = fr[i];
+        const int code = dec[i];
+        const int kind = code & 3;
+        const U3L o = u3ladd(B, off[i]);
+        const int32_t lo = pr.x < pr.y ? pr.x : pr.y, hi = pr.x < pr.y ? pr.y : pr.x;
+        if (kind == 0) {
+            near[near0 + o.c] = make_int2(lo, hi);
+        } else if (kind == 1) {
+            far[far0 + o.b] = make_int2(lo, hi);
+        } else if (kind == 2) {
+            const int32_t c0 = w.child_first[pr.x], nc = w.nchild[pr.x];
+            int2* q = next + o.a;
+            for (int32_t x = 0; x < nc; ++x)
+                for (int32_t y = x; y < nc; ++y) *q++ = make_int2(c0 + x, c0 + y);
+        } else {
+            const int32_t S = (code & 4) ? pr.y : pr.x, O = (code & 4) ? pr.x : pr.y;
+            const int32_t c0 = w.child_first[S], nc = w.nchild[S];
+            int2* q = next + o.a;
+            for (int32_t x = 0; x < nc; ++x) q[x] = make_int2(c0 + x, O);
+        }
+    }
 }
 
 // Directed entries of the far list: (A <- B) and (B <- A).
@@ -332,13 +404,22 @@ __global__ __launch_bounds__(TB) void item_build_kernel(const uint32_t* __restri
     it_leaf[i] = (int32_t)tgt[q];
 }
 
-__global__ __launch_bounds__(TB) void item_finish_kernel(int64_t T, int64_t ne, const uint32_t* __restrict__ it_q0,
+// The item count T is read on the device (the host only knows ne >= T).
+// Entries i >= T get pc = 0 so that a scan over all ne slots yields the
+// partial-sum offsets of the items and their total.
+__global__ __launch_bounds__(TB) void item_finish_kernel(const uint32_t* __restrict__ T_dev, int64_t ne,
+                                                         const uint32_t* __restrict__ it_q0,
                                                          const int32_t* __restrict__ it_leaf,
                                                          const int32_t* __restrict__ count,
                                                          uint32_t* __restrict__ it_q1, uint32_t* __restrict__ pc,
                                                          int32_t* __restrict__ leaf_item0) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i >= T) return;
+    if (i >= ne) return;
+    const int64_t T = *T_dev;
+    if (i >= T) {
+        pc[i] = 0u;
+        return;
+    }
     it_q1[i] = (i + 1 < T) ? it_q0[i + 1] : (uint32_t)ne;
     const int32_t L = it_leaf[i];
     const bool first_of_leaf = (i == 0 || it_leaf[i - 1] != L);
@@ -348,10 +429,13 @@ __global__ __launch_bounds__(TB) void item_finish_kernel(int64_t T, int64_t ne, 
     if (first_of_leaf) leaf_item0[L] = (int32_t)i;
 }
 
-__global__ __launch_bounds__(TB) void item_count_kernel(int64_t T, const int32_t* __restrict__ it_leaf,
+__global__ __launch_bounds__(TB) void item_count_kernel(const uint32_t* __restrict__ T_dev, int64_t ne,
+                                                        const int32_t* __restrict__ it_leaf,
                                                         const int32_t* __restrict__ leaf_item0,
                                                         int32_t* __restrict__ leaf_nitems) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= ne) return;
+    const int64_t T = *T_dev;
     if (i >= T) return;
     const int32_t L = it_leaf[i];
     if (i + 1 == T || it_leaf[i + 1] != L) leaf_nitems[L] = (int32_t)(i + 1 - leaf_item0[L]);
@@ -395,20 +479,12 @@ void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& off,
     std::swap(srcbuf.ctx, srcout.ctx);
 }
 
-}  // namespace
-
-void walk_tree(Tree& t, double theta, hipStream_t s) {
+// Frontier passes sized on the host: the totals of every pass are read back
+// and the buffers grown before its outputs are written.  Used for the first
+// walk of a tree and whenever the unsynchronised passes ran out of room.
+void walk_bfs_sized(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
     Ctx* ctx = t.ctx;
     const int64_t nn = t.n_nodes;
-    WalkNodes w{t.nd_level.as<int32_t>(), t.nd_child_first.as<int32_t>(), t.nd_nchild.as<int32_t>(),
-                t.nd_Z.as<double4>(), t.nd_rmax.as<double>()};
-
-    // frontier (int2), per-pair counts and offsets (U3); all tree-owned, grow-only
-    DevBuf& fr = t.w_fr;
-    DevBuf& fr2 = t.w_fr2;
-    DevBuf& cnt = t.w_cnt;
-    DevBuf& off = t.w_off;
-    fr.ensure(ctx, 4096 * 8);
     int64_t cap_far = (int64_t)(t.m2l_pairs.cap / 8), cap_near = (int64_t)(t.p2p_pairs.cap / 8);
     if (cap_far < 4096) {
         cap_far = std::max<int64_t>(4096, 64 * nn);
@@ -418,44 +494,145 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         cap_near = std::max<int64_t>(4096, 16 * nn);
         t.p2p_pairs.ensure(ctx, (size_t)cap_near * 8);
     }
+    t.w_fr.ensure(ctx, 4096 * 8);
+    t.w_off.ensure(ctx, (size_t)kWalkGrid * sizeof(U3L));
+    t.w_state.ensure(ctx, sizeof(WalkState));
     t.scratch2.ensure(ctx, 256);
-    const int2 root = make_int2(0, 0);
-    TFMM_HIP(hipMemcpyAsync(fr.p, &root, sizeof(int2), hipMemcpyHostToDevice, s));
-    int64_t nf = 1, n_far = 0, n_near = 0;
-    while (nf > 0) {
-        // every buffer resized here is idle: the previous iteration ended with a sync
-        const int64_t nb = cdiv(nf, TB);
-        cnt.ensure(ctx, (size_t)nf * sizeof(U3));   // per-pair offsets inside the block
-        off.ensure(ctx, (size_t)nb * sizeof(U3));   // block totals -> block offsets
-        hipLaunchKernelGGL(walk_count_kernel, dim3((unsigned)nb), dim3(TB), 0, s, w, fr.as<int2>(), nf, theta,
-                           cnt.as<U3>(), off.as<U3>());
+    WalkState* st = t.w_state.as<WalkState>();
+    U3L* tot = t.scratch2.as<U3L>();
+    hipLaunchKernelGGL(walk_init_kernel, dim3(1), dim3(kWave), 0, s, st, t.w_fr.as<int2>());
+    TFMM_LAUNCHED();
+    DevBuf* cur = &t.w_fr;
+    DevBuf* nxt = &t.w_fr2;
+    int64_t nf = 1, max_nf = 1, n_far = 0, n_near = 0;
+    for (int k = 0; nf > 0; ++k) {
+        const int parity = k & 1;
+        const unsigned g = (unsigned)std::min<int64_t>(kWalkGrid, cdiv(nf, TB));
+        // buffers resized here are idle: a resize waits for the device
+        t.w_dec.ensure(ctx, (size_t)nf);
+        t.w_cnt.ensure(ctx, (size_t)nf * sizeof(U3));
+        hipLaunchKernelGGL(walk_count_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur->as<int2>(),
+                           (const WalkState*)st, parity, theta, t.w_dec.as<uint8_t>(), t.w_cnt.as<U3>(),
+                           t.w_off.as<U3L>());
         TFMM_LAUNCHED();
-        U3* tot = t.scratch2.as<U3>();
-        hipLaunchKernelGGL(walk_top_kernel, dim3(1), dim3(TB), 0, s, off.as<U3>(), nb, tot);
+        hipLaunchKernelGGL(walk_total_kernel, dim3(1), dim3(TB), 0, s, (const U3L*)t.w_off.as<U3L>(), (int)g, tot);
         TFMM_LAUNCHED();
-        const U3 T = read_back(ctx, tot, s);
+        const U3L T = read_back(ctx, (const U3L*)tot, s);
+        if (T.a > UINT32_MAX || T.b > UINT32_MAX || T.c > UINT32_MAX)
+            fail(TFMM_ENOMEM, "walk: one frontier pass would emit more than 2^32 pairs");
         if (n_far + (int64_t)T.b > cap_far) {
-            cap_far = std::max<int64_t>(2 * cap_far, n_far + T.b);
+            cap_far = std::max<int64_t>(2 * cap_far, n_far + (int64_t)T.b);
             t.m2l_pairs.ensure_keep(ctx, (size_t)cap_far * 8, s);
         }
         if (n_near + (int64_t)T.c > cap_near) {
-            cap_near = std::max<int64_t>(2 * cap_near, n_near + T.c);
+            cap_near = std::max<int64_t>(2 * cap_near, n_near + (int64_t)T.c);
             t.p2p_pairs.ensure_keep(ctx, (size_t)cap_near * 8, s);
         }
-        fr2.ensure(ctx, (size_t)std::max<uint32_t>(T.a, 1) * 8);
-        hipLaunchKernelGGL(walk_emit_kernel, dim3((unsigned)nb), dim3(TB), 0, s, w, fr.as<int2>(), nf, theta,
-                           (const U3*)cnt.as<U3>(), (const U3*)off.as<U3>(), fr2.as<int2>(), t.m2l_pairs.as<int2>(),
-                           n_far, t.p2p_pairs.as<int2>(), n_near);
+        nxt->ensure(ctx, (size_t)std::max<unsigned long long>(T.a, 1) * 8);
+        const size_t cap_next = std::min<size_t>(nxt->cap / 8, UINT32_MAX);
+        hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur->as<int2>(), st,
+                           parity, (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3*)t.w_cnt.as<U3>(),
+                           (const U3L*)t.w_off.as<U3L>(), nxt->as<int2>(), t.m2l_pairs.as<int2>(),
+                           t.p2p_pairs.as<int2>(), (uint32_t)cap_next, (unsigned long long)(t.m2l_pairs.cap / 8),
+                           (unsigned long long)(t.p2p_pairs.cap / 8));
         TFMM_LAUNCHED();
-        n_far += T.b;
-        n_near += T.c;
-        nf = T.a;
-        std::swap(fr.p, fr2.p);
-        std::swap(fr.cap, fr2.cap);
-        std::swap(fr.ctx, fr2.ctx);
+        n_far += (int64_t)T.b;
+        n_near += (int64_t)T.c;
+        nf = (int64_t)T.a;
+        max_nf = std::max(max_nf, nf);
+        std::swap(cur, nxt);
     }
+    const WalkState h = read_back(ctx, (const WalkState*)st, s);
+    if (h.overflow)
+        fail(TFMM_EDEVICE, "walk: a host-sized frontier pass reported an overflow");
     t.n_m2l = n_far;
     t.n_p2p = n_near;
+    t.walk_hint_fr = max_nf;
+}
+
+// Frontier passes with no host synchronisation, sized from the previous walk
+// of this tree plus a quarter.  A pair's level sum grows by at least one per
+// expansion, a non-leaf sits above the deepest level and a pair of leaves is
+// never expanded, so every frontier after pass 2 max_level is empty; the host
+// checks that, and the overflow flag, once at the end.  Returns false (lists
+// invalid) when the host-sized passes must be used instead.
+bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
+    Ctx* ctx = t.ctx;
+    if (t.walk_hint_fr <= 0) return false;
+    const int64_t want_fr = t.walk_hint_fr + t.walk_hint_fr / 4 + 4096;
+    const int64_t want_far = t.walk_hint_far + t.walk_hint_far / 4 + 4096;
+    const int64_t want_near = t.walk_hint_near + t.walk_hint_near / 4 + 4096;
+    if (want_fr > (int64_t)UINT32_MAX) return false;
+    t.w_fr.ensure(ctx, (size_t)want_fr * 8);
+    t.w_fr2.ensure(ctx, (size_t)want_fr * 8);
+    t.w_dec.ensure(ctx, (size_t)want_fr);
+    t.w_cnt.ensure(ctx, (size_t)want_fr * sizeof(U3));
+    t.w_off.ensure(ctx, (size_t)kWalkGrid * sizeof(U3L));
+    t.m2l_pairs.ensure(ctx, (size_t)want_far * 8);
+    t.p2p_pairs.ensure(ctx, (size_t)want_near * 8);
+    t.w_state.ensure(ctx, sizeof(WalkState));
+    const size_t cap_next = std::min({t.w_fr.cap / 8, t.w_fr2.cap / 8, t.w_dec.cap, t.w_cnt.cap / sizeof(U3),
+                                      (size_t)UINT32_MAX});
+    const unsigned long long cap_far = t.m2l_pairs.cap / 8, cap_near = t.p2p_pairs.cap / 8;
+    WalkState* st = t.w_state.as<WalkState>();
+    hipLaunchKernelGGL(walk_init_kernel, dim3(1), dim3(kWave), 0, s, st, t.w_fr.as<int2>());
+    TFMM_LAUNCHED();
+    const int passes = 2 * t.max_level + 1;
+    int64_t bound = 1;  // a pass's frontier is at most 36 times the previous one
+    for (int k = 0; k < passes; ++k) {
+        const int parity = k & 1;
+        const unsigned g = (unsigned)std::min<int64_t>(kWalkGrid, cdiv(bound, TB));
+        int2* cur = parity ? t.w_fr2.as<int2>() : t.w_fr.as<int2>();
+        int2* nxt = parity ? t.w_fr.as<int2>() : t.w_fr2.as<int2>();
+        hipLaunchKernelGGL(walk_count_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur,
+                           (const WalkState*)st, parity, theta, t.w_dec.as<uint8_t>(), t.w_cnt.as<U3>(),
+                           t.w_off.as<U3L>());
+        TFMM_LAUNCHED();
+        hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur, st, parity,
+                           (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3*)t.w_cnt.as<U3>(),
+                           (const U3L*)t.w_off.as<U3L>(), nxt, t.m2l_pairs.as<int2>(), t.p2p_pairs.as<int2>(),
+                           (uint32_t)cap_next, cap_far, cap_near);
+        TFMM_LAUNCHED();
+        bound = std::min<int64_t>((int64_t)cap_next, 36 * bound);
+    }
+    const WalkState h = read_back(ctx, (const WalkState*)st, s);
+    const int pf = passes & 1;
+    if (h.overflow || h.nf[pf] != 0u) return false;
+    t.n_m2l = (int64_t)h.n_far[pf];
+    t.n_p2p = (int64_t)h.n_near[pf];
+    t.walk_hint_fr = h.max_nf;
+    return true;
+}
+
+// Device slots of the list-building totals, read back together at the end.
+struct WalkTotals {
+    uint32_t far_targets;  // nodes with a non-empty far list
+    uint32_t near_entries; // directed near entries (check of 2 n_near - n_leaves)
+    uint32_t items;        // near-field work items
+    uint32_t partial;      // partial-sum rows of multi-item leaves
+    uint32_t scratch[12];  // totals nobody reads
+    unsigned long long near_int;
+};
+
+}  // namespace
+
+void walk_tree(Tree& t, double theta, hipStream_t s) {
+    Ctx* ctx = t.ctx;
+    const int64_t nn = t.n_nodes;
+    WalkNodes w{t.nd_level.as<int32_t>(), t.nd_child_first.as<int32_t>(), t.nd_nchild.as<int32_t>(),
+                t.nd_Z.as<double4>(), t.nd_rmax.as<double>()};
+    t.walk_valid = false;
+    if (!walk_bfs_async(t, w, theta, s)) walk_bfs_sized(t, w, theta, s);
+    t.walk_hint_far = t.n_m2l;
+    t.walk_hint_near = t.n_p2p;
+    const int64_t n_far = t.n_m2l, n_near = t.n_p2p;
+
+    t.w_res.ensure(ctx, sizeof(WalkTotals));
+    WalkTotals* res = t.w_res.as<WalkTotals>();
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(TB), 0, s, reinterpret_cast<int32_t*>(res),
+                       (int64_t)(sizeof(WalkTotals) / 4), 0);
+    TFMM_LAUNCHED();
+    uint32_t* junk = res->scratch;
 
     DevBuf& tg = t.w_tg;
     DevBuf& sr = t.w_sr;
@@ -478,15 +655,15 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
                            (const uint32_t*)t.m2l_off.as<uint32_t>(), nn, flag);
         TFMM_LAUNCHED();
         t.scratch.ensure(ctx, scan_scratch_bytes(nn) + 256);
-        uint32_t* tot = t.scratch2.as<uint32_t>();
-        exclusive_scan_u32(flag, ex, nn, t.scratch.p, tot, s);
-        t.n_m2l_targets = read_back(ctx, tot, s);
-        t.m2l_targets.ensure(ctx, (size_t)std::max<int64_t>(t.n_m2l_targets, 1) * 4);
+        exclusive_scan_u32(flag, ex, nn, t.scratch.p, &res->far_targets, s);
+        t.m2l_targets.ensure(ctx, (size_t)std::max<int64_t>(nn, 1) * 4);
         hipLaunchKernelGGL(compact_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)flag,
                            (const uint32_t*)ex, nn, t.m2l_targets.as<int32_t>());
         TFMM_LAUNCHED();
     }
-    // near lists: directed (self pairs once), by target
+    // near lists: directed (self pairs once), by target.  Every leaf has
+    // exactly one self pair, so the entry count is 2 n_near - n_leaves.
+    const int64_t ne = 2 * n_near - t.n_leaves;
     {
         t.w_c.ensure(ctx, (size_t)std::max<int64_t>(n_near, 1) * 8);
         uint32_t* c = t.w_c.as<uint32_t>();
@@ -494,9 +671,7 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         hipLaunchKernelGGL(near_count_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near, c);
         TFMM_LAUNCHED();
         t.scratch.ensure(ctx, scan_scratch_bytes(n_near) + 256);
-        uint32_t* tot = t.scratch2.as<uint32_t>();
-        exclusive_scan_u32(c, o, n_near, t.scratch.p, tot, s);
-        const int64_t ne = read_back(ctx, tot, s);
+        exclusive_scan_u32(c, o, n_near, t.scratch.p, &res->near_entries, s);
         tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         hipLaunchKernelGGL(near_entries_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near,
@@ -504,16 +679,13 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         TFMM_LAUNCHED();
         build_csr(t, tg, sr, ne, t.p2p_off, t.p2p_src, s);
         // directed near particle interactions (for throughput accounting)
-        unsigned long long* acc = reinterpret_cast<unsigned long long*>(t.scratch2.as<char>() + 128);
-        hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(TB), 0, s, reinterpret_cast<int32_t*>(acc), 2, 0);
-        TFMM_LAUNCHED();
         const unsigned nb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(ne, TB)));
         hipLaunchKernelGGL(near_work_kernel, dim3(nb), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
-                           (const int32_t*)t.p2p_src.as<int32_t>(), ne, t.nd_count.as<int32_t>(), acc);
+                           (const int32_t*)t.p2p_src.as<int32_t>(), ne, t.nd_count.as<int32_t>(), &res->near_int);
         TFMM_LAUNCHED();
-        t.n_near_int = (int64_t)read_back(ctx, acc, s);
 
-        // work items over the sorted near entries (tg holds the sorted targets)
+        // work items over the sorted near entries (tg holds the sorted targets);
+        // there are at most ne items, so every item array is sized by ne
         t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 16);
         uint32_t* ec = t.w_c.as<uint32_t>();
         uint32_t* P = ec + std::max<int64_t>(ne, 1);
@@ -523,35 +695,40 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         hipLaunchKernelGGL(entry_sources_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const int32_t*)t.p2p_src.as<int32_t>(),
                            ne, t.nd_count.as<int32_t>(), ec);
         TFMM_LAUNCHED();
-        uint32_t* tot2 = t.scratch2.as<uint32_t>();
-        exclusive_scan_u32(ec, P, ne, t.scratch.p, tot2, s);
+        exclusive_scan_u32(ec, P, ne, t.scratch.p, junk, s);
         hipLaunchKernelGGL(item_flag_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
                            (const uint32_t*)P, (const uint32_t*)t.p2p_off.as<uint32_t>(), ne, fl);
         TFMM_LAUNCHED();
-        exclusive_scan_u32(fl, ex, ne, t.scratch.p, tot2, s);
-        const int64_t T = read_back(ctx, tot2, s);
-        t.n_items = T;
-        t.it_leaf.ensure(ctx, (size_t)std::max<int64_t>(T, 1) * 4);
-        t.it_q0.ensure(ctx, (size_t)std::max<int64_t>(T, 1) * 4);
-        t.it_q1.ensure(ctx, (size_t)std::max<int64_t>(T, 1) * 4);
-        t.it_pbase.ensure(ctx, (size_t)std::max<int64_t>(T, 1) * 4);
+        exclusive_scan_u32(fl, ex, ne, t.scratch.p, &res->items, s);
+        const size_t ni = (size_t)std::max<int64_t>(ne, 1);
+        t.it_leaf.ensure(ctx, ni * 4);
+        t.it_q0.ensure(ctx, ni * 4);
+        t.it_q1.ensure(ctx, ni * 4);
+        t.it_pbase.ensure(ctx, ni * 4);
         t.leaf_item0.ensure(ctx, (size_t)(nn + 1) * 4);
+        t.leaf_nitems.ensure(ctx, (size_t)(nn + 1) * 4);
         hipLaunchKernelGGL(item_build_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)fl, (const uint32_t*)ex,
                            (const uint32_t*)tg.as<uint32_t>(), ne, t.it_leaf.as<int32_t>(), t.it_q0.as<uint32_t>());
         TFMM_LAUNCHED();
         // per-item partial sizes reuse the entry-count scratch
-        hipLaunchKernelGGL(item_finish_kernel, dim3(grid(T)), dim3(TB), 0, s, T, ne,
+        hipLaunchKernelGGL(item_finish_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)&res->items, ne,
                            (const uint32_t*)t.it_q0.as<uint32_t>(), (const int32_t*)t.it_leaf.as<int32_t>(),
                            t.nd_count.as<int32_t>(), t.it_q1.as<uint32_t>(), ec, t.leaf_item0.as<int32_t>());
         TFMM_LAUNCHED();
-        t.leaf_nitems.ensure(ctx, (size_t)(nn + 1) * 4);
-        hipLaunchKernelGGL(item_count_kernel, dim3(grid(T)), dim3(TB), 0, s, T, (const int32_t*)t.it_leaf.as<int32_t>(),
-                           (const int32_t*)t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>());
+        hipLaunchKernelGGL(item_count_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)&res->items, ne,
+                           (const int32_t*)t.it_leaf.as<int32_t>(), (const int32_t*)t.leaf_item0.as<int32_t>(),
+                           t.leaf_nitems.as<int32_t>());
         TFMM_LAUNCHED();
-        t.scratch.ensure(ctx, scan_scratch_bytes(T) + 256);
-        exclusive_scan_u32(ec, t.it_pbase.as<uint32_t>(), T, t.scratch.p, tot2, s);
-        t.n_partial = read_back(ctx, tot2, s);
+        exclusive_scan_u32(ec, t.it_pbase.as<uint32_t>(), ne, t.scratch.p, &res->partial, s);
     }
+    const WalkTotals h = read_back(ctx, (const WalkTotals*)res, s);
+    if ((int64_t)h.near_entries != ne)
+        fail(TFMM_EDEVICE, "walk: near entry count " + std::to_string(h.near_entries) + " differs from " +
+                               std::to_string(ne));
+    t.n_m2l_targets = h.far_targets;
+    t.n_near_int = (int64_t)h.near_int;
+    t.n_items = h.items;
+    t.n_partial = h.partial;
     t.walk_valid = true;
     t.walk_theta = theta;
 }

@@ -112,6 +112,30 @@ def test_lists_bitexact(ctx, name, n_leaf, theta):
     gt.close()
 
 
+@pytest.mark.parametrize("name,n_leaf", [("plummer20k", 16), ("ball2k", 8), ("coincident", 8), ("single", 4)])
+def test_lists_rewalk(ctx, name, n_leaf):
+    """A tree walked again sizes its frontier passes from the previous walk
+    and runs them without host synchronisation; when they run out of room
+    (theta 0.8 -> 0.2 multiplies the list lengths on plummer20k) the walk
+    falls back to host-sized passes.  Every walk must give the oracle's
+    lists."""
+    pos, m = _case(name)
+    gt = _gpu_tree(ctx, pos, m, n_leaf)
+    sizes = {}
+    for theta in (0.8, 0.8, 0.2, 0.2, 0.5):
+        gt.walk(theta)
+        gf, gn = gt.lists()
+        of, on = oracle.Tree(pos, m, n_leaf=n_leaf, theta=theta).lists()
+        assert len(gf) == len(of) and len(gn) == len(on), theta
+        assert np.array_equal(_pairset(gf), _pairset(of)), theta
+        assert np.array_equal(_pairset(gn), _pairset(on)), theta
+        sizes[theta] = (len(gf), len(gn))
+    if name == "plummer20k":
+        # the walk at 0.2 cannot fit the room sized from the walk at 0.8
+        assert sizes[0.2][0] > 2 * sizes[0.8][0] + 8192
+    gt.close()
+
+
 _oracle_cache = {}
 
 
