@@ -2,14 +2,17 @@
 // of every near pair of leaves, both directions, self pairs included (the
 // gradient of Eq. jia with -(r^2 + eps^2)^(-1/2)).
 //
-// One wavefront (= one workgroup) owns one target leaf.  Its nt <= 64 target
-// particles are replicated G = floor(64 / nt) times across the lanes; replica
-// g takes every G-th staged source, so small leaves still fill the wave.
+// One wavefront (= one workgroup) owns one target leaf.  A chunk of nt <= 64
+// target particles is laid out over the lanes as G groups of L lanes, each
+// lane holding R consecutive targets (L = ceil(nt / R), G = floor(64 / L));
+// group g takes every G-th staged source.  R in 1..4 is chosen per chunk to
+// keep the most lanes busy (R = 1 with G replicas for small leaves, R > 1 for
+// leaves of 33..64 particles), and a staged source is reused for R targets.
 // Source leaves are staged into an LDS chunk already expressed in the target
 // leaf's frame: the leaf-to-leaf offset Z_B - Z_A is applied in FP64 and the
 // result rounded once (FP32 in the mixed path), so the inner loop is a uniform
-// stream of LDS broadcasts and FMAs.  Each chunk's FP32 partial sums go into
-// FP64 per-lane accumulators; the replicas are summed through LDS at the end.
+// stream of LDS broadcasts and FMAs.  Each chunk's partial sums go into FP64
+// per-lane accumulators; the groups are summed through LDS at the end.
 // A leaf's list is cut into work items of bounded source count (a leaf in a
 // sparse halo can be near almost every particle); every item writes its own
 // partial sums and a second kernel adds a leaf's items in order.
@@ -63,6 +66,49 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
+constexpr int RMAX = 4;  // most targets per lane
+
+// Lane layout of a target chunk: the R in 1..RMAX that keeps the most lanes
+// busy (useful fraction nt * G / (64 * R)); ties go to the smaller R.
+__device__ __forceinline__ void chunk_layout(int nt, int& R, int& L, int& G) {
+    R = 1;
+    L = nt;
+    G = kWave / nt;
+#pragma unroll
+    for (int r = 2; r <= RMAX; ++r) {
+        const int l = (nt + r - 1) / r;
+        const int g = kWave / l;
+        if (g * R > G * r) {  // nt g / r > nt G / R
+            R = r;
+            L = l;
+            G = g;
+        }
+    }
+}
+
+// Interactions of one staged chunk for a lane's R targets: sources g, g + G, ...
+template <typename T, bool SAFE, int R>
+__device__ __forceinline__ void consume(const typename Vec4<T>::type* stage, int g, int G, int cp, const T* tx,
+                                        const T* ty, const T* tz, T eps2, T* sx, T* sy, T* sz) {
+    constexpr int U = (R >= 4) ? 1 : 4 / R;
+    const int step = G * U;
+    const int cmain = cp / step * step;
+    int k = g;
+    for (; k < cmain; k += step) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const typename Vec4<T>::type v = stage[k + u * G];
+#pragma unroll
+            for (int r = 0; r < R; ++r) interact<T, SAFE>(v, tx[r], ty[r], tz[r], eps2, sx[r], sy[r], sz[r]);
+        }
+    }
+    for (; k < cp; k += G) {
+        const typename Vec4<T>::type v = stage[k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) interact<T, SAFE>(v, tx[r], ty[r], tz[r], eps2, sx[r], sy[r], sz[r]);
+    }
+}
+
 template <typename T, bool SAFE>
 __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ it_leaf,
                                                     const uint32_t* __restrict__ it_q0,
@@ -97,12 +143,25 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
 
     for (int32_t tc = 0; tc < na; tc += kWave) {
         const int nt = (na - tc) < kWave ? (na - tc) : kWave;
-        const int G = kWave / nt;
-        const int tl = lane % nt;
-        const int g = lane / nt;
+        int R, L, G;
+        chunk_layout(nt, R, L, G);
+        const int l = lane % L;
+        const int g = lane / L;
         const bool act = g < G;
-        const V4 me = P[fa + tc + tl];
-        double ax = 0.0, ay = 0.0, az = 0.0;
+        // the lane's targets l R + r; slots past nt repeat a valid target and are dropped
+        T tx[RMAX], ty[RMAX], tz[RMAX];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            int ti = l * R + r;
+            ti = ti < nt ? ti : nt - 1;
+            const V4 me = P[fa + tc + ti];
+            tx[r] = me.x;
+            ty[r] = me.y;
+            tz[r] = me.z;
+        }
+        double ax[RMAX], ay[RMAX], az[RMAX];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) ax[r] = ay[r] = az[r] = 0.0;
 
         for (uint32_t qb = q0; qb < q1; qb += kWave) {
             // one list entry per lane: source leaf, its range and its offset
@@ -151,46 +210,58 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                         stage[lane + kWave * k] = w;
                     }
                 }
-                // pad to a multiple of G, then run: replica g takes g, g+G, ...
+                // pad to a multiple of G, then run: group g takes g, g+G, ...
                 const int cp = (cnt + G - 1) / G * G;
                 if (cnt + lane < cp) stage[cnt + lane] = pad;
                 __syncthreads();
-                T sx = T(0), sy = T(0), sz = T(0);
-                if (act) {
-                    const int step = G * UNR;
-                    const int cmain = cp / step * step;
-                    int k = g;
-                    for (; k < cmain; k += step) {
+                T sx[RMAX], sy[RMAX], sz[RMAX];
 #pragma unroll
-                        for (int u = 0; u < UNR; ++u)
-                            interact<T, SAFE>(stage[k + u * G], me.x, me.y, me.z, eps2, sx, sy, sz);
+                for (int r = 0; r < RMAX; ++r) sx[r] = sy[r] = sz[r] = T(0);
+                if (act) {
+                    switch (R) {
+                        case 1: consume<T, SAFE, 1>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz); break;
+                        case 2: consume<T, SAFE, 2>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz); break;
+                        case 3: consume<T, SAFE, 3>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz); break;
+                        default: consume<T, SAFE, 4>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz); break;
                     }
-                    for (; k < cp; k += G) interact<T, SAFE>(stage[k], me.x, me.y, me.z, eps2, sx, sy, sz);
                 }
-                ax += (double)sx;
-                ay += (double)sy;
-                az += (double)sz;
+#pragma unroll
+                for (int r = 0; r < RMAX; ++r) {
+                    ax[r] += (double)sx[r];
+                    ay[r] += (double)sy[r];
+                    az[r] += (double)sz[r];
+                }
                 __syncthreads();
             }
         }
 
-        red[0][lane] = ax;
-        red[1][lane] = ay;
-        red[2][lane] = az;
-        __syncthreads();
-        if (lane < nt) {
-            double sx = 0.0, sy = 0.0, sz = 0.0;
-            for (int r = 0; r < G; ++r) {
-                sx += red[0][r * nt + lane];
-                sy += red[1][r * nt + lane];
-                sz += red[2][r * nt + lane];
+        // target t = l R + r sits in slot r of lanes l, l + L, ..., one per
+        // group; slot by slot, through LDS
+        const int tl = lane / R, tr = lane % R;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < R) {
+                red[0][lane] = ax[r];
+                red[1][lane] = ay[r];
+                red[2][lane] = az[r];
+                __syncthreads();
+                if (lane < nt && tr == r) {
+                    for (int q = 0; q < G; ++q) {
+                        fx += red[0][q * L + tl];
+                        fy += red[1][q * L + tl];
+                        fz += red[2][q * L + tl];
+                    }
+                }
+                __syncthreads();
             }
-            const int64_t j = (int64_t)(tc + lane);
-            out[3 * j] = sx;
-            out[3 * j + 1] = sy;
-            out[3 * j + 2] = sz;
         }
-        __syncthreads();
+        if (lane < nt) {
+            const int64_t j = (int64_t)(tc + lane);
+            out[3 * j] = fx;
+            out[3 * j + 1] = fy;
+            out[3 * j + 2] = fz;
+        }
     }
 }
 
