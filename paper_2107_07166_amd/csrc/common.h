@@ -86,7 +86,7 @@ struct Tree {
     DevBuf keys, keys2;        // uint64 Morton keys
     DevBuf perm, perm2;        // int32 sorted position -> original index
     DevBuf lvlb;               // uint8 level at which a key boundary appears before position j
-    DevBuf owner, flags;       // int32 scratch for the level-by-level octree build
+    DevBuf owner, flags;       // octree-build scratch (window levels and leaf levels; counts and flags)
     DevBuf Xm;                 // double4 (x, y, z, m)
     DevBuf leaf_of;            // int32 leaf node of each sorted position
     DevBuf src4;               // float4/double4 (x, y, z relative to the leaf centre of mass, m)

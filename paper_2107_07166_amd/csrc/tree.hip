@@ -119,8 +119,7 @@ __global__ __launch_bounds__(TB) void gather_kernel(const double* __restrict__ p
                                                     const double* __restrict__ mass,
                                                     const uint64_t* __restrict__ keys,
                                                     const int32_t* __restrict__ perm, int64_t n,
-                                                    double4* __restrict__ Xm, uint8_t* __restrict__ lvlb,
-                                                    int32_t* __restrict__ owner) {
+                                                    double4* __restrict__ Xm, uint8_t* __restrict__ lvlb) {
     const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (j >= n) return;
     const int64_t a = perm[j];
@@ -131,7 +130,6 @@ __global__ __launch_bounds__(TB) void gather_kernel(const double* __restrict__ p
         lb = (x == 0) ? (uint8_t)(kLevels + 1) : (uint8_t)(kLevels - (63 - __clzll((long long)x)) / 3);
     }
     lvlb[j] = lb;
-    owner[j] = 0;
 }
 
 struct NodeArrays {
@@ -144,67 +142,223 @@ struct NodeArrays {
     int32_t* parent;
 };
 
-__global__ void root_kernel(NodeArrays nd, int32_t n) {
-    nd.level[0] = 0;
-    nd.prefix[0] = 0;
-    nd.first[0] = 0;
-    nd.count[0] = n;
-    nd.child_first[0] = -1;
-    nd.nchild[0] = 0;
-    nd.parent[0] = -1;
+// ---- octree from the sorted keys, all levels at once -------------------------
+// With the split rule "count > n_leaf and level < 21", a particle's leaf level
+// lambda(j) is one more than the deepest level at which its cell holds more
+// than n_leaf particles (capped at 21), and that happens exactly when some
+// window of n_leaf + 1 consecutive sorted keys around j shares the prefix of
+// that level.  Position j then starts a node at every level l with
+// lvlb[j] <= l <= lambda(j) (l >= 1; the root is node 0).  Node ids are level
+// major and in position order inside a level, so an id is the level's first
+// id plus the number of node starts at that level before j: per-level counts
+// per block, scanned over blocks, plus wave ballots inside the block.
+constexpr int NSLOT = kLevels + 2;  // levels 0..21 and a slot for the leaf count
+constexpr int kMaxLeafWindow = 4096;
+
+// cl[i] = deepest level shared by keys[i] and keys[i + n_leaf] (21 if equal).
+__global__ __launch_bounds__(TB) void window_level_kernel(const uint64_t* __restrict__ keys, int64_t nw, int n_leaf,
+                                                          int8_t* __restrict__ cl) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= nw) return;
+    const uint64_t x = keys[i] ^ keys[i + n_leaf];
+    cl[i] = (x == 0) ? (int8_t)kLevels : (int8_t)(kLevels - (63 - __clzll((long long)x)) / 3 - 1);
 }
 
-// Level l: which sorted positions start a child of a node that splits.
-__global__ __launch_bounds__(TB) void level_flag_kernel(NodeArrays nd, int64_t n, int lvl, int n_leaf,
-                                                        const uint8_t* __restrict__ lvlb,
-                                                        int32_t* __restrict__ owner,
-                                                        int32_t* __restrict__ leaf_of,
-                                                        uint32_t* __restrict__ flag) {
-    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (j >= n) return;
-    const int32_t o = owner[j];
-    uint32_t f = 0;
-    if (o >= 0) {
-        if (nd.count[o] > n_leaf && lvl < kLevels) {
-            f = (j == nd.first[o] || lvlb[j] == lvl + 1) ? 1u : 0u;
-        } else {
-            leaf_of[j] = o;
-            owner[j] = -1;
+// lambda(j) from the largest cl over the n_leaf + 1 windows that contain j
+// (a sparse-table maximum in LDS), and per-level counts of node starts and of
+// leaf starts for the block.
+__global__ __launch_bounds__(TB) void leaf_level_kernel(const int8_t* __restrict__ cl, int64_t n, int n_leaf,
+                                                        const uint8_t* __restrict__ lvlb, uint8_t* __restrict__ lam,
+                                                        uint32_t* __restrict__ cnt, int64_t nblk) {
+    constexpr int VMAX = (TB + kMaxLeafWindow + TB - 1) / TB;
+    __shared__ int8_t m[TB + kMaxLeafWindow];
+    __shared__ uint32_t wc[TB / kWave][NSLOT];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int64_t j0 = (int64_t)blockIdx.x * TB;
+    const int64_t nw = n - n_leaf;
+    const int TL = TB + n_leaf;
+    for (int t = tid; t < TL; t += TB) {
+        const int64_t i = j0 - n_leaf + t;
+        m[t] = (i >= 0 && i < nw) ? cl[i] : (int8_t)-1;
+    }
+    __syncthreads();
+    const int w = n_leaf + 1;
+    int span = 1;
+    while (2 * span <= w) {
+        int8_t v[VMAX];
+#pragma unroll
+        for (int q = 0; q < VMAX; ++q) {
+            const int t = tid + q * TB;
+            if (t < TL) {
+                const int8_t x = m[t], y = (t + span < TL) ? m[t + span] : (int8_t)-1;
+                v[q] = x > y ? x : y;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < VMAX; ++q) {
+            const int t = tid + q * TB;
+            if (t < TL) m[t] = v[q];
+        }
+        __syncthreads();
+        span *= 2;
+    }
+    const int64_t j = j0 + tid;
+    const bool valid = j < n;
+    int a = 99, b = 0;
+    if (valid) {
+        // windows [tid, tid + w) of the tile; m[t] covers [t, t + span)
+        const int8_t x = m[tid], y = m[tid + w - span];
+        const int bd = x > y ? x : y;
+        b = bd < 0 ? 0 : (bd + 1 < kLevels ? bd + 1 : kLevels);
+        lam[j] = (uint8_t)b;
+        a = lvlb[j] > 1 ? lvlb[j] : 1;
+    }
+    for (int l = 1; l <= kLevels; ++l) {
+        const unsigned long long bl = __ballot(a <= l && l <= b);
+        if (lane == 0) wc[wv][l] = (uint32_t)__popcll(bl);
+    }
+    const unsigned long long leaf = __ballot(a <= b);
+    if (lane == 0) {
+        wc[wv][0] = 0u;
+        wc[wv][NSLOT - 1] = (uint32_t)__popcll(leaf);
+    }
+    __syncthreads();
+    if (tid < NSLOT) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < TB / kWave; ++q) c += wc[q][tid];
+        cnt[(int64_t)tid * nblk + blockIdx.x] = c;
+    }
+}
+
+// Exclusive scan over the blocks of one slot's counts (one block per slot).
+__global__ __launch_bounds__(TB) void slot_scan_kernel(uint32_t* __restrict__ cnt, int64_t nblk,
+                                                       uint32_t* __restrict__ tot) {
+    __shared__ uint32_t sh[TB];
+    uint32_t* c = cnt + (int64_t)blockIdx.x * nblk;
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < nblk; c0 += TB) {
+        const int64_t i = c0 + threadIdx.x;
+        const uint32_t x = (i < nblk) ? c[i] : 0u;
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int d = 1; d < TB; d <<= 1) {
+            const uint32_t y = (threadIdx.x >= (unsigned)d) ? sh[threadIdx.x - d] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < nblk) c[i] = carry + sh[threadIdx.x] - x;
+        const uint32_t last = sh[TB - 1];
+        __syncthreads();
+        carry += last;
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// Level boundaries and sizes of the octree (read back by the host once).
+struct TreeHeader {
+    int64_t LB[kLevels + 2];  // first node id of levels 0..21, then the node count
+    int64_t max_level, n_nodes, n_leaves;
+};
+
+__global__ void tree_header_kernel(const uint32_t* __restrict__ tot, TreeHeader* __restrict__ h) {
+    if (threadIdx.x != 0) return;
+    h->LB[0] = 0;
+    h->LB[1] = 1;
+    int64_t ml = 0;
+    for (int l = 1; l <= kLevels; ++l) {
+        h->LB[l + 1] = h->LB[l] + tot[l];
+        if (tot[l] > 0) ml = l;
+    }
+    h->max_level = ml;
+    h->n_nodes = h->LB[kLevels + 1];
+    h->n_leaves = (int64_t)tot[NSLOT - 1] + (ml == 0 ? 1 : 0);
+}
+
+__global__ __launch_bounds__(TB) void node_create_kernel(NodeArrays nd, int64_t n, const uint64_t* __restrict__ keys,
+                                                         const uint8_t* __restrict__ lvlb,
+                                                         const uint8_t* __restrict__ lam,
+                                                         const uint32_t* __restrict__ boff, int64_t nblk,
+                                                         const TreeHeader* __restrict__ h,
+                                                         int32_t* __restrict__ leaf_of) {
+    __shared__ unsigned long long bal[TB / kWave][NSLOT];
+    __shared__ uint32_t woff[TB / kWave][NSLOT];
+    __shared__ int64_t sLB[kLevels + 2];
+    __shared__ uint32_t sboff[NSLOT];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int64_t j = (int64_t)blockIdx.x * TB + tid;
+    const bool valid = j < n;
+    const int a = valid ? (lvlb[j] > 1 ? (int)lvlb[j] : 1) : 99;
+    const int b = valid ? (int)lam[j] : 0;
+    for (int l = 1; l <= kLevels; ++l) {
+        const unsigned long long bl = __ballot(a <= l && l <= b);
+        if (lane == 0) bal[wv][l] = bl;
+    }
+    if (tid < kLevels + 2) sLB[tid] = h->LB[tid];
+    if (tid >= 1 && tid <= kLevels) sboff[tid] = boff[(int64_t)tid * nblk + blockIdx.x];
+    __syncthreads();
+    if (tid >= 1 && tid <= kLevels) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < TB / kWave; ++q) {
+            woff[q][tid] = run;
+            run += (uint32_t)__popcll(bal[q][tid]);
         }
     }
-    flag[j] = f;
-}
-
-__global__ __launch_bounds__(TB) void level_create_kernel(NodeArrays nd, int64_t n, int lvl, int32_t le,
-                                                          const uint64_t* __restrict__ keys,
-                                                          const uint32_t* __restrict__ flag,
-                                                          const uint32_t* __restrict__ excl,
-                                                          int32_t* __restrict__ owner) {
-    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (j >= n) return;
-    const int32_t o = owner[j];
-    if (o < 0) return;
-    const int32_t c = le + (int32_t)(excl[j] + flag[j]) - 1;
-    if (flag[j]) {
-        nd.level[c] = lvl + 1;
-        nd.prefix[c] = keys[j] >> (3 * (kLevels - (lvl + 1)));
-        nd.first[c] = (int32_t)j;
-        nd.parent[c] = o;
-        nd.child_first[c] = -1;
-        nd.nchild[c] = 0;
+    __syncthreads();
+    if (!valid) return;
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    auto rank = [&](int l) -> int64_t {
+        return (int64_t)sboff[l] + woff[wv][l] + (uint32_t)__popcll(bal[wv][l] & lt);
+    };
+    auto incl = [&](int l) -> int64_t {
+        if (l == 0) return 1;
+        return rank(l) + ((a <= l && l <= b) ? 1 : 0);
+    };
+    leaf_of[j] = (b == 0) ? 0 : (int32_t)(sLB[b] + incl(b) - 1);
+    if (j == 0) {
+        nd.level[0] = 0;
+        nd.prefix[0] = 0;
+        nd.first[0] = 0;
+        nd.count[0] = (int32_t)n;
+        nd.parent[0] = -1;
+        nd.nchild[0] = 0;
+        nd.child_first[0] = (b >= 1) ? (int32_t)(sLB[1] + rank(1)) : -1;
     }
-    owner[j] = c;
+    for (int l = a; l <= b; ++l) {
+        const int64_t id = sLB[l] + rank(l);
+        nd.level[id] = l;
+        nd.prefix[id] = keys[j] >> (3 * (kLevels - l));
+        nd.first[id] = (int32_t)j;
+        nd.count[id] = 0;
+        nd.nchild[id] = 0;
+        nd.parent[id] = (l == 1) ? 0 : (int32_t)(sLB[l - 1] + incl(l - 1) - 1);
+        nd.child_first[id] = (l + 1 <= b) ? (int32_t)(sLB[l + 1] + rank(l + 1)) : -1;
+    }
 }
 
-__global__ __launch_bounds__(TB) void level_finish_kernel(NodeArrays nd, int32_t le, int32_t cnt) {
-    const int32_t i = blockIdx.x * TB + threadIdx.x;
-    if (i >= cnt) return;
-    const int32_t c = le + i;
+// Particle counts (a node ends where the next node of its level starts if
+// that node has the same parent, else where its parent ends) and child counts
+// (written by the last child).
+__global__ __launch_bounds__(TB) void node_finish_kernel(NodeArrays nd, int64_t nn, int64_t n,
+                                                         const TreeHeader* __restrict__ h) {
+    const int64_t c = 1 + (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (c >= nn) return;
+    const int l = nd.level[c];
     const int32_t P = nd.parent[c];
-    const int32_t end = (i + 1 < cnt && nd.parent[c + 1] == P) ? nd.first[c + 1] : nd.first[P] + nd.count[P];
-    nd.count[c] = end - nd.first[c];
-    if (nd.first[c] == nd.first[P]) nd.child_first[P] = c;
-    atomicAdd(&nd.nchild[P], 1);
+    int64_t x = c, end = n;
+    for (int lx = l; lx >= 1; --lx) {
+        const int64_t nx = x + 1;
+        if (nx < h->LB[lx + 1] && nd.parent[nx] == nd.parent[x]) {
+            end = nd.first[nx];
+            break;
+        }
+        x = nd.parent[x];
+    }
+    nd.count[c] = (int32_t)(end - nd.first[c]);
+    if (c + 1 >= h->LB[l + 1] || nd.parent[c + 1] != P) nd.nchild[P] = (int32_t)(c - nd.child_first[P] + 1);
 }
 
 __global__ __launch_bounds__(TB) void leaf_flag_kernel(const int32_t* __restrict__ nchild, int64_t nn,
@@ -419,69 +573,64 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     // sorted particles, boundary levels
     t.Xm.ensure(ctx, un * 32);
     t.lvlb.ensure(ctx, un);
-    t.owner.ensure(ctx, un * 4);
+    t.owner.ensure(ctx, un * 2);
     t.leaf_of.ensure(ctx, un * 4);
-    t.flags.ensure(ctx, un * 4 * 2);
     hipLaunchKernelGGL(gather_kernel, dim3(grid(n)), dim3(TB), 0, s, pos, mass, t.keys.as<uint64_t>(),
-                       t.perm.as<int32_t>(), n, t.Xm.as<double4>(), t.lvlb.as<uint8_t>(), t.owner.as<int32_t>());
+                       t.perm.as<int32_t>(), n, t.Xm.as<double4>(), t.lvlb.as<uint8_t>());
     TFMM_LAUNCHED();
 
-    // octree, level by level
-    int64_t cap = std::max<int64_t>(1024, 4 * n / std::max(1, t.n_leaf) + 64);
-    ensure_nodes(t, cap, 0, s);
-    NodeArrays nd = node_arrays(t);
-    hipLaunchKernelGGL(root_kernel, dim3(1), dim3(1), 0, s, nd, (int32_t)n);
-    TFMM_LAUNCHED();
-    uint32_t* flag = t.flags.as<uint32_t>();
-    uint32_t* excl = flag + n;
-    t.scratch2.ensure(ctx, 256);
-    uint32_t* total = t.scratch2.as<uint32_t>();
-    void* scan_scr = t.scratch.p;
-    t.level_begin.assign(1, 0);
-    int64_t lb = 0, le = 1;
-    int lvl = 0;
-    for (;; ++lvl) {
-        t.level_begin.push_back(le);
-        hipLaunchKernelGGL(level_flag_kernel, dim3(grid(n)), dim3(TB), 0, s, nd, n, lvl, t.n_leaf,
-                           t.lvlb.as<uint8_t>(), t.owner.as<int32_t>(), t.leaf_of.as<int32_t>(), flag);
+    // octree: leaf level of every particle, node starts per level, node table
+    const int64_t nblk = cdiv(n, TB);
+    const int64_t nw = n - t.n_leaf;  // windows of n_leaf + 1 consecutive keys
+    // cl (int8, n) and lambda (uint8, n) share the owner buffer
+    int8_t* cl = reinterpret_cast<int8_t*>(t.owner.as<int32_t>());
+    uint8_t* lam = reinterpret_cast<uint8_t*>(cl + n);
+    t.flags.ensure(ctx, std::max<size_t>(un * 8, (size_t)(NSLOT * nblk + NSLOT) * 4));
+    uint32_t* cnt = t.flags.as<uint32_t>();
+    uint32_t* tot = cnt + NSLOT * nblk;
+    t.scratch2.ensure(ctx, sizeof(TreeHeader) + 256);
+    TreeHeader* hdr = t.scratch2.as<TreeHeader>();
+    if (nw > 0) {
+        hipLaunchKernelGGL(window_level_kernel, dim3(grid(nw)), dim3(TB), 0, s, (const uint64_t*)t.keys.as<uint64_t>(),
+                           nw, t.n_leaf, cl);
         TFMM_LAUNCHED();
-        if (lvl >= kLevels) break;
-        exclusive_scan_u32(flag, excl, n, scan_scr, total, s);
-        const uint32_t T = read_back(ctx, total, s);
-        if (T == 0) break;
-        if (le + (int64_t)T > cap) {
-            cap = std::max<int64_t>(2 * cap, le + T);
-            ensure_nodes(t, cap, le, s);
-            nd = node_arrays(t);
-        }
-        hipLaunchKernelGGL(level_create_kernel, dim3(grid(n)), dim3(TB), 0, s, nd, n, lvl, (int32_t)le,
-                           t.keys.as<uint64_t>(), (const uint32_t*)flag, (const uint32_t*)excl,
-                           t.owner.as<int32_t>());
-        TFMM_LAUNCHED();
-        hipLaunchKernelGGL(level_finish_kernel, dim3(grid(T)), dim3(TB), 0, s, nd, (int32_t)le, (int32_t)T);
-        TFMM_LAUNCHED();
-        lb = le;
-        le += T;
     }
-    (void)lb;
-    t.n_nodes = le;
-    t.max_level = lvl;
-    // level_begin holds the start of levels 0..max_level and the end
-    t.level_begin.resize((size_t)t.max_level + 2);
-    t.level_begin[(size_t)t.max_level + 1] = le;
+    hipLaunchKernelGGL(leaf_level_kernel, dim3((unsigned)nblk), dim3(TB), 0, s, (const int8_t*)cl, n, t.n_leaf,
+                       (const uint8_t*)t.lvlb.as<uint8_t>(), lam, cnt, nblk);
+    TFMM_LAUNCHED();
+    hipLaunchKernelGGL(slot_scan_kernel, dim3(NSLOT), dim3(TB), 0, s, cnt, nblk, tot);
+    TFMM_LAUNCHED();
+    hipLaunchKernelGGL(tree_header_kernel, dim3(1), dim3(kWave), 0, s, (const uint32_t*)tot, hdr);
+    TFMM_LAUNCHED();
+    const TreeHeader H = read_back(ctx, (const TreeHeader*)hdr, s);
+    t.n_nodes = H.n_nodes;
+    t.max_level = (int)H.max_level;
+    t.n_leaves = H.n_leaves;
+    t.level_begin.assign((size_t)t.max_level + 2, 0);
+    for (int l = 0; l <= t.max_level + 1; ++l) t.level_begin[(size_t)l] = H.LB[l];
     const int64_t nn = t.n_nodes;
+    ensure_nodes(t, std::max<int64_t>(nn, 1), 0, s);
+    NodeArrays nd = node_arrays(t);
+    hipLaunchKernelGGL(node_create_kernel, dim3((unsigned)nblk), dim3(TB), 0, s, nd, n,
+                       (const uint64_t*)t.keys.as<uint64_t>(), (const uint8_t*)t.lvlb.as<uint8_t>(),
+                       (const uint8_t*)lam, (const uint32_t*)cnt, nblk, (const TreeHeader*)hdr,
+                       t.leaf_of.as<int32_t>());
+    TFMM_LAUNCHED();
+    if (nn > 1) {
+        hipLaunchKernelGGL(node_finish_kernel, dim3(grid(nn - 1)), dim3(TB), 0, s, nd, nn, n, (const TreeHeader*)hdr);
+        TFMM_LAUNCHED();
+    }
 
-    // leaves
+    // leaves, in node order
     t.flags.ensure(ctx, (size_t)std::max<int64_t>(n, nn) * 4 * 2);
     t.scratch.ensure(ctx, scan_scratch_bytes(std::max<int64_t>(n, nn)) + 256);
-    scan_scr = t.scratch.p;
-    flag = t.flags.as<uint32_t>();
-    excl = flag + std::max<int64_t>(n, nn);
+    uint32_t* flag = t.flags.as<uint32_t>();
+    uint32_t* excl = flag + std::max<int64_t>(n, nn);
+    uint32_t* total = reinterpret_cast<uint32_t*>(t.scratch2.as<char>() + sizeof(TreeHeader));
     hipLaunchKernelGGL(leaf_flag_kernel, dim3(grid(nn)), dim3(TB), 0, s, nd.nchild, nn, flag);
     TFMM_LAUNCHED();
-    exclusive_scan_u32(flag, excl, nn, scan_scr, total, s);
-    t.n_leaves = read_back(ctx, total, s);
-    t.leaves.ensure(ctx, (size_t)t.n_leaves * 4);
+    exclusive_scan_u32(flag, excl, nn, t.scratch.p, total, s);
+    t.leaves.ensure(ctx, (size_t)std::max<int64_t>(t.n_leaves, 1) * 4);
     hipLaunchKernelGGL(leaf_compact_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)flag,
                        (const uint32_t*)excl, nn, t.leaves.as<int32_t>());
     TFMM_LAUNCHED();
