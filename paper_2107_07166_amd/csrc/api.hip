@@ -148,6 +148,8 @@ int tfmm_ctx_create(int device, size_t hbm_budget_bytes, tfmm_ctx** out) {
         set_device(c);
         c->pinned_bytes = 1 << 16;
         TFMM_HIP(hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault));
+        TFMM_HIP(hipMalloc(reinterpret_cast<void**>(&c->dev_err), 256));
+        TFMM_HIP(hipMemset(c->dev_err, 0, 256));
     });
     if (rc != TFMM_OK) {
         delete c;
@@ -166,6 +168,7 @@ int tfmm_ctx_destroy(tfmm_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->dev_err) (void)hipFree(ctx->dev_err);
     delete ctx;
     return TFMM_OK;
 }

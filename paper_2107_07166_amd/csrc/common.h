@@ -62,6 +62,7 @@ struct Ctx {
     bool broken = false;
     void* pinned = nullptr;  // small pinned host staging area
     size_t pinned_bytes = 0;
+    uint32_t* dev_err = nullptr;  // device word set by a kernel whose bounded wait ran out
     int live_trees = 0;
     void* alloc(size_t bytes);
     void free(void* p, size_t bytes);
@@ -145,20 +146,36 @@ struct U3 {
     uint32_t a, b, c;
 };
 size_t scan_scratch_bytes(int64_t n);
-// Exclusive scan of n values; writes the total to *total_dev (device).
+// Exclusive scan of n values (in == out allowed); writes the total to
+// *total_dev (device).  err: the context's device error word.
 void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
-                        uint32_t* total_dev, hipStream_t s);
-void exclusive_scan_u3(const U3* in, U3* out, int64_t n, void* scratch, U3* total_dev,
-                       hipStream_t s);
+                        uint32_t* total_dev, uint32_t* err, hipStream_t s);
 
 // ---- radix sort (sort.hip) ----------------------------------------------------
-size_t sort_scratch_bytes(int64_t n);
+size_t sort_scratch_bytes(int64_t n, int bits);
 // Stable LSD sort of (key, value) by the low `bits` bits of key; result ends in
 // keys/vals (alt buffers are scratch of the same size).
 void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
-                    int64_t n, int bits, void* scratch, hipStream_t s);
+                    int64_t n, int bits, void* scratch, uint32_t* err, hipStream_t s);
 void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
-                    int64_t n, int bits, void* scratch, hipStream_t s);
+                    int64_t n, int bits, void* scratch, uint32_t* err, hipStream_t s);
+
+// Copies one device value to the host together with the context's device
+// error word, with a single synchronisation; fails if a kernel set the word.
+template <typename V>
+V read_back_checked(Ctx* ctx, const V* dev, hipStream_t s) {
+    static_assert(sizeof(V) <= 32768, "read-back value too large");
+    char* h = static_cast<char*>(ctx->pinned);
+    TFMM_HIP(hipMemcpyAsync(h, dev, sizeof(V), hipMemcpyDeviceToHost, s));
+    TFMM_HIP(hipMemcpyAsync(h + 32768, ctx->dev_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TFMM_HIP(hipStreamSynchronize(s));
+    V v;
+    std::memcpy(&v, h, sizeof(V));
+    uint32_t e;
+    std::memcpy(&e, h + 32768, sizeof(e));
+    if (e != 0u) fail(TFMM_EDEVICE, "a device-side wait ran past its bound (internal error); results are invalid");
+    return v;
+}
 
 // ---- phases ---------------------------------------------------------------
 void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s);

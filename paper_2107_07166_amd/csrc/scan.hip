@@ -1,146 +1,151 @@
-// Device-wide exclusive prefix sums (reduce / scan-of-block-sums / down-sweep).
+// Device-wide exclusive prefix sums of uint32 values, one pass.
+//
 // Used for stream compaction in the octree build and the tree walk, where the
 // scan keeps the compacted order identical to the input order (deterministic).
+// Tiles of 4096 values take their index from an atomic ticket, scan locally
+// (coalesced loads transposed through LDS, 16 consecutive values per thread),
+// publish their total, and add the totals of earlier tiles found by looking
+// back over the published words (decoupled look-back, one wavefront reading 64
+// earlier words at a time; a tile publishes before it waits and only waits
+// for tiles already running).  Each wait is bounded:
+// past kSpinLimit polls the device error word is set and the kernel ends.
+// In-place use (in == out) is allowed.
 #include "common.h"
 
 namespace tfmm {
 namespace {
 
 constexpr int SB = 256;            // threads per block
-constexpr int SI = 8;              // items per thread
-constexpr int STILE = SB * SI;     // items per block
+constexpr int SI = 16;             // values per thread
+constexpr int STILE = SB * SI;     // values per tile
+constexpr uint32_t kSpinLimit = 1u << 20;
 
-__device__ __forceinline__ U3 operator+(U3 x, U3 y) { return {x.a + y.a, x.b + y.b, x.c + y.c}; }
-__device__ __forceinline__ U3 vsub(U3 x, U3 y) { return {x.a - y.a, x.b - y.b, x.c - y.c}; }
-__device__ __forceinline__ uint32_t vsub(uint32_t x, uint32_t y) { return x - y; }
+constexpr unsigned long long kFlagOwn = 1ull << 62;
+constexpr unsigned long long kFlagTotal = 2ull << 62;
+constexpr unsigned long long kValMask = (1ull << 62) - 1;
 
-template <typename V> __device__ __forceinline__ V vzero();
-template <> __device__ __forceinline__ uint32_t vzero<uint32_t>() { return 0u; }
-template <> __device__ __forceinline__ U3 vzero<U3>() { return {0u, 0u, 0u}; }
+__device__ __forceinline__ int pad(int i) { return i + (i >> 5); }
 
-__device__ __forceinline__ uint32_t shfl_up(uint32_t v, int d) { return __shfl_up(v, d, kWave); }
-__device__ __forceinline__ U3 shfl_up(U3 v, int d) {
-    return {(uint32_t)__shfl_up(v.a, d, kWave), (uint32_t)__shfl_up(v.b, d, kWave),
-            (uint32_t)__shfl_up(v.c, d, kWave)};
+__global__ __launch_bounds__(SB) void scan_zero_kernel(unsigned long long* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * SB + threadIdx.x; i < n; i += (int64_t)gridDim.x * SB) p[i] = 0ull;
 }
 
-// Inclusive scan over the block of one value per thread; returns the inclusive
-// prefix and writes the block total.
-template <typename V>
-__device__ V block_inclusive(V v, V& total, V* wsum) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
+__global__ __launch_bounds__(SB) void scan_lookback_kernel(const uint32_t* in, uint32_t* out, int64_t n,
+                                                           unsigned long long* __restrict__ status,
+                                                           uint32_t* __restrict__ ticket,
+                                                           uint32_t* __restrict__ total, uint32_t* __restrict__ err) {
+    __shared__ uint32_t sv[STILE + STILE / 32];
+    __shared__ uint32_t wsum[SB / kWave];
+    __shared__ unsigned long long s_prefix;
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t t0 = tile * STILE;
+#pragma unroll
+    for (int r = 0; r < SI; ++r) {
+        const int64_t i = t0 + r * SB + tid;
+        sv[pad(r * SB + tid)] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t x[SI];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < SI; ++k) {
+        x[k] = sv[pad(tid * SI + k)];
+        sum += x[k];
+    }
+    // block scan of the per-thread sums
+    uint32_t incl = sum;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
-        V u = shfl_up(v, d);
-        if (lane >= d) v = v + u;
+        const uint32_t u = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += u;
     }
-    if (lane == kWave - 1) wsum[w] = v;
+    if (lane == kWave - 1) wsum[wv] = incl;
     __syncthreads();
-    V off = vzero<V>();
-    V tot = vzero<V>();
+    uint32_t woff = 0, tile_total = 0;
 #pragma unroll
-    for (int i = 0; i < SB / kWave; ++i) {
-        V x = wsum[i];
-        if (i < w) off = off + x;
-        tot = tot + x;
+    for (int q = 0; q < SB / kWave; ++q) {
+        if (q < wv) woff += wsum[q];
+        tile_total += wsum[q];
+    }
+    const uint32_t texcl = woff + incl - sum;
+
+    // look-back by the first wavefront: lane k reads the word of tile - 1 - k
+    if (wv == 0) {
+        unsigned long long* st = status + tile;
+        if (lane == 0)
+            __hip_atomic_store(st, (tile == 0 ? kFlagTotal : kFlagOwn) | (unsigned long long)tile_total,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long excl = 0;
+        int64_t j0 = tile - 1;
+        uint32_t spins = 0;
+        while (j0 >= 0) {
+            const int64_t j = j0 - lane;
+            // words before the first tile count as a zero running total
+            const unsigned long long y =
+                j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kFlagTotal;
+            const unsigned long long flag = y & ~kValMask;
+            const unsigned long long totm = __ballot(flag == kFlagTotal);
+            const unsigned long long zerom = __ballot(flag == 0ull);
+            const int first_total = totm ? __ffsll((long long)totm) - 1 : kWave;
+            const unsigned long long need = first_total >= kWave - 1 ? ~0ull : ((2ull << first_total) - 1ull);
+            if (zerom & need) {
+                if (++spins > kSpinLimit) {
+                    if (lane == 0) atomicOr(err, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            unsigned long long v = ((need >> lane) & 1ull) ? (y & kValMask) : 0ull;
+#pragma unroll
+            for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+            excl += v;
+            if (first_total < kWave) break;
+            j0 -= kWave;
+        }
+        if (lane == 0) {
+            if (tile > 0)
+                __hip_atomic_store(st, kFlagTotal | (excl + tile_total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_prefix = excl;
+            if (t0 + STILE >= n) *total = (uint32_t)(excl + tile_total);
+        }
     }
     __syncthreads();
-    total = tot;
-    return off + v;
-}
-
-template <typename V>
-__global__ __launch_bounds__(SB) void scan_reduce_kernel(const V* __restrict__ in, int64_t n,
-                                                         V* __restrict__ bsum) {
-    __shared__ V wsum[SB / kWave];
-    const int64_t base = (int64_t)blockIdx.x * STILE + (int64_t)threadIdx.x * SI;
-    V s = vzero<V>();
+    uint32_t run = (uint32_t)s_prefix + texcl;
 #pragma unroll
-    for (int i = 0; i < SI; ++i)
-        if (base + i < n) s = s + in[base + i];
-    V tot;
-    block_inclusive(s, tot, wsum);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
-// One block scans the block sums (exclusive, in place) and writes the total.
-template <typename V>
-__global__ __launch_bounds__(SB) void scan_top_kernel(V* __restrict__ bsum, int64_t nb,
-                                                      V* __restrict__ total) {
-    __shared__ V wsum[SB / kWave];
-    V carry = vzero<V>();
-    for (int64_t c0 = 0; c0 < nb; c0 += STILE) {
-        const int64_t base = c0 + (int64_t)threadIdx.x * SI;
-        V loc[SI];
-        V s = vzero<V>();
-#pragma unroll
-        for (int i = 0; i < SI; ++i) {
-            loc[i] = (base + i < nb) ? bsum[base + i] : vzero<V>();
-            s = s + loc[i];
-        }
-        V tot;
-        const V incl = block_inclusive(s, tot, wsum);
-        V start = carry + vsub(incl, s);
-#pragma unroll
-        for (int i = 0; i < SI; ++i) {
-            if (base + i < nb) bsum[base + i] = start;
-            start = start + loc[i];
-        }
-        carry = carry + tot;
+    for (int k = 0; k < SI; ++k) {
+        sv[pad(tid * SI + k)] = run;
+        run += x[k];
     }
-    if (threadIdx.x == 0) *total = carry;
-}
-
-template <typename V>
-__global__ __launch_bounds__(SB) void scan_down_kernel(const V* __restrict__ in, V* __restrict__ out,
-                                                       int64_t n, const V* __restrict__ bsum) {
-    __shared__ V wsum[SB / kWave];
-    const int64_t base = (int64_t)blockIdx.x * STILE + (int64_t)threadIdx.x * SI;
-    V loc[SI];
-    V s = vzero<V>();
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < SI; ++i) {
-        loc[i] = (base + i < n) ? in[base + i] : vzero<V>();
-        s = s + loc[i];
+    for (int r = 0; r < SI; ++r) {
+        const int64_t i = t0 + r * SB + tid;
+        if (i < n) out[i] = sv[pad(r * SB + tid)];
     }
-    V tot;
-    const V incl = block_inclusive(s, tot, wsum);
-    V start = bsum[blockIdx.x] + vsub(incl, s);
-#pragma unroll
-    for (int i = 0; i < SI; ++i) {
-        if (base + i < n) out[base + i] = start;
-        start = start + loc[i];
-    }
-}
-
-template <typename V>
-void scan_impl(const V* in, V* out, int64_t n, void* scratch, V* total, hipStream_t s) {
-    const int64_t nb = cdiv(n > 0 ? n : 1, STILE);
-    V* bsum = static_cast<V*>(scratch);
-    hipLaunchKernelGGL(scan_reduce_kernel<V>, dim3((unsigned)nb), dim3(SB), 0, s, in, n, bsum);
-    TFMM_LAUNCHED();
-    hipLaunchKernelGGL(scan_top_kernel<V>, dim3(1), dim3(SB), 0, s, bsum, nb, total);
-    TFMM_LAUNCHED();
-    hipLaunchKernelGGL(scan_down_kernel<V>, dim3((unsigned)nb), dim3(SB), 0, s, in, out, n,
-                       (const V*)bsum);
-    TFMM_LAUNCHED();
 }
 
 }  // namespace
 
-size_t scan_scratch_bytes(int64_t n) {
-    return (size_t)round_up(cdiv(n > 0 ? n : 1, STILE) * (int64_t)sizeof(U3), 256);
-}
+size_t scan_scratch_bytes(int64_t n) { return (size_t)(cdiv(n > 0 ? n : 1, STILE) + 64) * 8 + 256; }
 
-void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
-                        uint32_t* total_dev, hipStream_t s) {
-    scan_impl<uint32_t>(in, out, n, scratch, total_dev, s);
-}
-
-void exclusive_scan_u3(const U3* in, U3* out, int64_t n, void* scratch, U3* total_dev,
-                       hipStream_t s) {
-    scan_impl<U3>(in, out, n, scratch, total_dev, s);
+void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch, uint32_t* total_dev,
+                        uint32_t* err, hipStream_t s) {
+    const int64_t nb = cdiv(n > 0 ? n : 1, STILE);
+    auto* words = static_cast<unsigned long long*>(scratch);
+    uint32_t* ticket = reinterpret_cast<uint32_t*>(words);  // first 64 words: ticket
+    unsigned long long* status = words + 64;
+    const int64_t nz = 64 + nb;
+    hipLaunchKernelGGL(scan_zero_kernel, dim3((unsigned)std::min<int64_t>(1024, cdiv(nz, SB))), dim3(SB), 0, s, words,
+                       nz);
+    TFMM_LAUNCHED();
+    hipLaunchKernelGGL(scan_lookback_kernel, dim3((unsigned)nb), dim3(SB), 0, s, in, out, n, status, ticket,
+                       total_dev, err);
+    TFMM_LAUNCHED();
 }
 
 }  // namespace tfmm

@@ -1,12 +1,22 @@
 // Stable LSD radix sort of (key, int32 value) pairs, 8-bit digits.
 //
-// Per pass: a histogram kernel counts digits per 4096-key tile, a device scan
-// turns the digit-major counts into global offsets, and a scatter kernel ranks
-// every key inside its tile (wave ballots find the lanes sharing a digit, a
-// per-wave LDS counter carries ranks across rounds), stages the tile in LDS in
-// digit order and writes it out in contiguous runs.  Tile order = input order,
-// so equal keys keep their input order (stable); with the identity as initial
-// payload, ties are broken by the original index.
+// One histogram kernel counts the digits of every pass at once (the global
+// digit totals do not depend on the order of the keys).  Each pass is then a
+// single kernel over 4096-key tiles: a tile ranks its keys (wave ballots find
+// the lanes sharing a digit, a per-wave LDS counter carries ranks across
+// rounds), publishes its per-digit counts, and finds the number of keys with
+// the same digit in all earlier tiles by looking back over their published
+// counts (decoupled look-back: a tile publishes its own count before it
+// waits, and earlier tiles publish running totals, so the look-back usually
+// stops after a tile or two).  Tiles take their index from an atomic ticket,
+// so a tile only ever waits for tiles that are already running.  A status word
+// carries its own value, so relaxed device-scope atomics suffice.  The tile is
+// staged in LDS in digit order and written out in contiguous runs.  Tile
+// order = input order, so equal keys keep their input order (stable).
+//
+// Every wait is bounded: a look-back that spins past kSpinLimit polls sets a
+// device error word, which the host checks at its next read-back; the kernel
+// always runs to its end.
 #include "common.h"
 
 namespace tfmm {
@@ -15,8 +25,17 @@ namespace {
 constexpr int RB = 256;          // threads per block
 constexpr int RW = RB / kWave;   // waves per block
 constexpr int RI = 16;           // keys per lane
-constexpr int RTILE = RB * RI;   // keys per block
+constexpr int RTILE = RB * RI;   // keys per tile
 constexpr int RADIX = 256;
+constexpr int MAXP = 8;          // passes of a 64-bit key
+constexpr int kHistBlocks = 1024;
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+// Tile status word: bits 62..63 flag (0 none, 1 own count, 2 running total
+// including this tile), low 62 bits the value.
+constexpr unsigned long long kFlagOwn = 1ull << 62;
+constexpr unsigned long long kFlagTotal = 2ull << 62;
+constexpr unsigned long long kValMask = (1ull << 62) - 1;
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const int lane = threadIdx.x & (kWave - 1);
@@ -35,57 +54,97 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d) {
     return peers;
 }
 
+__global__ __launch_bounds__(RB) void zero_u64_kernel(unsigned long long* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) p[i] = 0ull;
+}
+
+// Digit totals of every pass: LDS counters per block, then global atomics.
 template <typename K>
-__global__ __launch_bounds__(RB) void radix_hist_kernel(const K* __restrict__ kin, int64_t n, int shift,
-                                                        uint32_t* __restrict__ hist, int nb) {
-    __shared__ uint32_t h[RADIX];
-    h[threadIdx.x] = 0;
+__global__ __launch_bounds__(RB) void radix_hist_all_kernel(const K* __restrict__ kin, int64_t n, int passes,
+                                                            uint32_t* __restrict__ ghist) {
+    __shared__ uint32_t h[MAXP][RADIX];
+    for (int p = 0; p < MAXP; ++p) h[p][threadIdx.x] = 0u;
     __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
-    const int64_t wbase = (int64_t)blockIdx.x * RTILE + (int64_t)w * (kWave * RI);
-    for (int r = 0; r < RI; ++r) {
-        const int64_t i = wbase + (int64_t)r * kWave + lane;
-        const bool valid = i < n;
-        const uint32_t d = valid ? (uint32_t)((kin[i] >> shift) & (RADIX - 1)) : (uint32_t)RADIX - 1;
-        const uint64_t peers = digit_peers(d) & __ballot(valid);
-        if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    constexpr int U = 4;
+    const int64_t stride = (int64_t)gridDim.x * RB * U;
+    for (int64_t base = (int64_t)blockIdx.x * RB * U; base < n; base += stride) {
+        K k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + (int64_t)u * RB + threadIdx.x;
+            k[u] = i < n ? kin[i] : (K)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + (int64_t)u * RB + threadIdx.x < n) {
+                for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(k[u] >> (8 * p)) & (RADIX - 1)], 1u);
+            }
+        }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t c = h[p][threadIdx.x];
+        if (c) atomicAdd(&ghist[p * RADIX + threadIdx.x], c);
+    }
+}
+
+// Exclusive scan of each pass's 256 digit totals (one block).
+__global__ __launch_bounds__(RB) void radix_digit_base_kernel(uint32_t* __restrict__ ghist, int passes) {
+    __shared__ uint32_t sh[RB];
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t x = ghist[p * RADIX + threadIdx.x];
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int d = 1; d < RB; d <<= 1) {
+            const uint32_t y = (threadIdx.x >= (unsigned)d) ? sh[threadIdx.x - d] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += y;
+            __syncthreads();
+        }
+        ghist[p * RADIX + threadIdx.x] = sh[threadIdx.x] - x;
+        __syncthreads();
+    }
 }
 
 template <typename K>
-__global__ __launch_bounds__(RB) void radix_scatter_kernel(const K* __restrict__ kin,
-                                                           const int32_t* __restrict__ vin,
-                                                           K* __restrict__ kout, int32_t* __restrict__ vout,
-                                                           int64_t n, int shift,
-                                                           const uint32_t* __restrict__ off, int nb) {
+__global__ __launch_bounds__(RB) void radix_pass_kernel(const K* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                        K* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
+                                                        int shift, const uint32_t* __restrict__ dbase,
+                                                        unsigned long long* __restrict__ status,
+                                                        uint32_t* __restrict__ ticket, uint32_t* __restrict__ err) {
     __shared__ uint32_t wcnt[RW][RADIX];
     __shared__ uint32_t dstart[RADIX];
-    __shared__ uint32_t gbase[RADIX];
+    __shared__ unsigned long long gbase[RADIX];
     __shared__ uint32_t wsum[RW];
     __shared__ K skeys[RTILE];
     __shared__ int32_t svals[RTILE];
+    __shared__ uint32_t s_tile;
 
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     for (int ww = 0; ww < RW; ++ww) wcnt[ww][threadIdx.x] = 0;
     __syncthreads();
+    const int64_t tile = s_tile;
 
-    const int64_t tile0 = (int64_t)blockIdx.x * RTILE;
+    const int64_t tile0 = tile * RTILE;
     const int64_t wbase = tile0 + (int64_t)w * (kWave * RI);
     K k[RI];
     int32_t v[RI];
     uint32_t rank[RI];
     uint32_t dig[RI];
-    const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < RI; ++r) {
         const int64_t i = wbase + (int64_t)r * kWave + lane;
         const bool valid = i < n;
         k[r] = valid ? kin[i] : (K)0;
         v[r] = valid ? vin[i] : 0;
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+        const int64_t i = wbase + (int64_t)r * kWave + lane;
+        const bool valid = i < n;
         const uint32_t d = valid ? (uint32_t)((k[r] >> shift) & (RADIX - 1)) : (uint32_t)RADIX - 1;
         dig[r] = d;
         const uint64_t peers = digit_peers(d);
@@ -96,7 +155,7 @@ __global__ __launch_bounds__(RB) void radix_scatter_kernel(const K* __restrict__
     }
     __syncthreads();
 
-    // per digit: exclusive offsets across waves, then the digit totals' scan
+    // per digit: exclusive offsets across waves and the tile's count
     const int d = threadIdx.x;
     uint32_t tot = 0;
     for (int ww = 0; ww < RW; ++ww) {
@@ -104,6 +163,56 @@ __global__ __launch_bounds__(RB) void radix_scatter_kernel(const K* __restrict__
         wcnt[ww][d] = tot;
         tot += c;
     }
+    // padding keys of the last tile were counted under digit 255: drop them
+    const int64_t rem = n - tile0;
+    const int valid_count = (int)(rem < RTILE ? rem : RTILE);
+    const uint32_t real = (d == RADIX - 1) ? tot - (uint32_t)(RTILE - valid_count) : tot;
+
+    // publish, look back over earlier tiles, publish the running total
+    unsigned long long* st = status + tile * RADIX;
+    unsigned long long excl = 0;
+    if (tile == 0) {
+        __hip_atomic_store(&st[d], kFlagTotal | (unsigned long long)real, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(&st[d], kFlagOwn | (unsigned long long)real, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // earlier tiles' words for this digit, kLook at a time (independent loads)
+        constexpr int kLook = 8;
+        uint32_t spins = 0;
+        int64_t j = tile - 1;
+        bool done = false;
+        while (!done && j >= 0) {
+            unsigned long long y[kLook];
+#pragma unroll
+            for (int b = 0; b < kLook; ++b)
+                y[b] = (j - b >= 0) ? __hip_atomic_load(&status[(j - b) * RADIX + d], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)
+                                    : kFlagTotal;
+            bool stalled = false;
+#pragma unroll
+            for (int b = 0; b < kLook; ++b) {
+                if (done || stalled) continue;
+                const unsigned long long flag = y[b] & ~kValMask;
+                if (flag == 0ull) {
+                    stalled = true;  // reload from tile j
+                } else {
+                    excl += y[b] & kValMask;
+                    --j;
+                    if (flag == kFlagTotal) done = true;
+                }
+            }
+            if (stalled) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __hip_atomic_store(&st[d], kFlagTotal | (excl + real), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    gbase[d] = (unsigned long long)dbase[d] + excl;
+
     uint32_t incl = tot;
 #pragma unroll
     for (int s = 1; s < kWave; s <<= 1) {
@@ -111,7 +220,6 @@ __global__ __launch_bounds__(RB) void radix_scatter_kernel(const K* __restrict__
         if (lane >= s) incl += u;
     }
     if (lane == kWave - 1) wsum[w] = incl;
-    gbase[d] = off[(int64_t)d * nb + blockIdx.x];
     __syncthreads();
     uint32_t woff = 0;
     for (int ww = 0; ww < w; ++ww) woff += wsum[ww];
@@ -126,8 +234,6 @@ __global__ __launch_bounds__(RB) void radix_scatter_kernel(const K* __restrict__
     }
     __syncthreads();
 
-    const int64_t rem = n - tile0;
-    const int valid_count = (int)(rem < RTILE ? rem : RTILE);
     for (int i = threadIdx.x; i < valid_count; i += RB) {
         const K kk = skeys[i];
         const uint32_t dd = (uint32_t)((kk >> shift) & (RADIX - 1));
@@ -137,27 +243,50 @@ __global__ __launch_bounds__(RB) void radix_scatter_kernel(const K* __restrict__
     }
 }
 
+// Scratch layout: digit bases [MAXP][RADIX] u32, tickets [MAXP] u32 (padded),
+// then the tile status words [passes][tiles][RADIX] u64.
+struct SortScratch {
+    uint32_t* dbase;
+    uint32_t* ticket;
+    unsigned long long* status;
+    int64_t zero_words;  // u64 words to clear from the start of the scratch
+};
+
+SortScratch carve(void* scratch, int64_t n, int passes) {
+    const int64_t nb = cdiv(n > 0 ? n : 1, RTILE);
+    auto* base = static_cast<unsigned long long*>(scratch);
+    SortScratch s;
+    s.dbase = reinterpret_cast<uint32_t*>(base);                          // MAXP*RADIX u32 = 1024 u64
+    s.ticket = reinterpret_cast<uint32_t*>(base + MAXP * RADIX / 2);      // 64 u64 of room
+    s.status = base + MAXP * RADIX / 2 + 64;
+    s.zero_words = MAXP * RADIX / 2 + 64 + (int64_t)passes * nb * RADIX;
+    return s;
+}
+
 template <typename K>
-void radix_sort_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int64_t n, int bits,
-                     void* scratch, hipStream_t s) {
+void radix_sort_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int64_t n, int bits, void* scratch,
+                     uint32_t* err, hipStream_t s) {
     if (n <= 1 || bits <= 0) return;
-    const int nb = (int)cdiv(n, RTILE);
-    const int64_t nh = (int64_t)RADIX * nb;
-    uint32_t* hist = static_cast<uint32_t*>(scratch);
-    uint32_t* total = hist + round_up(nh, 64);
-    void* scan_scr = total + 64;
     const int passes = (bits + 7) / 8;
+    const int nb = (int)cdiv(n, RTILE);
+    const SortScratch sc = carve(scratch, n, passes);
+    const unsigned zb = (unsigned)std::min<int64_t>(2048, cdiv(sc.zero_words, RB));
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(zb), dim3(RB), 0, s, static_cast<unsigned long long*>(scratch),
+                       sc.zero_words);
+    TFMM_LAUNCHED();
+    const unsigned hb = (unsigned)std::min<int64_t>(kHistBlocks, cdiv(n, RB * 4));
+    hipLaunchKernelGGL(radix_hist_all_kernel<K>, dim3(hb), dim3(RB), 0, s, (const K*)keys, n, passes, sc.dbase);
+    TFMM_LAUNCHED();
+    hipLaunchKernelGGL(radix_digit_base_kernel, dim3(1), dim3(RB), 0, s, sc.dbase, passes);
+    TFMM_LAUNCHED();
     K* kin = keys;
     int32_t* vin = vals;
     K* kout = keys_alt;
     int32_t* vout = vals_alt;
     for (int ps = 0; ps < passes; ++ps) {
-        const int shift = 8 * ps;
-        hipLaunchKernelGGL(radix_hist_kernel<K>, dim3(nb), dim3(RB), 0, s, kin, n, shift, hist, nb);
-        TFMM_LAUNCHED();
-        exclusive_scan_u32(hist, hist, nh, scan_scr, total, s);
-        hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(nb), dim3(RB), 0, s, kin, vin, kout, vout, n,
-                           shift, (const uint32_t*)hist, nb);
+        hipLaunchKernelGGL(radix_pass_kernel<K>, dim3(nb), dim3(RB), 0, s, (const K*)kin, (const int32_t*)vin, kout,
+                           vout, n, 8 * ps, (const uint32_t*)(sc.dbase + ps * RADIX),
+                           sc.status + (int64_t)ps * nb * RADIX, sc.ticket + ps, err);
         TFMM_LAUNCHED();
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -170,20 +299,19 @@ void radix_sort_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int
 
 }  // namespace
 
-size_t sort_scratch_bytes(int64_t n) {
-    const int64_t nb = cdiv(n > 0 ? n : 1, RTILE);
-    const int64_t nh = (int64_t)RADIX * nb;
-    return (size_t)(round_up(nh, 64) + 64) * sizeof(uint32_t) + scan_scratch_bytes(nh) + 256;
+size_t sort_scratch_bytes(int64_t n, int bits) {
+    const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
+    return (size_t)carve(nullptr, n, passes).zero_words * 8 + 256;
 }
 
-void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n,
-                    int bits, void* scratch, hipStream_t s) {
-    radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, scratch, s);
+void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
+                    void* scratch, uint32_t* err, hipStream_t s) {
+    radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, scratch, err, s);
 }
 
-void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
-                    int bits, void* scratch, hipStream_t s) {
-    radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, scratch, s);
+void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
+                    void* scratch, uint32_t* err, hipStream_t s) {
+    radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, scratch, err, s);
 }
 
 }  // namespace tfmm

@@ -532,7 +532,7 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
 
     // bounding cube (host computes ext and scale exactly as the key definition says)
     const int nbb = (int)std::min<int64_t>(1024, cdiv(n, TB));
-    t.scratch.ensure(ctx, std::max<size_t>({(size_t)nbb * 6 * 8 + 64, sort_scratch_bytes(n) + 256,
+    t.scratch.ensure(ctx, std::max<size_t>({(size_t)nbb * 6 * 8 + 64, sort_scratch_bytes(n, 3 * kLevels) + 256,
                                             scan_scratch_bytes(n) + 256}));
     double* part = t.scratch.as<double>();
     double* bb = part + 6 * nbb;
@@ -568,7 +568,7 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
                        (double)scale, t.keys.as<uint64_t>(), t.perm.as<int32_t>());
     TFMM_LAUNCHED();
     radix_sort_u64(t.keys.as<uint64_t>(), t.perm.as<int32_t>(), t.keys2.as<uint64_t>(), t.perm2.as<int32_t>(),
-                   n, 3 * kLevels, t.scratch.p, s);
+                   n, 3 * kLevels, t.scratch.p, ctx->dev_err, s);
 
     // sorted particles, boundary levels
     t.Xm.ensure(ctx, un * 32);
@@ -602,7 +602,7 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     TFMM_LAUNCHED();
     hipLaunchKernelGGL(tree_header_kernel, dim3(1), dim3(kWave), 0, s, (const uint32_t*)tot, hdr);
     TFMM_LAUNCHED();
-    const TreeHeader H = read_back(ctx, (const TreeHeader*)hdr, s);
+    const TreeHeader H = read_back_checked(ctx, (const TreeHeader*)hdr, s);
     t.n_nodes = H.n_nodes;
     t.max_level = (int)H.max_level;
     t.n_leaves = H.n_leaves;
@@ -629,7 +629,7 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     uint32_t* total = reinterpret_cast<uint32_t*>(t.scratch2.as<char>() + sizeof(TreeHeader));
     hipLaunchKernelGGL(leaf_flag_kernel, dim3(grid(nn)), dim3(TB), 0, s, nd.nchild, nn, flag);
     TFMM_LAUNCHED();
-    exclusive_scan_u32(flag, excl, nn, t.scratch.p, total, s);
+    exclusive_scan_u32(flag, excl, nn, t.scratch.p, total, ctx->dev_err, s);
     t.leaves.ensure(ctx, (size_t)std::max<int64_t>(t.n_leaves, 1) * 4);
     hipLaunchKernelGGL(leaf_compact_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)flag,
                        (const uint32_t*)excl, nn, t.leaves.as<int32_t>());
@@ -660,7 +660,7 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
         t.rmax_items.ensure(ctx, (size_t)ub * 8);
         hipLaunchKernelGGL(rmax_chunks_kernel, dim3(grid(nn)), dim3(TB), 0, s, nd.count, nn, c);
         TFMM_LAUNCHED();
-        exclusive_scan_u32(c, base, nn, t.scratch.p, total, s);
+        exclusive_scan_u32(c, base, nn, t.scratch.p, total, ctx->dev_err, s);
         hipLaunchKernelGGL(rmax_items_kernel, dim3(grid(nn)), dim3(TB), 0, s, nn, (const uint32_t*)c,
                            (const uint32_t*)base, t.rmax_items.as<int2>());
         TFMM_LAUNCHED();

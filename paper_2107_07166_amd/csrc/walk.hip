@@ -319,11 +319,11 @@ __global__ __launch_bounds__(TB) void near_entries_kernel(const int2* __restrict
 // >= t, for t = 0..nn (each t written by exactly one thread).
 __global__ __launch_bounds__(TB) void csr_offsets_kernel(const uint32_t* __restrict__ keys, int64_t ne,
                                                          int64_t nn, uint32_t* __restrict__ off) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i > ne) return;
-    const int64_t lo = (i == 0) ? 0 : (int64_t)keys[i - 1] + 1;
-    const int64_t hi = (i == ne) ? nn : (int64_t)keys[i];
-    for (int64_t t = lo; t <= hi; ++t) off[t] = (uint32_t)i;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i <= ne; i += (int64_t)gridDim.x * TB) {
+        const int64_t lo = (i == 0) ? 0 : (int64_t)keys[i - 1] + 1;
+        const int64_t hi = (i == ne) ? nn : (int64_t)keys[i];
+        for (int64_t t = lo; t <= hi; ++t) off[t] = (uint32_t)i;
+    }
 }
 
 __global__ __launch_bounds__(TB) void nonempty_from_off_kernel(const uint32_t* __restrict__ off, int64_t n,
@@ -468,10 +468,12 @@ void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& off,
     t.scratch2.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8 + 256);
     uint32_t* kalt = t.scratch2.as<uint32_t>();
     int32_t* valt = reinterpret_cast<int32_t*>(kalt + std::max<int64_t>(ne, 1));
-    t.scratch.ensure(ctx, sort_scratch_bytes(ne) + 1024);
-    radix_sort_u32(tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(), kalt, valt, ne, bits_for(nn), t.scratch.p, s);
+    t.scratch.ensure(ctx, sort_scratch_bytes(ne, bits_for(nn)) + 1024);
+    radix_sort_u32(tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(), kalt, valt, ne, bits_for(nn), t.scratch.p, ctx->dev_err,
+                   s);
     off.ensure(ctx, (size_t)(nn + 1) * 4);
-    hipLaunchKernelGGL(csr_offsets_kernel, dim3(grid(ne + 1)), dim3(TB), 0, s, (const uint32_t*)tgtbuf.as<uint32_t>(),
+    hipLaunchKernelGGL(csr_offsets_kernel, dim3((unsigned)std::min<int64_t>(2048, grid(ne + 1))), dim3(TB), 0, s,
+                       (const uint32_t*)tgtbuf.as<uint32_t>(),
                        ne, nn, off.as<uint32_t>());
     TFMM_LAUNCHED();
     std::swap(srcbuf.p, srcout.p);
@@ -655,7 +657,7 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
                            (const uint32_t*)t.m2l_off.as<uint32_t>(), nn, flag);
         TFMM_LAUNCHED();
         t.scratch.ensure(ctx, scan_scratch_bytes(nn) + 256);
-        exclusive_scan_u32(flag, ex, nn, t.scratch.p, &res->far_targets, s);
+        exclusive_scan_u32(flag, ex, nn, t.scratch.p, &res->far_targets, ctx->dev_err, s);
         t.m2l_targets.ensure(ctx, (size_t)std::max<int64_t>(nn, 1) * 4);
         hipLaunchKernelGGL(compact_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)flag,
                            (const uint32_t*)ex, nn, t.m2l_targets.as<int32_t>());
@@ -671,7 +673,7 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         hipLaunchKernelGGL(near_count_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near, c);
         TFMM_LAUNCHED();
         t.scratch.ensure(ctx, scan_scratch_bytes(n_near) + 256);
-        exclusive_scan_u32(c, o, n_near, t.scratch.p, &res->near_entries, s);
+        exclusive_scan_u32(c, o, n_near, t.scratch.p, &res->near_entries, ctx->dev_err, s);
         tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         hipLaunchKernelGGL(near_entries_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near,
@@ -695,11 +697,11 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         hipLaunchKernelGGL(entry_sources_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const int32_t*)t.p2p_src.as<int32_t>(),
                            ne, t.nd_count.as<int32_t>(), ec);
         TFMM_LAUNCHED();
-        exclusive_scan_u32(ec, P, ne, t.scratch.p, junk, s);
+        exclusive_scan_u32(ec, P, ne, t.scratch.p, junk, ctx->dev_err, s);
         hipLaunchKernelGGL(item_flag_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
                            (const uint32_t*)P, (const uint32_t*)t.p2p_off.as<uint32_t>(), ne, fl);
         TFMM_LAUNCHED();
-        exclusive_scan_u32(fl, ex, ne, t.scratch.p, &res->items, s);
+        exclusive_scan_u32(fl, ex, ne, t.scratch.p, &res->items, ctx->dev_err, s);
         const size_t ni = (size_t)std::max<int64_t>(ne, 1);
         t.it_leaf.ensure(ctx, ni * 4);
         t.it_q0.ensure(ctx, ni * 4);
@@ -719,9 +721,9 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
                            (const int32_t*)t.it_leaf.as<int32_t>(), (const int32_t*)t.leaf_item0.as<int32_t>(),
                            t.leaf_nitems.as<int32_t>());
         TFMM_LAUNCHED();
-        exclusive_scan_u32(ec, t.it_pbase.as<uint32_t>(), ne, t.scratch.p, &res->partial, s);
+        exclusive_scan_u32(ec, t.it_pbase.as<uint32_t>(), ne, t.scratch.p, &res->partial, ctx->dev_err, s);
     }
-    const WalkTotals h = read_back(ctx, (const WalkTotals*)res, s);
+    const WalkTotals h = read_back_checked(ctx, (const WalkTotals*)res, s);
     if ((int64_t)h.near_entries != ne)
         fail(TFMM_EDEVICE, "walk: near entry count " + std::to_string(h.near_entries) + " differs from " +
                                std::to_string(ne));
