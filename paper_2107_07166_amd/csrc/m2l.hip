@@ -7,9 +7,9 @@
 //   standard  : L_j(A) += sum_i D_{i+j}(R) W_i(B)    (Taylor series of Eq. taylor)
 //   conserving: P_j(A) += sum_i G_{i+j}(R) W_i(B), Q'_ej(A) += Q_ej - R_e P_j
 //               (realigned force, Eq. realign, scalar kept to degree p-1).
-// One wavefront owns one target node: its lanes stride over the target's
-// source list, each lane accumulating a private local expansion, and a
-// butterfly reduction across the wave produces the node's locals (written
+// Each half wavefront (32 lanes) owns one target node: its lanes stride over
+// the target's source list, each lane accumulating a private local expansion,
+// and a DPP reduction across the half wave produces the node's locals (written
 // once, no atomics, fixed order -> reproducible).
 #include "common.h"
 #include "expansions_gen.h"
@@ -17,15 +17,40 @@
 namespace tfmm {
 namespace {
 
-constexpr int MB = 256;  // threads per block = 4 waves = 4 target nodes
+constexpr int MB = 256;         // threads per block = 4 waves
+constexpr int LPT = 32;         // lanes per target node
+constexpr int TPW = kWave / LPT;  // target nodes per wavefront
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 
+// Reductions with DPP lane moves only (no LDS): pairs and quads (quad_perm),
+// half rows (row_half_mirror), rows (row_mirror), then row 0 into row 1 and
+// row 2 into row 3 (row_bcast:15).  Lanes not addressed by a row mask add zero.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xF, false);
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(dpp_i<CTRL, ROWMASK>(__float_as_int(v)));
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = dpp_i<CTRL, ROWMASK>((int)(uint32_t)u);
+    const int hi = dpp_i<CTRL, ROWMASK>((int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Sum over each half wavefront (32 lanes), results in lanes 31 and 63.
 template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+__device__ __forceinline__ T half_wave_sum_last(T v) {
+    v += dpp<0xB1>(v);        // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);        // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);       // row_half_mirror
+    v += dpp<0x140>(v);       // row_mirror
+    v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
     return v;
 }
 
@@ -44,14 +69,17 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets, const int32_
     // list bounds in scalar registers
     const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (MB / kWave) + threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
-    if (wave >= n_targets) return;
-    const int32_t A = targets[wave];
+    if (wave * TPW >= n_targets) return;
+    const int half = lane / LPT, sl = lane % LPT;
+    const int64_t ti = wave * TPW + half;
+    const bool has = ti < n_targets;
+    const int32_t A = has ? targets[ti] : targets[wave * TPW];
     const double4 za = Z[A];
     T acc[NOUT];
 #pragma unroll
     for (int k = 0; k < NOUT; ++k) acc[k] = T(0);
-    const uint32_t q1 = off[A + 1];
-    for (uint32_t q = off[A] + lane; q < q1; q += kWave) {
+    const uint32_t q0 = has ? off[A] : 0u, q1 = has ? off[A + 1] : 0u;
+    for (uint32_t q = q0 + sl; q < q1; q += LPT) {
         const int32_t B = src[q];
         const double4 zb = Z[B];
         const T Rx = (T)(za.x - zb.x), Ry = (T)(za.y - zb.y), Rz = (T)(za.z - zb.z);
@@ -83,8 +111,8 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets, const int32_
         }
     }
 #pragma unroll
-    for (int k = 0; k < NOUT; ++k) acc[k] = wave_sum(acc[k]);
-    if (lane == 0) {
+    for (int k = 0; k < NOUT; ++k) acc[k] = half_wave_sum_last(acc[k]);
+    if (has && sl == LPT - 1) {
         double* out = loc + (int64_t)A * NOUT;
 #pragma unroll
         for (int k = 0; k < NOUT; ++k) out[k] = (double)acc[k];
@@ -101,7 +129,7 @@ void launch(Tree& t, double eps2, hipStream_t s) {
     const int64_t nt = t.n_m2l_targets;
     if (nt <= 0) return;
     const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
-    hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), dim3((unsigned)cdiv(nt * kWave, MB)), dim3(MB), 0, s, nt,
+    hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), dim3((unsigned)cdiv(cdiv(nt, TPW) * kWave, MB)), dim3(MB), 0, s, nt,
                        t.m2l_targets.as<int32_t>(), t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(),
                        t.nd_Z.as<double4>(), W, eps2, t.loc.as<double>());
     TFMM_LAUNCHED();
