@@ -116,6 +116,7 @@ struct Tree {
     // sizes seen by the previous walk of this tree (capacity hints for the
     // passes that run without host synchronisation; 0 = none yet)
     int64_t walk_hint_fr = 0, walk_hint_far = 0, walk_hint_near = 0;
+    std::vector<int64_t> walk_hint_nf;  // frontier size of every pass
     // near-field work items: a target leaf's list cut into pieces of bounded
     // source count, each run by one wavefront into its own partial sums
     int64_t n_items = 0, n_partial = 0;

@@ -22,9 +22,12 @@
 namespace tfmm {
 namespace {
 
-constexpr int RB = 256;          // threads per block
-constexpr int RW = RB / kWave;   // waves per block
-constexpr int RI = 16;           // keys per lane
+#ifndef TFMM_SORT_RI
+#define TFMM_SORT_RI 16
+#endif
+constexpr int RB = 256;           // threads per block (one digit per thread)
+constexpr int RW = RB / kWave;    // waves per block
+constexpr int RI = TFMM_SORT_RI;  // keys per lane
 constexpr int RTILE = RB * RI;   // keys per tile
 constexpr int RADIX = 256;
 constexpr int MAXP = 8;          // passes of a 64-bit key

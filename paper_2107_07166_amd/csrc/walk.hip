@@ -144,6 +144,7 @@ __device__ __forceinline__ U3L block_sum(U3L x, U3L* wsum) {
 // passes can be queued without reading anything back.  A pass whose outputs
 // would not fit sets a sticky flag and writes nothing; later passes then see
 // an empty frontier.
+constexpr int kMaxPasses = 64;  // a walk needs at most 2 * 21 + 1 passes
 struct WalkState {
     uint32_t nf[2];
     uint32_t overflow;
@@ -151,6 +152,7 @@ struct WalkState {
     uint32_t max_nf;  // largest frontier seen
     uint32_t pad;
     unsigned long long n_far[2], n_near[2];
+    uint32_t nf_pass[kMaxPasses];  // frontier size of every pass (sizes the next walk's grids)
 };
 constexpr int kWalkGrid = 1024;
 
@@ -173,6 +175,7 @@ __global__ void walk_init_kernel(WalkState* __restrict__ st, int2* __restrict__ 
         st->n_near[0] = st->n_near[1] = 0ull;
         fr[0] = make_int2(0, 0);
     }
+    for (int k = threadIdx.x; k < kMaxPasses; k += blockDim.x) st->nf_pass[k] = 0u;
 }
 
 // Decision code: bits 0-1 kind (0 near, 1 far, 2 expand self, 3 split);
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(TB) void walk_total_kernel(const U3L* __restrict__ 
 // Every block sums the block totals itself (the pass total and its own
 // offset), so no scan launch sits between counting and emitting.
 __global__ __launch_bounds__(TB) void walk_emit_pass_kernel(WalkNodes w, const int2* __restrict__ fr,
-                                                            WalkState* __restrict__ st, int parity,
+                                                            WalkState* __restrict__ st, int pass,
                                                             const uint8_t* __restrict__ dec,
                                                             const U3* __restrict__ off, const U3L* __restrict__ bsum,
                                                             int2* __restrict__ next, int2* __restrict__ far,
@@ -234,6 +237,7 @@ __global__ __launch_bounds__(TB) void walk_emit_pass_kernel(WalkNodes w, const i
     }
     const U3L T = block_sum(all, wsum);
     const U3L B = block_sum(before, wsum);
+    const int parity = pass & 1;
     const uint32_t nf = st->overflow ? 0u : st->nf[parity];
     const unsigned long long far0 = st->n_far[parity], near0 = st->n_near[parity];
     const unsigned long long lim = 0xffffffffull;
@@ -252,6 +256,7 @@ __global__ __launch_bounds__(TB) void walk_emit_pass_kernel(WalkNodes w, const i
         st->n_near[parity ^ 1] = near0 + T.c;
         if (nf > 0u) st->passes += 1u;
         if ((uint32_t)T.a > st->max_nf) st->max_nf = (uint32_t)T.a;
+        if (pass < kMaxPasses) st->nf_pass[pass] = nf;
     }
     int64_t t0, t1;
     block_tiles(nf, t0, t1);
@@ -507,8 +512,10 @@ void walk_bfs_sized(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
     DevBuf* cur = &t.w_fr;
     DevBuf* nxt = &t.w_fr2;
     int64_t nf = 1, max_nf = 1, n_far = 0, n_near = 0;
+    t.walk_hint_nf.clear();
     for (int k = 0; nf > 0; ++k) {
         const int parity = k & 1;
+        t.walk_hint_nf.push_back(nf);
         const unsigned g = (unsigned)std::min<int64_t>(kWalkGrid, cdiv(nf, TB));
         // buffers resized here are idle: a resize waits for the device
         t.w_dec.ensure(ctx, (size_t)nf);
@@ -532,8 +539,8 @@ void walk_bfs_sized(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
         }
         nxt->ensure(ctx, (size_t)std::max<unsigned long long>(T.a, 1) * 8);
         const size_t cap_next = std::min<size_t>(nxt->cap / 8, UINT32_MAX);
-        hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur->as<int2>(), st,
-                           parity, (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3*)t.w_cnt.as<U3>(),
+        hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur->as<int2>(), st, k,
+                           (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3*)t.w_cnt.as<U3>(),
                            (const U3L*)t.w_off.as<U3L>(), nxt->as<int2>(), t.m2l_pairs.as<int2>(),
                            t.p2p_pairs.as<int2>(), (uint32_t)cap_next, (unsigned long long)(t.m2l_pairs.cap / 8),
                            (unsigned long long)(t.p2p_pairs.cap / 8));
@@ -580,17 +587,22 @@ bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
     hipLaunchKernelGGL(walk_init_kernel, dim3(1), dim3(kWave), 0, s, st, t.w_fr.as<int2>());
     TFMM_LAUNCHED();
     const int passes = 2 * t.max_level + 1;
+    if (passes > kMaxPasses) return false;
     int64_t bound = 1;  // a pass's frontier is at most 36 times the previous one
     for (int k = 0; k < passes; ++k) {
         const int parity = k & 1;
-        const unsigned g = (unsigned)std::min<int64_t>(kWalkGrid, cdiv(bound, TB));
+        // grid from this pass's frontier in the previous walk (any grid covers
+        // any frontier; a small one keeps small passes cheap)
+        int64_t expect = bound;
+        if (k < (int)t.walk_hint_nf.size()) expect = std::min(bound, t.walk_hint_nf[k] + t.walk_hint_nf[k] / 4 + 1024);
+        const unsigned g = (unsigned)std::min<int64_t>(kWalkGrid, cdiv(std::max<int64_t>(expect, 1), TB));
         int2* cur = parity ? t.w_fr2.as<int2>() : t.w_fr.as<int2>();
         int2* nxt = parity ? t.w_fr.as<int2>() : t.w_fr2.as<int2>();
         hipLaunchKernelGGL(walk_count_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur,
                            (const WalkState*)st, parity, theta, t.w_dec.as<uint8_t>(), t.w_cnt.as<U3>(),
                            t.w_off.as<U3L>());
         TFMM_LAUNCHED();
-        hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur, st, parity,
+        hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur, st, k,
                            (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3*)t.w_cnt.as<U3>(),
                            (const U3L*)t.w_off.as<U3L>(), nxt, t.m2l_pairs.as<int2>(), t.p2p_pairs.as<int2>(),
                            (uint32_t)cap_next, cap_far, cap_near);
@@ -603,6 +615,7 @@ bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
     t.n_m2l = (int64_t)h.n_far[pf];
     t.n_p2p = (int64_t)h.n_near[pf];
     t.walk_hint_fr = h.max_nf;
+    t.walk_hint_nf.assign(h.nf_pass, h.nf_pass + passes);
     return true;
 }
 
