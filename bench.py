@@ -35,8 +35,8 @@ P2P_FLOP_PER_PAIR = 20        # per directed particle interaction (convention)
 # factor a plain copy of known size reads) and WRITE_SIZE (x1); see
 # profiles/p2p_plummer1m_counters.md.  Valid only for the kernel source the
 # counters were taken with (first 16 hex digits of its sha256).
-P2P_TRAFFIC_BYTES = (2 * 256200 + 32009) * 1024
-P2P_TRAFFIC_SOURCE_SHA = "6c53744775858ce3"
+P2P_TRAFFIC_BYTES = (2 * 224355 + 32009) * 1024
+P2P_TRAFFIC_SOURCE_SHA = "af6f9231838197b4"
 
 
 def _p2p_traffic():
@@ -117,11 +117,13 @@ def cpu_baseline(w, pos, mass, budget_s, n_leaf):
     ot = oracle.Tree(pos, mass, n_leaf=n_leaf, theta=w.theta)
     t_tree = time.perf_counter() - t0
     rng = np.random.default_rng(12345)
-    probe = rng.choice(w.n, 32, replace=False)
+    probe = rng.choice(w.n, 64, replace=False)
+    # the first call also builds the oracle's lazy per-node lists: time a second one
+    ot.forces(w.p, w.eps, "conserving", targets=probe[:8])
     t0 = time.perf_counter()
     ot.forces(w.p, w.eps, "conserving", targets=probe)
     t_probe = time.perf_counter() - t0
-    k = int(np.clip(32 * budget_s / max(t_probe, 1e-3), 32, 20000))
+    k = int(np.clip(64 * budget_s / max(t_probe, 1e-3), 64, 50000))
     sample = rng.choice(w.n, k, replace=False)
     t0 = time.perf_counter()
     f_cons = ot.forces(w.p, w.eps, "conserving", targets=sample)
@@ -143,7 +145,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n-leaf", type=int, default=64)
-    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle force time")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle force time")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -12,6 +12,12 @@
         theta in {0.4,0.6,0.8}, plus persistent leapfrog sessions: FP32 mixed
         with concurrent slots against FP64 one solve at a time, same trace;
         solves/s and p50/p99 latency, and the per-request mixed-vs-FP64 error.
+    python -m paper_2107_07166_amd.studies profile [--steps 3] [--n-leaf 64]
+        Driver for profilers: the benchmark workload (Plummer N=2^20, p=4,
+        theta=0.5, conserving, mixed), one tree, then --steps rebuild + walk +
+        evaluate steps with per-phase event times.
+    python -m paper_2107_07166_amd.studies copy
+        Counter calibration: three device copies of a 256 MiB buffer.
 """
 
 from __future__ import annotations
@@ -116,9 +122,41 @@ def study_serve(n_requests: int, n_sessions: int, rate: float, slots: int, budge
     return out
 
 
+def study_profile(steps: int, n_leaf: int) -> dict:
+    w = generators.WORKLOADS["plummer1m"]
+    pos, mass = w.make()
+    pd, md = _dev(pos), _dev(mass)
+    ctx = api.Context(0)
+    tree = api.Tree(ctx, pd, md, n_leaf=n_leaf)
+    f = torch.empty((w.n, 3), dtype=torch.float64, device=pd.device)
+    tree.set_timing(True)
+    phases = []
+    for _ in range(steps):
+        tree.rebuild(pd, md)
+        tree.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant="conserving", precision="mixed32", out=f)
+        torch.cuda.synchronize()
+        phases.append(tree.phase_times())
+    out = {"study": "profile", "steps": steps, "n_leaf": n_leaf, "tree": tree.info(),
+           "phases_ms_last": phases[-1]}
+    tree.close()
+    ctx.close()
+    return out
+
+
+def study_copy() -> dict:
+    x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"study": "copy", "bytes_per_copy": 256 << 20, "copies": 3}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["binary", "disk", "serve"])
+    ap.add_argument("study", choices=["binary", "disk", "serve", "profile", "copy"])
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--dt", type=float, default=1e-3)
@@ -134,6 +172,10 @@ def main():
         r = study_binary(a.n or (1 << 22), a.steps, a.dt, a.n_leaf)
     elif a.study == "disk":
         r = study_disk(a.n or 4194304, a.n_leaf, a.reps)
+    elif a.study == "profile":
+        r = study_profile(a.steps, a.n_leaf)
+    elif a.study == "copy":
+        r = study_copy()
     else:
         r = study_serve(a.requests, a.sessions, a.rate, a.slots, a.budget_gb)
     print(json.dumps(r), flush=True)
