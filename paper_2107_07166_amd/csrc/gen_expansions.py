@@ -189,6 +189,45 @@ def gen_struct(P):
         out.append("    }")
     out.append("  }")
 
+    # conserving M2L one polynomial at a time (for orders whose four
+    # accumulator sets do not fit the registers together):
+    #   cons_p:    Pa_j  += sum_{|i| <= P-1-|j|, |i| != 1} G_{i+j} W_i
+    #   cons_q<E>: Qa_j  -= sum_{|i| <= P-1-|j|} G_{i+j} V_i,
+    #              V_i = (i_E + 1) W_{i+E} [|i| >= 1] + R_E W_i [|i| != 1],
+    # the same terms as m2l_cons (Q_Ej - R_E p_j) grouped per source moment.
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static void cons_p(const T* G, const T* W, T* Pa) {")
+    for j in all_upto(P - 1):
+        terms = [(idx(add(i, j)), idx(i)) for i in all_upto(P - 1 - sum(j)) if sum(i) != 1]
+        expr = f"Pa[{idx(j)}]"
+        for gi, wi in terms:
+            expr = f"fma(G[{gi}], W[{wi}], {expr})"
+        out.append(f"    Pa[{idx(j)}] = {expr};")
+    out.append("  }")
+    for e in range(3):
+        out.append("  template <typename T>")
+        out.append(f"  __device__ __forceinline__ static void cons_q{AX[e]}(const T* G, const T* W, T R{AX[e]}, T* Qa) {{")
+        for i in all_upto(P - 1):
+            parts = []
+            if sum(i) >= 1:
+                c = i[e] + 1
+                wi = idx(add(i, E[e]))
+                parts.append(f"W[{wi}]" if c == 1 else f"{fmt(c)} * W[{wi}]")
+            if sum(i) != 1:
+                parts.append(f"R{AX[e]} * W[{idx(i)}]")
+            if len(parts) == 2:
+                if parts[0].startswith("W["):
+                    v = f"fma(R{AX[e]}, W[{idx(i)}], {parts[0]})"
+                else:
+                    v = f"fma(R{AX[e]}, W[{idx(i)}], {parts[0]})"
+            else:
+                v = parts[0]
+            out.append(f"    {{ const T v = {v};")
+            for j in all_upto(P - 1 - sum(i)):
+                out.append(f"      Qa[{idx(j)}] = fma(-G[{idx(add(i, j))}], v, Qa[{idx(j)}]);")
+            out.append("    }")
+        out.append("  }")
+
     # monomials x^j / j! for |j| <= Q (into Mo)
     def mono_lines(Q, var="Mo", dx="dx", dy="dy", dz="dz"):
         ls = [f"{var}[0] = T(1);"]

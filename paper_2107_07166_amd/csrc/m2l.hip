@@ -119,20 +119,107 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets, const int32_
     }
 }
 
+// Conserving M2L one output polynomial per launch (POLY 0: P, 1..3: Q'_x,y,z)
+// for orders whose four accumulator sets do not fit the registers together:
+// each launch recomputes the g-derivatives of every pair and accumulates one
+// set of NC1 locals, written into its slice of the node's 4 NC1 block.
+template <int P, int POLY, typename T>
+__global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets, const int32_t* __restrict__ targets,
+                                                           const uint32_t* __restrict__ off,
+                                                           const int32_t* __restrict__ src,
+                                                           const double4* __restrict__ Z, const T* __restrict__ W,
+                                                           double eps2, double* __restrict__ loc) {
+    using E = Expansion<P>;
+    constexpr int NC = E::NC;
+    constexpr int NC1 = E::NC1;
+    constexpr int NCP = (NC + 3) / 4 * 4;
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (MB / kWave) + threadIdx.x / kWave));
+    const int lane = threadIdx.x & (kWave - 1);
+    if (wave * TPW >= n_targets) return;
+    const int half = lane / LPT, sl = lane % LPT;
+    const int64_t ti = wave * TPW + half;
+    const bool has = ti < n_targets;
+    const int32_t A = has ? targets[ti] : targets[wave * TPW];
+    const double4 za = Z[A];
+    T acc[NC1];
+#pragma unroll
+    for (int k = 0; k < NC1; ++k) acc[k] = T(0);
+    const uint32_t q0 = has ? off[A] : 0u, q1 = has ? off[A + 1] : 0u;
+    for (uint32_t q = q0 + sl; q < q1; q += LPT) {
+        const int32_t B = src[q];
+        const double4 zb = Z[B];
+        const T Rx = (T)(za.x - zb.x), Ry = (T)(za.y - zb.y), Rz = (T)(za.z - zb.z);
+        const T s = Rx * Rx + Ry * Ry + Rz * Rz + (T)eps2;
+        const T rinv = rsqrt_t(s);
+        const T inv_s = rinv * rinv;
+        T F[P + 1];
+        F[0] = -rinv;
+#pragma unroll
+        for (int n = 1; n <= P; ++n) F[n] = (T)(-(2 * n - 1)) * F[n - 1] * inv_s;
+        T w[NCP];
+        const typename Vec4<T>::type* wb = reinterpret_cast<const typename Vec4<T>::type*>(W + (int64_t)B * NCP);
+#pragma unroll
+        for (int k = 0; k < NCP / 4; ++k) {
+            const typename Vec4<T>::type v = wb[k];
+            w[4 * k] = v.x;
+            w[4 * k + 1] = v.y;
+            w[4 * k + 2] = v.z;
+            w[4 * k + 3] = v.w;
+        }
+        T G[NC1];
+        E::g_derivs(Rx, Ry, Rz, F, G);
+        if constexpr (POLY == 0) E::cons_p(G, w, acc);
+        else if constexpr (POLY == 1) E::cons_qx(G, w, Rx, acc);
+        else if constexpr (POLY == 2) E::cons_qy(G, w, Ry, acc);
+        else E::cons_qz(G, w, Rz, acc);
+    }
+#pragma unroll
+    for (int k = 0; k < NC1; ++k) acc[k] = half_wave_sum_last(acc[k]);
+    if (has && sl == LPT - 1) {
+        double* out = loc + (int64_t)A * (4 * NC1) + POLY * NC1;
+#pragma unroll
+        for (int k = 0; k < NC1; ++k) out[k] = (double)acc[k];
+    }
+}
+
 __global__ void zero_f64_kernel(double* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = 0.0;
 }
+
+// Orders from which the conserving locals are accumulated one polynomial per
+// launch (the fused kernel would spill its 4 NC1 accumulators).
+constexpr int kConsSplitP = 5;
 
 template <int P, int VAR, typename T>
 void launch(Tree& t, double eps2, hipStream_t s) {
     const int64_t nt = t.n_m2l_targets;
     if (nt <= 0) return;
     const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
-    hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), dim3((unsigned)cdiv(cdiv(nt, TPW) * kWave, MB)), dim3(MB), 0, s, nt,
-                       t.m2l_targets.as<int32_t>(), t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(),
-                       t.nd_Z.as<double4>(), W, eps2, t.loc.as<double>());
-    TFMM_LAUNCHED();
+    const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, MB));
+    if constexpr (VAR == TFMM_CONSERVING && P >= kConsSplitP) {
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 0, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.loc.as<double>());
+        TFMM_LAUNCHED();
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 1, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.loc.as<double>());
+        TFMM_LAUNCHED();
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 2, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.loc.as<double>());
+        TFMM_LAUNCHED();
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 3, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.loc.as<double>());
+        TFMM_LAUNCHED();
+    } else {
+        hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.loc.as<double>());
+        TFMM_LAUNCHED();
+    }
 }
 
 template <int P>

@@ -13,9 +13,10 @@
         with concurrent slots against FP64 one solve at a time, same trace;
         solves/s and p50/p99 latency, and the per-request mixed-vs-FP64 error.
     python -m paper_2107_07166_amd.studies profile [--steps 3] [--n-leaf 64]
-        Driver for profilers: the benchmark workload (Plummer N=2^20, p=4,
-        theta=0.5, conserving, mixed), one tree, then --steps rebuild + walk +
-        evaluate steps with per-phase event times.
+                                                   [--workload plummer1m] [--variant conserving]
+        Driver for profilers: a workload (default the benchmark one, Plummer
+        N=2^20, p=4, theta=0.5; mixed precision), one tree, then --steps
+        rebuild + walk + evaluate steps with per-phase event times.
     python -m paper_2107_07166_amd.studies copy
         Counter calibration: three device copies of a 256 MiB buffer.
 """
@@ -122,8 +123,8 @@ def study_serve(n_requests: int, n_sessions: int, rate: float, slots: int, budge
     return out
 
 
-def study_profile(steps: int, n_leaf: int) -> dict:
-    w = generators.WORKLOADS["plummer1m"]
+def study_profile(steps: int, n_leaf: int, workload: str = "plummer1m", variant: str = "conserving") -> dict:
+    w = generators.WORKLOADS[workload]
     pos, mass = w.make()
     pd, md = _dev(pos), _dev(mass)
     ctx = api.Context(0)
@@ -133,10 +134,11 @@ def study_profile(steps: int, n_leaf: int) -> dict:
     phases = []
     for _ in range(steps):
         tree.rebuild(pd, md)
-        tree.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant="conserving", precision="mixed32", out=f)
+        tree.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision="mixed32", out=f)
         torch.cuda.synchronize()
         phases.append(tree.phase_times())
-    out = {"study": "profile", "steps": steps, "n_leaf": n_leaf, "tree": tree.info(),
+    out = {"study": "profile", "workload": workload, "variant": variant, "steps": steps, "n_leaf": n_leaf,
+           "tree": tree.info(),
            "phases_ms_last": phases[-1]}
     tree.close()
     ctx.close()
@@ -167,13 +169,15 @@ def main():
     ap.add_argument("--rate", type=float, default=100.0)
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--workload", default="plummer1m", choices=sorted(generators.WORKLOADS))
+    ap.add_argument("--variant", default="conserving", choices=["standard", "conserving"])
     a = ap.parse_args()
     if a.study == "binary":
         r = study_binary(a.n or (1 << 22), a.steps, a.dt, a.n_leaf)
     elif a.study == "disk":
         r = study_disk(a.n or 4194304, a.n_leaf, a.reps)
     elif a.study == "profile":
-        r = study_profile(a.steps, a.n_leaf)
+        r = study_profile(a.steps, a.n_leaf, a.workload, a.variant)
     elif a.study == "copy":
         r = study_copy()
     else:
