@@ -152,7 +152,9 @@ int tfmm_momentum_diagnostics(tfmm_ctx *ctx, int64_t n, const double *pos, const
  * [4] far (M2L) unordered pairs, [5] near (P2P) unordered pairs, [6] directed
  * near particle interactions (sum over directed leaf pairs of n_target *
  * n_source, self pairs n(n-1)), [7] directed far pairs.  [4..7] are -1 before
- * the first walk.  Host output.  Errors: EINVAL. */
+ * the first walk.  Host output.  [6] is counted on the device on the first
+ * request after a walk; that request waits for the device to be idle.
+ * Errors: EINVAL, EDEVICE. */
 int tfmm_tree_info(const tfmm_tree *tree, int64_t *out);
 
 /* Copy the tree to host buffers (each may be NULL; caller-allocated):

@@ -293,15 +293,19 @@ int tfmm_momentum_diagnostics(tfmm_ctx* ctx, int64_t n, const double* pos, const
 
 int tfmm_tree_info(const tfmm_tree* tree, int64_t* out) {
     if (!tree || !out) return TFMM_EINVAL;
-    out[0] = tree->n;
-    out[1] = tree->n_nodes;
-    out[2] = tree->n_leaves;
-    out[3] = tree->max_level;
-    out[4] = tree->walk_valid ? tree->n_m2l : -1;
-    out[5] = tree->walk_valid ? tree->n_p2p : -1;
-    out[6] = tree->walk_valid ? tree->n_near_int : -1;
-    out[7] = tree->walk_valid ? 2 * tree->n_m2l : -1;
-    return TFMM_OK;
+    // the near-interaction count is computed on the first request after a walk
+    Tree& t = const_cast<Tree&>(*static_cast<const Tree*>(tree));
+    return guarded(t.ctx, [&] {
+        set_device(t.ctx);
+        out[0] = t.n;
+        out[1] = t.n_nodes;
+        out[2] = t.n_leaves;
+        out[3] = t.max_level;
+        out[4] = t.walk_valid ? t.n_m2l : -1;
+        out[5] = t.walk_valid ? t.n_p2p : -1;
+        out[6] = t.walk_valid ? near_interactions(t) : -1;
+        out[7] = t.walk_valid ? 2 * t.n_m2l : -1;
+    });
 }
 
 int tfmm_tree_export(tfmm_tree* tree, uint64_t* keys, int32_t* order, int32_t* level, uint64_t* prefix,

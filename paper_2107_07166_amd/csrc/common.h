@@ -109,8 +109,6 @@ struct Tree {
     DevBuf m2l_pairs, p2p_pairs;  // int2, lower node id first
     DevBuf m2l_off, m2l_src;      // per-target CSR (node ids), directed
     DevBuf p2p_off, p2p_src;
-    DevBuf m2l_targets;           // nodes with a non-empty far list
-    int64_t n_m2l_targets = 0;
     DevBuf w_fr, w_fr2, w_cnt, w_off, w_tg, w_sr, w_fl, w_c;  // walk and list-building scratch
     DevBuf w_state, w_res, w_dec; // device-side walk counters, list totals, pair decisions
     // sizes seen by the previous walk of this tree (capacity hints for the
@@ -181,6 +179,7 @@ V read_back_checked(Ctx* ctx, const V* dev, hipStream_t s) {
 // ---- phases ---------------------------------------------------------------
 void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s);
 void walk_tree(Tree& t, double theta, hipStream_t s);
+int64_t near_interactions(Tree& t);
 void compute_moments(Tree& t, int p, hipStream_t s);
 void prepare_sources(Tree& t, int precision, hipStream_t s);
 void run_m2l(Tree& t, int p, int variant, int precision, double eps2, hipStream_t s);

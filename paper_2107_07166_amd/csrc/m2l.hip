@@ -55,7 +55,7 @@ __device__ __forceinline__ T half_wave_sum_last(T v) {
 }
 
 template <int P, int VAR, typename T>
-__global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets, const int32_t* __restrict__ targets,
+__global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
                                                  const uint32_t* __restrict__ off,
                                                  const int32_t* __restrict__ src,
                                                  const double4* __restrict__ Z, const T* __restrict__ W,
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets, const int32_
     const int half = lane / LPT, sl = lane % LPT;
     const int64_t ti = wave * TPW + half;
     const bool has = ti < n_targets;
-    const int32_t A = has ? targets[ti] : targets[wave * TPW];
+    const int32_t A = (int32_t)(has ? ti : wave * TPW);
     const double4 za = Z[A];
     T acc[NOUT];
 #pragma unroll
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets, const int32_
     }
 #pragma unroll
     for (int k = 0; k < NOUT; ++k) acc[k] = half_wave_sum_last(acc[k]);
-    if (has && sl == LPT - 1) {
+    if (has && q1 > q0 && sl == LPT - 1) {
         double* out = loc + (int64_t)A * NOUT;
 #pragma unroll
         for (int k = 0; k < NOUT; ++k) out[k] = (double)acc[k];
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets, const int32_
 // each launch recomputes the g-derivatives of every pair and accumulates one
 // set of NC1 locals, written into its slice of the node's 4 NC1 block.
 template <int P, int POLY, typename T>
-__global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets, const int32_t* __restrict__ targets,
+__global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
                                                            const uint32_t* __restrict__ off,
                                                            const int32_t* __restrict__ src,
                                                            const double4* __restrict__ Z, const T* __restrict__ W,
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets, co
     const int half = lane / LPT, sl = lane % LPT;
     const int64_t ti = wave * TPW + half;
     const bool has = ti < n_targets;
-    const int32_t A = has ? targets[ti] : targets[wave * TPW];
+    const int32_t A = (int32_t)(has ? ti : wave * TPW);
     const double4 za = Z[A];
     T acc[NC1];
 #pragma unroll
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets, co
     }
 #pragma unroll
     for (int k = 0; k < NC1; ++k) acc[k] = half_wave_sum_last(acc[k]);
-    if (has && sl == LPT - 1) {
+    if (has && q1 > q0 && sl == LPT - 1) {
         double* out = loc + (int64_t)A * (4 * NC1) + POLY * NC1;
 #pragma unroll
         for (int k = 0; k < NC1; ++k) out[k] = (double)acc[k];
@@ -193,29 +193,29 @@ constexpr int kConsSplitP = 5;
 
 template <int P, int VAR, typename T>
 void launch(Tree& t, double eps2, hipStream_t s) {
-    const int64_t nt = t.n_m2l_targets;
+    const int64_t nt = t.n_nodes;  // every node; nodes with an empty far list write nothing
     if (nt <= 0) return;
     const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
     const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, MB));
     if constexpr (VAR == TFMM_CONSERVING && P >= kConsSplitP) {
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 0, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 0, T>), grid, dim3(MB), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 1, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 1, T>), grid, dim3(MB), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 2, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 2, T>), grid, dim3(MB), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 3, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 3, T>), grid, dim3(MB), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
     } else {
-        hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), grid, dim3(MB), 0, s, nt, t.m2l_targets.as<int32_t>(),
+        hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), grid, dim3(MB), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();

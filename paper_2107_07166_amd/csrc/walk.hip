@@ -331,22 +331,9 @@ __global__ __launch_bounds__(TB) void csr_offsets_kernel(const uint32_t* __restr
     }
 }
 
-__global__ __launch_bounds__(TB) void nonempty_from_off_kernel(const uint32_t* __restrict__ off, int64_t n,
-                                                               uint32_t* __restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i < n) flag[i] = off[i + 1] > off[i] ? 1u : 0u;
-}
-
 __global__ __launch_bounds__(TB) void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i < n) p[i] = v;
-}
-
-__global__ __launch_bounds__(TB) void compact_kernel(const uint32_t* __restrict__ flag,
-                                                     const uint32_t* __restrict__ excl, int64_t n,
-                                                     int32_t* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i < n && flag[i]) out[excl[i]] = (int32_t)i;
 }
 
 // Directed near particle interactions: sum over directed leaf pairs of
@@ -621,7 +608,7 @@ bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
 
 // Device slots of the list-building totals, read back together at the end.
 struct WalkTotals {
-    uint32_t far_targets;  // nodes with a non-empty far list
+    uint32_t unused0;
     uint32_t near_entries; // directed near entries (check of 2 n_near - n_leaves)
     uint32_t items;        // near-field work items
     uint32_t partial;      // partial-sum rows of multi-item leaves
@@ -662,19 +649,6 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
             TFMM_LAUNCHED();
         }
         build_csr(t, tg, sr, ne, t.m2l_off, t.m2l_src, s);
-        // targets with a non-empty far list
-        t.w_fl.ensure(ctx, (size_t)(nn + 1) * 8);
-        uint32_t* flag = t.w_fl.as<uint32_t>();
-        uint32_t* ex = flag + nn + 1;
-        hipLaunchKernelGGL(nonempty_from_off_kernel, dim3(grid(nn)), dim3(TB), 0, s,
-                           (const uint32_t*)t.m2l_off.as<uint32_t>(), nn, flag);
-        TFMM_LAUNCHED();
-        t.scratch.ensure(ctx, scan_scratch_bytes(nn) + 256);
-        exclusive_scan_u32(flag, ex, nn, t.scratch.p, &res->far_targets, ctx->dev_err, s);
-        t.m2l_targets.ensure(ctx, (size_t)std::max<int64_t>(nn, 1) * 4);
-        hipLaunchKernelGGL(compact_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)flag,
-                           (const uint32_t*)ex, nn, t.m2l_targets.as<int32_t>());
-        TFMM_LAUNCHED();
     }
     // near lists: directed (self pairs once), by target.  Every leaf has
     // exactly one self pair, so the entry count is 2 n_near - n_leaves.
@@ -693,12 +667,6 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
                            (const uint32_t*)o, tg.as<uint32_t>(), sr.as<int32_t>());
         TFMM_LAUNCHED();
         build_csr(t, tg, sr, ne, t.p2p_off, t.p2p_src, s);
-        // directed near particle interactions (for throughput accounting)
-        const unsigned nb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(ne, TB)));
-        hipLaunchKernelGGL(near_work_kernel, dim3(nb), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
-                           (const int32_t*)t.p2p_src.as<int32_t>(), ne, t.nd_count.as<int32_t>(), &res->near_int);
-        TFMM_LAUNCHED();
-
         // work items over the sorted near entries (tg holds the sorted targets);
         // there are at most ne items, so every item array is sized by ne
         t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 16);
@@ -740,12 +708,31 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
     if ((int64_t)h.near_entries != ne)
         fail(TFMM_EDEVICE, "walk: near entry count " + std::to_string(h.near_entries) + " differs from " +
                                std::to_string(ne));
-    t.n_m2l_targets = h.far_targets;
-    t.n_near_int = (int64_t)h.near_int;
+    t.n_near_int = -1;  // counted on request (near_interactions)
     t.n_items = h.items;
     t.n_partial = h.partial;
     t.walk_valid = true;
     t.walk_theta = theta;
+}
+
+// Directed near particle interactions of the last walk (throughput
+// accounting): one pass over the sorted near entries, on the null stream
+// after the device is idle, counted once per walk.
+int64_t near_interactions(Tree& t) {
+    if (!t.walk_valid) return -1;
+    if (t.n_near_int >= 0) return t.n_near_int;
+    Ctx* ctx = t.ctx;
+    TFMM_HIP(hipDeviceSynchronize());
+    const int64_t ne = 2 * t.n_p2p - t.n_leaves;
+    unsigned long long* acc = &t.w_res.as<WalkTotals>()->near_int;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(TB), 0, nullptr, reinterpret_cast<int32_t*>(acc), 2, 0);
+    TFMM_LAUNCHED();
+    const unsigned nb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(ne, TB)));
+    hipLaunchKernelGGL(near_work_kernel, dim3(nb), dim3(TB), 0, nullptr, (const uint32_t*)t.w_tg.as<uint32_t>(),
+                       (const int32_t*)t.p2p_src.as<int32_t>(), ne, t.nd_count.as<int32_t>(), acc);
+    TFMM_LAUNCHED();
+    t.n_near_int = (int64_t)read_back(ctx, (const unsigned long long*)acc, nullptr);
+    return t.n_near_int;
 }
 
 }  // namespace tfmm
