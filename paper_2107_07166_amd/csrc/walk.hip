@@ -373,64 +373,52 @@ __global__ __launch_bounds__(TB) void entry_sources_kernel(const int32_t* __rest
     if (q < ne) c[q] = (uint32_t)count[src[q]];
 }
 
-__global__ __launch_bounds__(TB) void item_flag_kernel(const uint32_t* __restrict__ tgt,
-                                                       const uint32_t* __restrict__ P,
-                                                       const uint32_t* __restrict__ off, int64_t ne,
-                                                       uint32_t* __restrict__ flag) {
+// Items of a node's near list: entry q (list start q0) belongs to item
+// k = floor((P[q] - P[q0]) / kItemSources) of its leaf.  A source leaf holds
+// at most 4096 particles, so k grows by at most one per entry and a list
+// with last entry q1 - 1 has k_last + 1 items.  Only a leaf split into
+// several items needs partial-sum rows (one per item and target particle).
+__global__ __launch_bounds__(TB) void node_items_kernel(const uint32_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ P, int64_t nn,
+                                                        const int32_t* __restrict__ count,
+                                                        uint32_t* __restrict__ nitems, uint32_t* __restrict__ prows) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= nn) return;
+    const uint32_t q0 = off[i], q1 = off[i + 1];
+    const uint32_t n = (q1 > q0) ? (P[q1 - 1] - P[q0]) / kItemSources + 1u : 0u;
+    nitems[i] = n;
+    prows[i] = n > 1u ? n * (uint32_t)count[i] : 0u;
+}
+
+// One thread per near entry; the entry that starts an item writes it.
+__global__ __launch_bounds__(TB) void item_write_kernel(const uint32_t* __restrict__ tgt,
+                                                        const uint32_t* __restrict__ P,
+                                                        const uint32_t* __restrict__ off, int64_t ne,
+                                                        const uint32_t* __restrict__ nitems,
+                                                        const uint32_t* __restrict__ item0,
+                                                        const uint32_t* __restrict__ pbase,
+                                                        const int32_t* __restrict__ count,
+                                                        int32_t* __restrict__ it_leaf, uint32_t* __restrict__ it_q0,
+                                                        uint32_t* __restrict__ it_q1, uint32_t* __restrict__ it_pbase,
+                                                        int32_t* __restrict__ leaf_item0,
+                                                        int32_t* __restrict__ leaf_nitems) {
     const int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (q >= ne) return;
-    const uint32_t q0 = off[tgt[q]];
-    uint32_t f = 1u;
-    if ((uint32_t)q != q0) f = ((P[q] - P[q0]) / kItemSources != (P[q - 1] - P[q0]) / kItemSources) ? 1u : 0u;
-    flag[q] = f;
-}
-
-__global__ __launch_bounds__(TB) void item_build_kernel(const uint32_t* __restrict__ flag,
-                                                        const uint32_t* __restrict__ excl,
-                                                        const uint32_t* __restrict__ tgt, int64_t ne,
-                                                        int32_t* __restrict__ it_leaf, uint32_t* __restrict__ it_q0) {
-    const int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (q >= ne || !flag[q]) return;
-    const uint32_t i = excl[q];
+    const uint32_t L = tgt[q];
+    const uint32_t q0 = off[L];
+    const uint32_t k = (P[q] - P[q0]) / kItemSources;
+    if ((uint32_t)q != q0 && k == (P[q - 1] - P[q0]) / kItemSources) return;
+    const uint32_t n = nitems[L];
+    const uint32_t i = item0[L] + k;
+    it_leaf[i] = (int32_t)L;
     it_q0[i] = (uint32_t)q;
-    it_leaf[i] = (int32_t)tgt[q];
-}
-
-// The item count T is read on the device (the host only knows ne >= T).
-// Entries i >= T get pc = 0 so that a scan over all ne slots yields the
-// partial-sum offsets of the items and their total.
-__global__ __launch_bounds__(TB) void item_finish_kernel(const uint32_t* __restrict__ T_dev, int64_t ne,
-                                                         const uint32_t* __restrict__ it_q0,
-                                                         const int32_t* __restrict__ it_leaf,
-                                                         const int32_t* __restrict__ count,
-                                                         uint32_t* __restrict__ it_q1, uint32_t* __restrict__ pc,
-                                                         int32_t* __restrict__ leaf_item0) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i >= ne) return;
-    const int64_t T = *T_dev;
-    if (i >= T) {
-        pc[i] = 0u;
-        return;
+    if (k > 0u) it_q1[i - 1] = (uint32_t)q;
+    if (k + 1u == n) it_q1[i] = off[L + 1];
+    it_pbase[i] = n > 1u ? pbase[L] + k * (uint32_t)count[L] : 0u;
+    if (k == 0u) {
+        leaf_item0[L] = (int32_t)item0[L];
+        leaf_nitems[L] = (int32_t)n;
     }
-    it_q1[i] = (i + 1 < T) ? it_q0[i + 1] : (uint32_t)ne;
-    const int32_t L = it_leaf[i];
-    const bool first_of_leaf = (i == 0 || it_leaf[i - 1] != L);
-    const bool last_of_leaf = (i + 1 == T || it_leaf[i + 1] != L);
-    // a leaf with a single item writes its result directly: no partial space
-    pc[i] = (first_of_leaf && last_of_leaf) ? 0u : (uint32_t)count[L];
-    if (first_of_leaf) leaf_item0[L] = (int32_t)i;
-}
-
-__global__ __launch_bounds__(TB) void item_count_kernel(const uint32_t* __restrict__ T_dev, int64_t ne,
-                                                        const int32_t* __restrict__ it_leaf,
-                                                        const int32_t* __restrict__ leaf_item0,
-                                                        int32_t* __restrict__ leaf_nitems) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i >= ne) return;
-    const int64_t T = *T_dev;
-    if (i >= T) return;
-    const int32_t L = it_leaf[i];
-    if (i + 1 == T || it_leaf[i + 1] != L) leaf_nitems[L] = (int32_t)(i + 1 - leaf_item0[L]);
 }
 
 unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, TB); }
@@ -667,22 +655,27 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
                            (const uint32_t*)o, tg.as<uint32_t>(), sr.as<int32_t>());
         TFMM_LAUNCHED();
         build_csr(t, tg, sr, ne, t.p2p_off, t.p2p_src, s);
-        // work items over the sorted near entries (tg holds the sorted targets);
-        // there are at most ne items, so every item array is sized by ne
-        t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 16);
+        // work items over the sorted near entries (tg holds the sorted targets)
+        t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8);
         uint32_t* ec = t.w_c.as<uint32_t>();
         uint32_t* P = ec + std::max<int64_t>(ne, 1);
-        uint32_t* fl = P + std::max<int64_t>(ne, 1);
-        uint32_t* ex = fl + std::max<int64_t>(ne, 1);
         t.scratch.ensure(ctx, scan_scratch_bytes(ne) + 256);
         hipLaunchKernelGGL(entry_sources_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const int32_t*)t.p2p_src.as<int32_t>(),
                            ne, t.nd_count.as<int32_t>(), ec);
         TFMM_LAUNCHED();
         exclusive_scan_u32(ec, P, ne, t.scratch.p, junk, ctx->dev_err, s);
-        hipLaunchKernelGGL(item_flag_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
-                           (const uint32_t*)P, (const uint32_t*)t.p2p_off.as<uint32_t>(), ne, fl);
+        // per node: items and partial rows, then their offsets
+        t.w_fl.ensure(ctx, (size_t)(nn + 1) * 16);
+        uint32_t* nit = t.w_fl.as<uint32_t>();
+        uint32_t* it0 = nit + (nn + 1);
+        uint32_t* prw = it0 + (nn + 1);
+        uint32_t* pbs = prw + (nn + 1);
+        hipLaunchKernelGGL(node_items_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)t.p2p_off.as<uint32_t>(),
+                           (const uint32_t*)P, nn, t.nd_count.as<int32_t>(), nit, prw);
         TFMM_LAUNCHED();
-        exclusive_scan_u32(fl, ex, ne, t.scratch.p, &res->items, ctx->dev_err, s);
+        exclusive_scan_u32(nit, it0, nn, t.scratch.p, &res->items, ctx->dev_err, s);
+        exclusive_scan_u32(prw, pbs, nn, t.scratch.p, &res->partial, ctx->dev_err, s);
+        // there are at most ne items, so every item array is sized by ne
         const size_t ni = (size_t)std::max<int64_t>(ne, 1);
         t.it_leaf.ensure(ctx, ni * 4);
         t.it_q0.ensure(ctx, ni * 4);
@@ -690,19 +683,12 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         t.it_pbase.ensure(ctx, ni * 4);
         t.leaf_item0.ensure(ctx, (size_t)(nn + 1) * 4);
         t.leaf_nitems.ensure(ctx, (size_t)(nn + 1) * 4);
-        hipLaunchKernelGGL(item_build_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)fl, (const uint32_t*)ex,
-                           (const uint32_t*)tg.as<uint32_t>(), ne, t.it_leaf.as<int32_t>(), t.it_q0.as<uint32_t>());
+        hipLaunchKernelGGL(item_write_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
+                           (const uint32_t*)P, (const uint32_t*)t.p2p_off.as<uint32_t>(), ne, (const uint32_t*)nit,
+                           (const uint32_t*)it0, (const uint32_t*)pbs, t.nd_count.as<int32_t>(),
+                           t.it_leaf.as<int32_t>(), t.it_q0.as<uint32_t>(), t.it_q1.as<uint32_t>(),
+                           t.it_pbase.as<uint32_t>(), t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>());
         TFMM_LAUNCHED();
-        // per-item partial sizes reuse the entry-count scratch
-        hipLaunchKernelGGL(item_finish_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)&res->items, ne,
-                           (const uint32_t*)t.it_q0.as<uint32_t>(), (const int32_t*)t.it_leaf.as<int32_t>(),
-                           t.nd_count.as<int32_t>(), t.it_q1.as<uint32_t>(), ec, t.leaf_item0.as<int32_t>());
-        TFMM_LAUNCHED();
-        hipLaunchKernelGGL(item_count_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)&res->items, ne,
-                           (const int32_t*)t.it_leaf.as<int32_t>(), (const int32_t*)t.leaf_item0.as<int32_t>(),
-                           t.leaf_nitems.as<int32_t>());
-        TFMM_LAUNCHED();
-        exclusive_scan_u32(ec, t.it_pbase.as<uint32_t>(), ne, t.scratch.p, &res->partial, ctx->dev_err, s);
     }
     const WalkTotals h = read_back_checked(ctx, (const WalkTotals*)res, s);
     if ((int64_t)h.near_entries != ne)
