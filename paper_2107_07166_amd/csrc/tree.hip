@@ -374,48 +374,76 @@ __global__ __launch_bounds__(TB) void leaf_compact_kernel(const uint32_t* __rest
     if (i < nn && flag[i]) leaves[excl[i]] = (int32_t)i;
 }
 
-// Mass and centre of mass of the nodes of one level (children done before).
-__global__ __launch_bounds__(TB) void geometry_level_kernel(const int32_t* __restrict__ first,
-                                                            const int32_t* __restrict__ count,
-                                                            const int32_t* __restrict__ child_first,
-                                                            const int32_t* __restrict__ nchild,
-                                                            const double4* __restrict__ Xm, int32_t lb,
-                                                            int32_t le, double4* __restrict__ S,
-                                                            double4* __restrict__ Z) {
-    const int32_t i = lb + blockIdx.x * TB + threadIdx.x;
-    if (i >= le) return;
+// Mass and centre of mass of the leaves (all levels in one launch).
+__global__ __launch_bounds__(TB) void geometry_leaf_kernel(const int32_t* __restrict__ leaves, int64_t n_leaves,
+                                                           const int32_t* __restrict__ first,
+                                                           const int32_t* __restrict__ count,
+                                                           const double4* __restrict__ Xm, double4* __restrict__ S,
+                                                           double4* __restrict__ Z) {
+    const int64_t l = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (l >= n_leaves) return;
+    const int32_t i = leaves[l];
     double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-    const int32_t nc = nchild[i];
-    if (nc == 0) {
-        // loads issued eight at a time, sums kept strictly left to right
-        const int32_t s0 = first[i], s1 = s0 + count[i];
-        for (int32_t s = s0; s < s1; s += 8) {
-            double4 p[8];
+    // loads issued eight at a time, sums kept strictly left to right
+    const int32_t s0 = first[i], s1 = s0 + count[i];
+    for (int32_t q = s0; q < s1; q += 8) {
+        double4 p[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (s + u < s1) p[u] = Xm[s + u];
+        for (int u = 0; u < 8; ++u)
+            if (q + u < s1) p[u] = Xm[q + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (s + u < s1) {
-                    M = M + p[u].w;
-                    sx = sx + p[u].w * p[u].x;
-                    sy = sy + p[u].w * p[u].y;
-                    sz = sz + p[u].w * p[u].z;
-                }
+        for (int u = 0; u < 8; ++u) {
+            if (q + u < s1) {
+                M = M + p[u].w;
+                sx = sx + p[u].w * p[u].x;
+                sy = sy + p[u].w * p[u].y;
+                sz = sz + p[u].w * p[u].z;
             }
-        }
-    } else {
-        const int32_t c0 = child_first[i];
-        for (int32_t c = c0; c < c0 + nc; ++c) {
-            const double4 q = S[c];
-            M = M + q.w;
-            sx = sx + q.x;
-            sy = sy + q.y;
-            sz = sz + q.z;
         }
     }
     S[i] = make_double4(sx, sy, sz, M);
     Z[i] = make_double4(sx / M, sy / M, sz / M, M);
+}
+
+// Inner node: sums over its children in digit order.
+__device__ __forceinline__ void geometry_inner(int32_t i, const int32_t* __restrict__ child_first,
+                                               const int32_t* __restrict__ nchild, double4* __restrict__ S,
+                                               double4* __restrict__ Z) {
+    const int32_t nc = nchild[i];
+    if (nc == 0) return;  // a leaf: done by geometry_leaf_kernel
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    const int32_t c0 = child_first[i];
+    for (int32_t c = c0; c < c0 + nc; ++c) {
+        const double4 q = S[c];
+        M = M + q.w;
+        sx = sx + q.x;
+        sy = sy + q.y;
+        sz = sz + q.z;
+    }
+    S[i] = make_double4(sx, sy, sz, M);
+    Z[i] = make_double4(sx / M, sy / M, sz / M, M);
+}
+
+// Inner nodes of one level (the level below is done).
+__global__ __launch_bounds__(TB) void geometry_level_kernel(const int32_t* __restrict__ child_first,
+                                                            const int32_t* __restrict__ nchild, int32_t lb,
+                                                            int32_t le, double4* __restrict__ S,
+                                                            double4* __restrict__ Z) {
+    const int32_t i = lb + blockIdx.x * TB + threadIdx.x;
+    if (i < le) geometry_inner(i, child_first, nchild, S, Z);
+}
+
+// Inner nodes of the top levels 0..top in one block, deepest first.
+struct LevelBounds {
+    int32_t b[kLevels + 2];
+};
+__global__ __launch_bounds__(TB) void geometry_top_kernel(const int32_t* __restrict__ child_first,
+                                                          const int32_t* __restrict__ nchild, LevelBounds lv, int top,
+                                                          double4* __restrict__ S, double4* __restrict__ Z) {
+    for (int L = top; L >= 0; --L) {
+        for (int32_t i = lv.b[L] + (int32_t)threadIdx.x; i < lv.b[L + 1]; i += TB) geometry_inner(i, child_first, nchild, S, Z);
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(TB) void fill_u64_kernel(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
@@ -635,16 +663,32 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
                        (const uint32_t*)excl, nn, t.leaves.as<int32_t>());
     TFMM_LAUNCHED();
 
-    // geometry, deepest level first
+    // geometry: leaves, then inner nodes level by level, deepest first; the
+    // top levels (at most kTopNodes nodes together) in a single block
     t.nd_S.ensure(ctx, (size_t)nn * 32);
     t.nd_Z.ensure(ctx, (size_t)nn * 32);
-    for (int L = t.max_level; L >= 0; --L) {
-        const int32_t b = (int32_t)t.level_begin[L], e = (int32_t)t.level_begin[L + 1];
-        if (e <= b) continue;
-        hipLaunchKernelGGL(geometry_level_kernel, dim3(grid(e - b)), dim3(TB), 0, s, nd.first, nd.count,
-                           nd.child_first, nd.nchild, t.Xm.as<double4>(), b, e, t.nd_S.as<double4>(),
-                           t.nd_Z.as<double4>());
-        TFMM_LAUNCHED();
+    hipLaunchKernelGGL(geometry_leaf_kernel, dim3(grid(t.n_leaves)), dim3(TB), 0, s,
+                       (const int32_t*)t.leaves.as<int32_t>(), t.n_leaves, nd.first, nd.count, t.Xm.as<double4>(),
+                       t.nd_S.as<double4>(), t.nd_Z.as<double4>());
+    TFMM_LAUNCHED();
+    {
+        constexpr int64_t kTopNodes = 1024;
+        int top = -1;
+        while (top + 1 <= t.max_level && t.level_begin[(size_t)top + 2] <= kTopNodes) ++top;
+        for (int L = t.max_level - 1; L > top; --L) {
+            const int32_t b = (int32_t)t.level_begin[L], e = (int32_t)t.level_begin[L + 1];
+            if (e <= b) continue;
+            hipLaunchKernelGGL(geometry_level_kernel, dim3(grid(e - b)), dim3(TB), 0, s, nd.child_first, nd.nchild,
+                               b, e, t.nd_S.as<double4>(), t.nd_Z.as<double4>());
+            TFMM_LAUNCHED();
+        }
+        if (top >= 0) {
+            LevelBounds lv{};
+            for (int L = 0; L <= top + 1; ++L) lv.b[L] = (int32_t)t.level_begin[L];
+            hipLaunchKernelGGL(geometry_top_kernel, dim3(1), dim3(TB), 0, s, nd.child_first, nd.nchild, lv, top,
+                               t.nd_S.as<double4>(), t.nd_Z.as<double4>());
+            TFMM_LAUNCHED();
+        }
     }
     t.nd_r2bits.ensure(ctx, (size_t)nn * 8);
     t.nd_rmax.ensure(ctx, (size_t)nn * 8);
