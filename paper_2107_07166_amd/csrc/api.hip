@@ -367,6 +367,11 @@ int tfmm_tree_destroy(tfmm_tree* tree) {
     (void)hipDeviceSynchronize();
     if (tree->ev_ready)
         for (auto& e : tree->ev) (void)hipEventDestroy(e);
+    if (tree->aux) {
+        (void)hipEventDestroy(tree->fork_ev);
+        (void)hipEventDestroy(tree->join_ev);
+        (void)hipStreamDestroy(tree->aux);
+    }
     delete tree;
     ctx->live_trees--;
     return TFMM_OK;

@@ -133,6 +133,13 @@ struct Tree {
     DevBuf scratch;               // scans and sorts
     DevBuf scratch2;
 
+    // a second stream for independent chains of kernels (the far- and
+    // near-list builds of a walk), forked from and joined to the caller's
+    // stream with events; default priority
+    hipStream_t aux = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    DevBuf scratch_b, scratch2_b, w_tg_b, w_sr_b;  // the near-list chain's own scratch
+
     // timing
     bool timing = false;
     hipEvent_t ev[8] = {};

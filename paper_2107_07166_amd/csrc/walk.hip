@@ -441,16 +441,15 @@ V read_back(Ctx* ctx, const V* dev, hipStream_t s) {
 // Stable sort of directed (target, source) entries by target, then CSR
 // offsets from the sorted targets.  The sources of every target stay in the
 // walk's emission order.
-void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& off, DevBuf& srcout,
-               hipStream_t s) {
+void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& off, DevBuf& srcout, DevBuf& scr,
+               DevBuf& scr2, hipStream_t s) {
     Ctx* ctx = t.ctx;
     const int64_t nn = t.n_nodes;
-    t.scratch2.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8 + 256);
-    uint32_t* kalt = t.scratch2.as<uint32_t>();
+    scr2.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8 + 256);
+    uint32_t* kalt = scr2.as<uint32_t>();
     int32_t* valt = reinterpret_cast<int32_t*>(kalt + std::max<int64_t>(ne, 1));
-    t.scratch.ensure(ctx, sort_scratch_bytes(ne, bits_for(nn)) + 1024);
-    radix_sort_u32(tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(), kalt, valt, ne, bits_for(nn), t.scratch.p, ctx->dev_err,
-                   s);
+    scr.ensure(ctx, sort_scratch_bytes(ne, bits_for(nn)) + 1024);
+    radix_sort_u32(tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(), kalt, valt, ne, bits_for(nn), scr.p, ctx->dev_err, s);
     off.ensure(ctx, (size_t)(nn + 1) * 4);
     hipLaunchKernelGGL(csr_offsets_kernel, dim3((unsigned)std::min<int64_t>(2048, grid(ne + 1))), dim3(TB), 0, s,
                        (const uint32_t*)tgtbuf.as<uint32_t>(),
@@ -459,6 +458,22 @@ void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& off,
     std::swap(srcbuf.p, srcout.p);
     std::swap(srcbuf.cap, srcout.cap);
     std::swap(srcbuf.ctx, srcout.ctx);
+}
+
+// Fork the tree's second stream from s / join it back into s.
+void aux_fork(Tree& t, hipStream_t s) {
+    if (!t.aux) {
+        TFMM_HIP(hipStreamCreateWithFlags(&t.aux, hipStreamNonBlocking));
+        TFMM_HIP(hipEventCreateWithFlags(&t.fork_ev, hipEventDisableTiming));
+        TFMM_HIP(hipEventCreateWithFlags(&t.join_ev, hipEventDisableTiming));
+    }
+    TFMM_HIP(hipEventRecord(t.fork_ev, s));
+    TFMM_HIP(hipStreamWaitEvent(t.aux, t.fork_ev, 0));
+}
+
+void aux_join(Tree& t, hipStream_t s) {
+    TFMM_HIP(hipEventRecord(t.join_ev, t.aux));
+    TFMM_HIP(hipStreamWaitEvent(s, t.join_ev, 0));
 }
 
 // Frontier passes sized on the host: the totals of every pass are read back
@@ -624,20 +639,26 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
     TFMM_LAUNCHED();
     uint32_t* junk = res->scratch;
 
-    DevBuf& tg = t.w_tg;
-    DevBuf& sr = t.w_sr;
+    // The far-list chain runs on the tree's second stream, the near-list chain
+    // on s; they share no buffer.
+    aux_fork(t, s);
     // far lists: directed, by target
     {
+        DevBuf& tg = t.w_tg;
+        DevBuf& sr = t.w_sr;
+        const hipStream_t fs = t.aux;
         const int64_t ne = 2 * n_far;
         tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         if (n_far > 0) {
-            hipLaunchKernelGGL(far_entries_kernel, dim3(grid(n_far)), dim3(TB), 0, s, t.m2l_pairs.as<int2>(),
+            hipLaunchKernelGGL(far_entries_kernel, dim3(grid(n_far)), dim3(TB), 0, fs, t.m2l_pairs.as<int2>(),
                                n_far, tg.as<uint32_t>(), sr.as<int32_t>());
             TFMM_LAUNCHED();
         }
-        build_csr(t, tg, sr, ne, t.m2l_off, t.m2l_src, s);
+        build_csr(t, tg, sr, ne, t.m2l_off, t.m2l_src, t.scratch, t.scratch2, fs);
     }
+    DevBuf& tg = t.w_tg_b;
+    DevBuf& sr = t.w_sr_b;
     // near lists: directed (self pairs once), by target.  Every leaf has
     // exactly one self pair, so the entry count is 2 n_near - n_leaves.
     const int64_t ne = 2 * n_near - t.n_leaves;
@@ -647,23 +668,23 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         uint32_t* o = c + std::max<int64_t>(n_near, 1);
         hipLaunchKernelGGL(near_count_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near, c);
         TFMM_LAUNCHED();
-        t.scratch.ensure(ctx, scan_scratch_bytes(n_near) + 256);
-        exclusive_scan_u32(c, o, n_near, t.scratch.p, &res->near_entries, ctx->dev_err, s);
+        t.scratch_b.ensure(ctx, scan_scratch_bytes(n_near) + 256);
+        exclusive_scan_u32(c, o, n_near, t.scratch_b.p, &res->near_entries, ctx->dev_err, s);
         tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         hipLaunchKernelGGL(near_entries_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near,
                            (const uint32_t*)o, tg.as<uint32_t>(), sr.as<int32_t>());
         TFMM_LAUNCHED();
-        build_csr(t, tg, sr, ne, t.p2p_off, t.p2p_src, s);
+        build_csr(t, tg, sr, ne, t.p2p_off, t.p2p_src, t.scratch_b, t.scratch2_b, s);
         // work items over the sorted near entries (tg holds the sorted targets)
         t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8);
         uint32_t* ec = t.w_c.as<uint32_t>();
         uint32_t* P = ec + std::max<int64_t>(ne, 1);
-        t.scratch.ensure(ctx, scan_scratch_bytes(ne) + 256);
+        t.scratch_b.ensure(ctx, scan_scratch_bytes(ne) + 256);
         hipLaunchKernelGGL(entry_sources_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const int32_t*)t.p2p_src.as<int32_t>(),
                            ne, t.nd_count.as<int32_t>(), ec);
         TFMM_LAUNCHED();
-        exclusive_scan_u32(ec, P, ne, t.scratch.p, junk, ctx->dev_err, s);
+        exclusive_scan_u32(ec, P, ne, t.scratch_b.p, junk, ctx->dev_err, s);
         // per node: items and partial rows, then their offsets
         t.w_fl.ensure(ctx, (size_t)(nn + 1) * 16);
         uint32_t* nit = t.w_fl.as<uint32_t>();
@@ -673,8 +694,8 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
         hipLaunchKernelGGL(node_items_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)t.p2p_off.as<uint32_t>(),
                            (const uint32_t*)P, nn, t.nd_count.as<int32_t>(), nit, prw);
         TFMM_LAUNCHED();
-        exclusive_scan_u32(nit, it0, nn, t.scratch.p, &res->items, ctx->dev_err, s);
-        exclusive_scan_u32(prw, pbs, nn, t.scratch.p, &res->partial, ctx->dev_err, s);
+        exclusive_scan_u32(nit, it0, nn, t.scratch_b.p, &res->items, ctx->dev_err, s);
+        exclusive_scan_u32(prw, pbs, nn, t.scratch_b.p, &res->partial, ctx->dev_err, s);
         // there are at most ne items, so every item array is sized by ne
         const size_t ni = (size_t)std::max<int64_t>(ne, 1);
         t.it_leaf.ensure(ctx, ni * 4);
@@ -690,6 +711,7 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
                            t.it_pbase.as<uint32_t>(), t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>());
         TFMM_LAUNCHED();
     }
+    aux_join(t, s);
     const WalkTotals h = read_back_checked(ctx, (const WalkTotals*)res, s);
     if ((int64_t)h.near_entries != ne)
         fail(TFMM_EDEVICE, "walk: near entry count " + std::to_string(h.near_entries) + " differs from " +
@@ -714,7 +736,7 @@ int64_t near_interactions(Tree& t) {
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(TB), 0, nullptr, reinterpret_cast<int32_t*>(acc), 2, 0);
     TFMM_LAUNCHED();
     const unsigned nb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(ne, TB)));
-    hipLaunchKernelGGL(near_work_kernel, dim3(nb), dim3(TB), 0, nullptr, (const uint32_t*)t.w_tg.as<uint32_t>(),
+    hipLaunchKernelGGL(near_work_kernel, dim3(nb), dim3(TB), 0, nullptr, (const uint32_t*)t.w_tg_b.as<uint32_t>(),
                        (const int32_t*)t.p2p_src.as<int32_t>(), ne, t.nd_count.as<int32_t>(), acc);
     TFMM_LAUNCHED();
     t.n_near_int = (int64_t)read_back(ctx, (const unsigned long long*)acc, nullptr);
