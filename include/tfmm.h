@@ -93,8 +93,8 @@ size_t tfmm_ctx_bytes_in_use(const tfmm_ctx *ctx);
  * axis over the bounding cube, stable sort, octree numbered level by level in
  * Morton order; per node FP64 mass, centre of mass and r_max (the exact
  * largest particle distance from the centre of mass, Eq. mac_criterion).
- * Synchronising (reads per-level sizes).  The tree keeps its own sorted copy
- * of pos and mass.  Errors: EINVAL, ENOMEM, EDEVICE. */
+ * Synchronising (reads the level boundaries back once).  The tree keeps its
+ * own sorted copy of pos and mass.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int tfmm_build_tree(tfmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
                     int n_leaf, void *stream, tfmm_tree **out);
 
@@ -113,7 +113,10 @@ int tfmm_tree_walk(tfmm_tree *tree, double theta, void *stream);
 /* Forces on every particle: force (device, n x 3 FP64 row-major, original
  * particle order) = G m_a (near + far) for the tree's particles.
  * potential: must be NULL (not provided).  Asynchronous except for the walk
- * when params->theta differs from the tree's last walk.
+ * when params->theta differs from the tree's last walk.  Part of the work
+ * runs on a second stream owned by the tree, forked from `stream` at the call
+ * and joined back into it before the forces are written, so the call is
+ * ordered on `stream` like a single kernel.
  * Errors: EINVAL (p outside 1..8, theta outside [0,1), eps < 0, bad variant
  * or precision, NULL force), ENOMEM, EDEVICE. */
 int tfmm_evaluate_forces(tfmm_tree *tree, const tfmm_params *params, double *force,
@@ -183,9 +186,11 @@ int tfmm_tree_destroy(tfmm_tree *tree);
 size_t tfmm_footprint_bytes(int64_t n, int p, int n_leaf, int precision);
 
 /* Per-phase device times (milliseconds) of the last tfmm_evaluate_forces on
- * this tree, measured with HIP events on its stream when timing is enabled
- * (tfmm_tree_set_timing): out[0] M2L, [1] P2P, [2] L2L, [3] L2P, [4] moments,
- * [5] whole evaluation.  Synchronising.  Errors: EINVAL, ESTATE. */
+ * this tree, measured with HIP events on the stream each phase runs on when
+ * timing is enabled (tfmm_tree_set_timing): out[0] M2L, [1] P2P, [2] L2L,
+ * [3] L2P, [4] moments (moments, M2L and L2L run on the tree's second stream,
+ * P2P and L2P on the caller's), [5] whole evaluation (including a walk if one
+ * was needed).  Synchronising.  Errors: EINVAL, ESTATE. */
 int tfmm_tree_set_timing(tfmm_tree *tree, int enable);
 int tfmm_tree_phase_times(tfmm_tree *tree, double *out);
 

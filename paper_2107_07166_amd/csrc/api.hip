@@ -101,23 +101,36 @@ void check_params(const tfmm_params* p) {
     if (p->precision != TFMM_FP64 && p->precision != TFMM_MIXED32) fail(TFMM_EINVAL, "unknown precision");
 }
 
+// Two streams: s (the caller's) and the tree's second stream a.
+//   a: moments (during the frontier passes) -> far-list chain -> M2L -> L2L
+//   s: sources -> frontier passes -> near-list chain -> [join a] -> P2P -> L2P
+// The latency-bound chains hide behind each other; P2P runs after the join,
+// alone on the device.
 void evaluate(Tree& t, const tfmm_params* prm, double* force, hipStream_t s) {
-    if (!t.walk_valid || t.walk_theta != prm->theta) walk_tree(t, prm->theta, s);
+    const bool need_walk = !t.walk_valid || t.walk_theta != prm->theta;
     const double eps2 = prm->softening * prm->softening;
-    if (t.timing) {
-        if (!t.ev_ready) {
-            for (auto& e : t.ev) TFMM_HIP(hipEventCreate(&e));
-            t.ev_ready = true;
-        }
-        TFMM_HIP(hipEventRecord(t.ev[0], s));
+    if (t.timing && !t.ev_ready) {
+        for (auto& e : t.ev) TFMM_HIP(hipEventCreate(&e));
+        t.ev_ready = true;
     }
-    compute_moments(t, prm->p, s);
+    aux_fork(t, s);
+    const hipStream_t a = t.aux;
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[0], a));
+    compute_moments(t, prm->p, a);
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[1], a));
     prepare_sources(t, prm->precision, s);
-    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[1], s));
-    run_m2l(t, prm->p, prm->variant, prm->precision, eps2, s);
-    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[2], s));
-    run_l2l(t, prm->p, prm->variant, s);
-    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[3], s));
+    if (need_walk) {
+        t.walk_valid = false;
+        walk_lists_begin(t, prm->theta, s);
+    }
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[7], a));
+    run_m2l(t, prm->p, prm->variant, prm->precision, eps2, a);
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[2], a));
+    run_l2l(t, prm->p, prm->variant, a);
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[3], a));
+    if (need_walk) walk_lists_end(t, s);
+    aux_join(t, s);
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[6], s));
     run_p2p(t, prm->precision, eps2, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[4], s));
     run_l2p(t, prm->p, prm->variant, prm->G, force, s);
@@ -403,16 +416,19 @@ int tfmm_tree_phase_times(tfmm_tree* tree, double* out) {
         Tree& t = *tree;
         if (!t.have_times) fail(TFMM_ESTATE, "no timed evaluation on this tree");
         TFMM_HIP(hipEventSynchronize(t.ev[5]));
-        float ms[5];
-        for (int i = 0; i < 5; ++i) TFMM_HIP(hipEventElapsedTime(&ms[i], t.ev[i], t.ev[i + 1]));
-        float all = 0;
-        TFMM_HIP(hipEventElapsedTime(&all, t.ev[0], t.ev[5]));
-        out[0] = ms[1];  // M2L
-        out[1] = ms[3];  // P2P
-        out[2] = ms[2];  // L2L
-        out[3] = ms[4];  // L2P
-        out[4] = ms[0];  // moments + sources
-        out[5] = all;
+        // events: moments [0,1], M2L [7,2], L2L [2,3] on the tree's second
+        // stream; P2P [6,4], L2P [4,5] on the caller's stream
+        auto el = [&](int i, int j) {
+            float ms = 0.f;
+            TFMM_HIP(hipEventElapsedTime(&ms, t.ev[i], t.ev[j]));
+            return (double)ms;
+        };
+        out[0] = el(7, 2);  // M2L
+        out[1] = el(6, 4);  // P2P
+        out[2] = el(2, 3);  // L2L
+        out[3] = el(4, 5);  // L2P
+        out[4] = el(0, 1);  // moments
+        out[5] = el(0, 5);  // whole evaluation after the tree build
     });
 }
 

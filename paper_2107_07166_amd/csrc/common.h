@@ -186,6 +186,10 @@ V read_back_checked(Ctx* ctx, const V* dev, hipStream_t s) {
 // ---- phases ---------------------------------------------------------------
 void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s);
 void walk_tree(Tree& t, double theta, hipStream_t s);
+void walk_lists_begin(Tree& t, double theta, hipStream_t s);
+void walk_lists_end(Tree& t, hipStream_t s);
+void aux_fork(Tree& t, hipStream_t s);
+void aux_join(Tree& t, hipStream_t s);
 int64_t near_interactions(Tree& t);
 void compute_moments(Tree& t, int p, hipStream_t s);
 void prepare_sources(Tree& t, int precision, hipStream_t s);

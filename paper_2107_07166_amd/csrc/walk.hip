@@ -460,22 +460,6 @@ void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& off,
     std::swap(srcbuf.ctx, srcout.ctx);
 }
 
-// Fork the tree's second stream from s / join it back into s.
-void aux_fork(Tree& t, hipStream_t s) {
-    if (!t.aux) {
-        TFMM_HIP(hipStreamCreateWithFlags(&t.aux, hipStreamNonBlocking));
-        TFMM_HIP(hipEventCreateWithFlags(&t.fork_ev, hipEventDisableTiming));
-        TFMM_HIP(hipEventCreateWithFlags(&t.join_ev, hipEventDisableTiming));
-    }
-    TFMM_HIP(hipEventRecord(t.fork_ev, s));
-    TFMM_HIP(hipStreamWaitEvent(t.aux, t.fork_ev, 0));
-}
-
-void aux_join(Tree& t, hipStream_t s) {
-    TFMM_HIP(hipEventRecord(t.join_ev, t.aux));
-    TFMM_HIP(hipStreamWaitEvent(s, t.join_ev, 0));
-}
-
 // Frontier passes sized on the host: the totals of every pass are read back
 // and the buffers grown before its outputs are written.  Used for the first
 // walk of a tree and whenever the unsynchronised passes ran out of room.
@@ -621,7 +605,26 @@ struct WalkTotals {
 
 }  // namespace
 
-void walk_tree(Tree& t, double theta, hipStream_t s) {
+// Fork the tree's second stream from s / join it back into s.
+void aux_fork(Tree& t, hipStream_t s) {
+    if (!t.aux) {
+        TFMM_HIP(hipStreamCreateWithFlags(&t.aux, hipStreamNonBlocking));
+        TFMM_HIP(hipEventCreateWithFlags(&t.fork_ev, hipEventDisableTiming));
+        TFMM_HIP(hipEventCreateWithFlags(&t.join_ev, hipEventDisableTiming));
+    }
+    TFMM_HIP(hipEventRecord(t.fork_ev, s));
+    TFMM_HIP(hipStreamWaitEvent(t.aux, t.fork_ev, 0));
+}
+
+void aux_join(Tree& t, hipStream_t s) {
+    TFMM_HIP(hipEventRecord(t.join_ev, t.aux));
+    TFMM_HIP(hipStreamWaitEvent(s, t.join_ev, 0));
+}
+
+// The frontier passes on s, then the far-list chain on the tree's second
+// stream (after the passes) and the near-list chain on s.  walk_lists_end
+// reads the totals back once the near chain is done.
+void walk_lists_begin(Tree& t, double theta, hipStream_t s) {
     Ctx* ctx = t.ctx;
     const int64_t nn = t.n_nodes;
     WalkNodes w{t.nd_level.as<int32_t>(), t.nd_child_first.as<int32_t>(), t.nd_nchild.as<int32_t>(),
@@ -711,8 +714,13 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
                            t.it_pbase.as<uint32_t>(), t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>());
         TFMM_LAUNCHED();
     }
-    aux_join(t, s);
-    const WalkTotals h = read_back_checked(ctx, (const WalkTotals*)res, s);
+    t.walk_theta = theta;
+}
+
+void walk_lists_end(Tree& t, hipStream_t s) {
+    Ctx* ctx = t.ctx;
+    const int64_t ne = 2 * t.n_p2p - t.n_leaves;
+    const WalkTotals h = read_back_checked(ctx, t.w_res.as<WalkTotals>(), s);
     if ((int64_t)h.near_entries != ne)
         fail(TFMM_EDEVICE, "walk: near entry count " + std::to_string(h.near_entries) + " differs from " +
                                std::to_string(ne));
@@ -720,7 +728,12 @@ void walk_tree(Tree& t, double theta, hipStream_t s) {
     t.n_items = h.items;
     t.n_partial = h.partial;
     t.walk_valid = true;
-    t.walk_theta = theta;
+}
+
+void walk_tree(Tree& t, double theta, hipStream_t s) {
+    walk_lists_begin(t, theta, s);
+    aux_join(t, s);
+    walk_lists_end(t, s);
 }
 
 // Directed near particle interactions of the last walk (throughput
