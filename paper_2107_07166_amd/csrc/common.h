@@ -81,9 +81,9 @@ struct Tree {
     int64_t n_nodes = 0, n_leaves = 0;
     int max_level = 0;
     std::vector<int64_t> level_begin;  // node index range of each level, size max_level + 2
-    double bbox[5] = {0, 0, 0, 0, 0};  // lo x/y/z, ext, scale
 
     // particles (sorted order unless noted)
+    DevBuf cube;               // FP64 key cube: lo x/y/z, hi x/y/z, ext, scale, non-finite flag
     DevBuf keys, keys2;        // uint64 Morton keys
     DevBuf perm, perm2;        // int32 sorted position -> original index
     DevBuf lvlb;               // uint8 level at which a key boundary appears before position j

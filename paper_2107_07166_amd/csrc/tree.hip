@@ -29,15 +29,21 @@ constexpr uint32_t QMAX = (1u << kLevels) - 1u;
 __global__ __launch_bounds__(TB) void bbox_partial_kernel(const double* __restrict__ pos, int64_t n,
                                                           double* __restrict__ part) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
     for (int64_t a = (int64_t)blockIdx.x * TB + threadIdx.x; a < n; a += (int64_t)gridDim.x * TB) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const double v = pos[3 * a + d];
+            bad |= !isfinite(v);
             lo[d] = v < lo[d] ? v : lo[d];
             hi[d] = v > hi[d] ? v : hi[d];
         }
     }
     __shared__ double sh[6][TB];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    if (bad) s_bad = 1;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         sh[d][threadIdx.x] = lo[d];
@@ -55,17 +61,25 @@ __global__ __launch_bounds__(TB) void bbox_partial_kernel(const double* __restri
         }
         __syncthreads();
     }
-    if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < 6) part[7 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x == 6) part[7 * blockIdx.x + 6] = s_bad ? 1.0 : 0.0;
 }
 
+// The cube of the keys: out[0..2] lo, [3..5] hi, [6] ext = the largest
+// extent (1 if all extents are 0), [7] scale = 2^21 / ext, [8] 1 if any
+// coordinate is not finite.  Exact FP64 operations, no contraction.
 __global__ __launch_bounds__(TB) void bbox_final_kernel(const double* __restrict__ part, int nb,
                                                         double* __restrict__ out) {
     __shared__ double sh[6][TB];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
     double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     for (int b = threadIdx.x; b < nb; b += TB) {
+        if (part[7 * b + 6] != 0.0) s_bad = 1;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const double lo = part[6 * b + d], hi = part[6 * b + 3 + d];
+            const double lo = part[7 * b + d], hi = part[7 * b + 3 + d];
             v[d] = lo < v[d] ? lo : v[d];
             v[3 + d] = hi > v[3 + d] ? hi : v[3 + d];
         }
@@ -85,6 +99,18 @@ __global__ __launch_bounds__(TB) void bbox_final_kernel(const double* __restrict
         __syncthreads();
     }
     if (threadIdx.x < 6) out[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x == 0) {
+        double ext = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double e = sh[3 + d][0] - sh[d][0];
+            if (e > ext) ext = e;
+        }
+        if (ext == 0.0) ext = 1.0;
+        const double scale = 2097152.0 / ext;
+        out[6] = ext;
+        out[7] = scale;
+        out[8] = (s_bad || !isfinite(ext) || !isfinite(scale)) ? 1.0 : 0.0;
+    }
 }
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v) {
@@ -97,12 +123,13 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
     return x;
 }
 
-__global__ __launch_bounds__(TB) void morton_kernel(const double* __restrict__ pos, int64_t n, double lox,
-                                                    double loy, double loz, double scale,
-                                                    uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
+__global__ __launch_bounds__(TB) void morton_kernel(const double* __restrict__ pos, int64_t n,
+                                                    const double* __restrict__ cube, uint64_t* __restrict__ keys,
+                                                    int32_t* __restrict__ idx) {
     const int64_t a = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (a >= n) return;
-    const double lo[3] = {lox, loy, loz};
+    const double lo[3] = {cube[0], cube[1], cube[2]};
+    const double scale = cube[7];
     uint32_t q[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -261,10 +288,13 @@ __global__ __launch_bounds__(TB) void slot_scan_kernel(uint32_t* __restrict__ cn
 struct TreeHeader {
     int64_t LB[kLevels + 2];  // first node id of levels 0..21, then the node count
     int64_t max_level, n_nodes, n_leaves;
+    int64_t nonfinite;        // a coordinate was not finite
 };
 
-__global__ void tree_header_kernel(const uint32_t* __restrict__ tot, TreeHeader* __restrict__ h) {
+__global__ void tree_header_kernel(const uint32_t* __restrict__ tot, const double* __restrict__ cube,
+                                   TreeHeader* __restrict__ h) {
     if (threadIdx.x != 0) return;
+    h->nonfinite = cube[8] != 0.0 ? 1 : 0;
     h->LB[0] = 0;
     h->LB[1] = 1;
     int64_t ml = 0;
@@ -558,42 +588,25 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     const int64_t n = t.n;
     const size_t un = (size_t)n;
 
-    // bounding cube (host computes ext and scale exactly as the key definition says)
+    // bounding cube and key scale, on the device (no read-back)
     const int nbb = (int)std::min<int64_t>(1024, cdiv(n, TB));
-    t.scratch.ensure(ctx, std::max<size_t>({(size_t)nbb * 6 * 8 + 64, sort_scratch_bytes(n, 3 * kLevels) + 256,
+    t.scratch.ensure(ctx, std::max<size_t>({(size_t)nbb * 7 * 8 + 64, sort_scratch_bytes(n, 3 * kLevels) + 256,
                                             scan_scratch_bytes(n) + 256}));
+    t.cube.ensure(ctx, 16 * sizeof(double));
     double* part = t.scratch.as<double>();
-    double* bb = part + 6 * nbb;
+    double* cube = t.cube.as<double>();
     hipLaunchKernelGGL(bbox_partial_kernel, dim3(nbb), dim3(TB), 0, s, pos, n, part);
     TFMM_LAUNCHED();
-    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(TB), 0, s, (const double*)part, nbb, bb);
+    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(TB), 0, s, (const double*)part, nbb, cube);
     TFMM_LAUNCHED();
-    TFMM_HIP(hipMemcpyAsync(ctx->pinned, bb, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
-    TFMM_HIP(hipStreamSynchronize(s));
-    double lohi[6];
-    std::memcpy(lohi, ctx->pinned, sizeof(lohi));
-    double ext = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        const volatile double e = lohi[3 + d] - lohi[d];
-        if (e > ext) ext = e;
-    }
-    if (ext == 0.0) ext = 1.0;
-    const volatile double scale = 2097152.0 / ext;
-    t.bbox[0] = lohi[0];
-    t.bbox[1] = lohi[1];
-    t.bbox[2] = lohi[2];
-    t.bbox[3] = ext;
-    t.bbox[4] = scale;
-    if (!std::isfinite(ext) || !std::isfinite((double)scale))
-        fail(TFMM_EINVAL, "positions contain non-finite values");
 
     // keys and stable order
     t.keys.ensure(ctx, un * 8);
     t.keys2.ensure(ctx, un * 8);
     t.perm.ensure(ctx, un * 4);
     t.perm2.ensure(ctx, un * 4);
-    hipLaunchKernelGGL(morton_kernel, dim3(grid(n)), dim3(TB), 0, s, pos, n, lohi[0], lohi[1], lohi[2],
-                       (double)scale, t.keys.as<uint64_t>(), t.perm.as<int32_t>());
+    hipLaunchKernelGGL(morton_kernel, dim3(grid(n)), dim3(TB), 0, s, pos, n, (const double*)cube,
+                       t.keys.as<uint64_t>(), t.perm.as<int32_t>());
     TFMM_LAUNCHED();
     radix_sort_u64(t.keys.as<uint64_t>(), t.perm.as<int32_t>(), t.keys2.as<uint64_t>(), t.perm2.as<int32_t>(),
                    n, 3 * kLevels, t.scratch.p, ctx->dev_err, s);
@@ -628,9 +641,10 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     TFMM_LAUNCHED();
     hipLaunchKernelGGL(slot_scan_kernel, dim3(NSLOT), dim3(TB), 0, s, cnt, nblk, tot);
     TFMM_LAUNCHED();
-    hipLaunchKernelGGL(tree_header_kernel, dim3(1), dim3(kWave), 0, s, (const uint32_t*)tot, hdr);
+    hipLaunchKernelGGL(tree_header_kernel, dim3(1), dim3(kWave), 0, s, (const uint32_t*)tot, (const double*)cube, hdr);
     TFMM_LAUNCHED();
     const TreeHeader H = read_back_checked(ctx, (const TreeHeader*)hdr, s);
+    if (H.nonfinite) fail(TFMM_EINVAL, "positions contain non-finite values");
     t.n_nodes = H.n_nodes;
     t.max_level = (int)H.max_level;
     t.n_leaves = H.n_leaves;

@@ -240,3 +240,22 @@ def test_full_size_plummer_1m(ctx):
             f = gt.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision=prec).cpu().numpy()
             assert _erms(f[sample], ref) <= tol, (variant, prec, _erms(f[sample], ref))
     gt.close()
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_nonfinite_positions_rejected(ctx, bad):
+    """A non-finite coordinate is an argument error (detected on the device,
+    reported with the tree's single read-back); the context stays usable."""
+    from paper_2107_07166_amd import api
+    pos, m = uniform_ball(1000, 11)
+    pos = pos.copy()
+    pos[17, 1] = bad
+    from paper_2107_07166_amd import _lib
+    with pytest.raises(api.TfmmError) as e:
+        _gpu_tree(ctx, pos, m, 16)
+    assert e.value.status == _lib.EINVAL and "non-finite" in str(e.value)
+    pos[17, 1] = 0.25
+    gt = _gpu_tree(ctx, pos, m, 16)
+    ot = oracle.Tree(pos, m, n_leaf=16, theta=0.5)
+    assert np.array_equal(gt.export()["keys"], ot.keys()[0])
+    gt.close()
