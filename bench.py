@@ -145,7 +145,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n-leaf", type=int, default=64)
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle force time")
+    ap.add_argument("--cpu-budget", type=float, default=18.0, help="seconds of oracle force time")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
