@@ -3,9 +3,12 @@
 Requests arrive over time (a Poisson trace); each asks for the forces on one
 particle set (N, p, theta, variant) or for the next leapfrog step of one of
 the persistent sessions.  The server keeps `slots` workers busy: as soon as a
-worker is free and the request at the head of the queue fits in the device
+worker is free and the solve at the head of the queue fits in the device
 memory budget (tfmm_footprint_bytes), it is admitted, so requests that arrive
-while others run start as slots and memory free up.  Every worker owns a
+while others run start as slots and memory free up.  Solves go first; a
+session step takes a free worker only while no admissible solve is waiting,
+and session steps hold at most `step_slots` workers at once (default half),
+so an arriving solve finds a worker ready.  Every worker owns a
 libtfmm context, its own HIP stream (default priority) and one reusable tree
 (device buffers are grow-only), so the work of several requests overlaps on
 the GPU.  Sessions keep particles and tree resident in HBM between steps and
@@ -137,8 +140,11 @@ class _Worker:
 
 class Server:
     def __init__(self, slots: int = 8, precision: str = "mixed32", budget_bytes: int = 64 << 30,
-                 n_leaf: int = 32, device: int = 0, sample_k: int = 16, keep_full: bool = False):
+                 n_leaf: int = 32, device: int = 0, sample_k: int = 16, keep_full: bool = False,
+                 step_slots: Optional[int] = None):
         self.slots = int(slots)
+        # most workers session steps may hold at once (the rest stay ready for solves)
+        self.step_slots = max(1, self.slots // 2) if step_slots is None else max(1, int(step_slots))
         self.precision = precision
         self.budget = int(budget_bytes)
         self.n_leaf = int(n_leaf)
@@ -158,7 +164,8 @@ class Server:
         sessions = sessions or []
         workers = [_Worker(i, self.device, self.n_leaf) for i in range(self.slots)]
         lock = threading.Condition()
-        pending = collections.deque()
+        pending = collections.deque()      # solves, FIFO
+        steps_q = collections.deque()      # session steps, FIFO
         records: List[Record] = []
         state = {"used": sum(session_footprint(s.n, s.params["p"], s.n_leaf, s.params["precision"])
                              for s in sessions),
@@ -168,7 +175,7 @@ class Server:
             raise MemoryError("the resident sessions alone exceed the memory budget")
         t0 = time.perf_counter()
         for k, s in enumerate(sessions):  # every session starts with one queued step
-            pending.append(Request(rid=state["next_step_id"] + k, arrival=0.0, kind="step", n=s.n, session=k,
+            steps_q.append(Request(rid=state["next_step_id"] + k, arrival=0.0, kind="step", n=s.n, session=k,
                                    p=s.params["p"], theta=s.params["theta"], variant=s.params["variant"],
                                    dt=session_dt))
         state["next_step_id"] += len(sessions)
@@ -199,7 +206,7 @@ class Server:
                 else:
                     busy_sessions.discard(req.session)
                     if state["solves_left"] > 0:
-                        pending.append(Request(rid=state["next_step_id"], arrival=rec.done, kind="step",
+                        steps_q.append(Request(rid=state["next_step_id"], arrival=rec.done, kind="step",
                                                n=req.n, session=req.session, p=req.p, theta=req.theta,
                                                variant=req.variant, dt=req.dt))
                         state["next_step_id"] += 1
@@ -214,13 +221,10 @@ class Server:
                 while nxt < len(requests) and requests[nxt].arrival <= now:
                     pending.append(requests[nxt])
                     nxt += 1
-                # admit from the head while a worker is free and memory allows (FIFO)
+                # admit solves from the head while a worker is free and memory allows (FIFO)
                 while pending and state["free_workers"]:
                     req = pending[0]
-                    if req.kind == "step" and req.session in busy_sessions:
-                        pending.rotate(-1)
-                        break
-                    fp = self.footprint(req) if req.kind == "solve" else 0
+                    fp = self.footprint(req)
                     if fp > self.budget:
                         pending.popleft()
                         records.append(Record(req.rid, req.kind, req.n, req.p, req.theta, req.variant, req.arrival,
@@ -232,9 +236,21 @@ class Server:
                     pending.popleft()
                     state["used"] += fp
                     wid = state["free_workers"].pop()
-                    if req.kind == "step":
-                        busy_sessions.add(req.session)
                     th = threading.Thread(target=execute, args=(wid, req, now, fp), daemon=True)
+                    threads.append(th)
+                    th.start()
+                # session steps fill the workers no admissible solve is waiting for
+                # (here either no solve waits or the head solve does not fit yet)
+                rounds = len(steps_q)
+                while steps_q and state["free_workers"] and rounds > 0 and len(busy_sessions) < self.step_slots:
+                    rounds -= 1
+                    req = steps_q.popleft()
+                    if req.session in busy_sessions:
+                        steps_q.append(req)
+                        continue
+                    busy_sessions.add(req.session)
+                    wid = state["free_workers"].pop()
+                    th = threading.Thread(target=execute, args=(wid, req, now, 0), daemon=True)
                     threads.append(th)
                     th.start()
                 if state["solves_left"] <= 0 and len(state["free_workers"]) == self.slots:

@@ -11,7 +11,8 @@
         Poisson trace of solves with N log-uniform in [1e3, 5e5], p in {2,4,6},
         theta in {0.4,0.6,0.8}, plus persistent leapfrog sessions: FP32 mixed
         with concurrent slots against FP64 one solve at a time, same trace;
-        solves/s and p50/p99 latency, and the per-request mixed-vs-FP64 error.
+        solves/s and p50/p99 latency, the per-request mixed-vs-FP64 error, and
+        the capacity of both (the same solves queued at once, no sessions).
     python -m paper_2107_07166_amd.studies profile [--steps 3] [--n-leaf 64]
                                                    [--workload plummer1m] [--variant conserving]
         Driver for profilers: a workload (default the benchmark one, Plummer
@@ -24,6 +25,7 @@
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import time
 
@@ -116,6 +118,11 @@ def study_serve(n_requests: int, n_sessions: int, rate: float, slots: int, budge
             close_sessions(sessions)
         res[name] = recs
         out[name] = summarize(recs)
+    # capacity: the same solves all queued at once, no sessions
+    burst = [dataclasses.replace(r, arrival=0.0) for r in trace]
+    for name, prec, k in (("fp64_one_at_a_time", "fp64", 1), ("mixed32_batched", "mixed32", slots)):
+        recs = Server(slots=k, precision=prec, budget_bytes=int(budget_gb * (1 << 30))).run(burst, inputs=inputs)
+        out[name]["capacity_solves_per_s"] = summarize(recs)["solves_per_s"]
     a = {r.rid: r.sample for r in res["mixed32_batched"] if r.kind == "solve" and not r.error}
     b = {r.rid: r.sample for r in res["fp64_one_at_a_time"] if r.kind == "solve" and not r.error}
     errs = [float(np.sqrt(np.mean(((a[i] - b[i]) ** 2).sum(1) / (b[i] ** 2).sum(1)))) for i in a if i in b]
@@ -167,7 +174,7 @@ def main():
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--sessions", type=int, default=16)
     ap.add_argument("--rate", type=float, default=100.0)
-    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--workload", default="plummer1m", choices=sorted(generators.WORKLOADS))
     ap.add_argument("--variant", default="conserving", choices=["standard", "conserving"])
