@@ -25,13 +25,25 @@ namespace {
 
 constexpr int TB = 256;
 
+// Per node, packed for the walk: geo = (centre of mass x, y, z, r_max),
+// top = (child count, level, first child, 0).
 struct WalkNodes {
-    const int32_t* level;
-    const int32_t* child_first;
-    const int32_t* nchild;
-    const double4* Z;
-    const double* rmax;
+    const double4* geo;
+    const int4* top;
 };
+
+__global__ __launch_bounds__(TB) void walk_nodes_kernel(int64_t nn, const double4* __restrict__ Z,
+                                                        const double* __restrict__ rmax,
+                                                        const int32_t* __restrict__ nchild,
+                                                        const int32_t* __restrict__ level,
+                                                        const int32_t* __restrict__ child_first,
+                                                        double4* __restrict__ geo, int4* __restrict__ top) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= nn) return;
+    const double4 z = Z[i];
+    geo[i] = make_double4(z.x, z.y, z.z, rmax[i]);
+    top[i] = make_int4(nchild[i], level[i], child_first[i], 0);
+}
 
 struct Decision {
     int kind;      // 0 near, 1 far, 2 expand self, 3 split S against O
@@ -41,8 +53,9 @@ struct Decision {
 
 __device__ __forceinline__ Decision decide(const WalkNodes& w, int32_t A, int32_t B, double theta) {
     Decision d{0, -1, -1, 0u};
+    const int4 ta = w.top[A];
     if (A == B) {
-        const int32_t nc = w.nchild[A];
+        const int32_t nc = ta.x;
         if (nc == 0) {
             d.kind = 0;
         } else {
@@ -51,15 +64,16 @@ __device__ __forceinline__ Decision decide(const WalkNodes& w, int32_t A, int32_
         }
         return d;
     }
-    const double4 za = w.Z[A], zb = w.Z[B];
-    const double dx = za.x - zb.x, dy = za.y - zb.y, dz = za.z - zb.z;
+    const int4 tb = w.top[B];
+    const double4 ga = w.geo[A], gb = w.geo[B];
+    const double dx = ga.x - gb.x, dy = ga.y - gb.y, dz = ga.z - gb.z;
     const double R = sqrt((dx * dx + dy * dy) + dz * dz);
-    const double ra = w.rmax[A], rb = w.rmax[B];
+    const double ra = ga.w, rb = gb.w;
     if (R > 0.0 && ra + rb <= theta * R) {
         d.kind = 1;
         return d;
     }
-    const int32_t na = w.nchild[A], nb = w.nchild[B];
+    const int32_t na = ta.x, nb = tb.x;
     if (na == 0 && nb == 0) {
         d.kind = 0;
         return d;
@@ -69,15 +83,16 @@ __device__ __forceinline__ Decision decide(const WalkNodes& w, int32_t A, int32_
     else if (nb == 0) S = A;
     else if (ra > rb) S = A;
     else if (rb > ra) S = B;
-    else if (w.level[A] < w.level[B]) S = A;
-    else if (w.level[B] < w.level[A]) S = B;
+    else if (ta.y < tb.y) S = A;
+    else if (tb.y < ta.y) S = B;
     else S = A < B ? A : B;
     d.kind = 3;
     d.S = S;
     d.O = (S == A) ? B : A;
-    d.nnew = (uint32_t)w.nchild[S];
+    d.nnew = (uint32_t)((S == A) ? na : nb);
     return d;
 }
+
 
 __device__ __forceinline__ U3 u3add(U3 x, U3 y) { return {x.a + y.a, x.b + y.b, x.c + y.c}; }
 
@@ -272,13 +287,15 @@ __global__ __launch_bounds__(TB) void walk_emit_pass_kernel(WalkNodes w, const i
         } else if (kind == 1) {
             far[far0 + o.b] = make_int2(lo, hi);
         } else if (kind == 2) {
-            const int32_t c0 = w.child_first[pr.x], nc = w.nchild[pr.x];
+            const int4 tp = w.top[pr.x];
+            const int32_t c0 = tp.z, nc = tp.x;
             int2* q = next + o.a;
             for (int32_t x = 0; x < nc; ++x)
                 for (int32_t y = x; y < nc; ++y) *q++ = make_int2(c0 + x, c0 + y);
         } else {
             const int32_t S = (code & 4) ? pr.y : pr.x, O = (code & 4) ? pr.x : pr.y;
-            const int32_t c0 = w.child_first[S], nc = w.nchild[S];
+            const int4 tp = w.top[S];
+            const int32_t c0 = tp.z, nc = tp.x;
             int2* q = next + o.a;
             for (int32_t x = 0; x < nc; ++x) q[x] = make_int2(c0 + x, O);
         }
@@ -627,8 +644,14 @@ void aux_join(Tree& t, hipStream_t s) {
 void walk_lists_begin(Tree& t, double theta, hipStream_t s) {
     Ctx* ctx = t.ctx;
     const int64_t nn = t.n_nodes;
-    WalkNodes w{t.nd_level.as<int32_t>(), t.nd_child_first.as<int32_t>(), t.nd_nchild.as<int32_t>(),
-                t.nd_Z.as<double4>(), t.nd_rmax.as<double>()};
+    t.w_geo.ensure(ctx, (size_t)std::max<int64_t>(nn, 1) * sizeof(double4));
+    t.w_top.ensure(ctx, (size_t)std::max<int64_t>(nn, 1) * sizeof(int4));
+    hipLaunchKernelGGL(walk_nodes_kernel, dim3(grid(nn)), dim3(TB), 0, s, nn, (const double4*)t.nd_Z.as<double4>(),
+                       (const double*)t.nd_rmax.as<double>(), (const int32_t*)t.nd_nchild.as<int32_t>(),
+                       (const int32_t*)t.nd_level.as<int32_t>(), (const int32_t*)t.nd_child_first.as<int32_t>(),
+                       t.w_geo.as<double4>(), t.w_top.as<int4>());
+    TFMM_LAUNCHED();
+    WalkNodes w{t.w_geo.as<double4>(), t.w_top.as<int4>()};
     t.walk_valid = false;
     if (!walk_bfs_async(t, w, theta, s)) walk_bfs_sized(t, w, theta, s);
     t.walk_hint_far = t.n_m2l;
