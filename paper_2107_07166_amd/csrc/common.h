@@ -112,6 +112,8 @@ struct Tree {
     DevBuf w_fr, w_fr2, w_cnt, w_off, w_tg, w_sr, w_fl, w_c;  // walk and list-building scratch
     DevBuf w_state, w_res, w_dec; // device-side walk counters, list totals, pair decisions
     DevBuf w_geo, w_top;          // per node, packed for the walk (COM + r_max; children, level)
+    DevBuf w_pst;                 // tile status words of the fused frontier passes
+    uint32_t w_epoch = 0;         // epoch of the last fused pass (tags its status words)
     // sizes seen by the previous walk of this tree (capacity hints for the
     // passes that run without host synchronisation; 0 = none yet)
     int64_t walk_hint_fr = 0, walk_hint_far = 0, walk_hint_near = 0;

@@ -146,7 +146,8 @@ __device__ __forceinline__ U3L block_sum(U3L x, U3L* wsum) {
 }
 
 // ---- frontier passes ----------------------------------------------------------
-// A pass has two kernels.  The counting kernel decides every frontier pair,
+// A pass has two kernels (the unsynchronised walk fuses them for small
+// frontiers, below).  The counting kernel decides every frontier pair,
 // stores the decision and scans the output counts (next-frontier pairs, far
 // pairs, near pairs) inside its block; the emitting kernel adds the totals of
 // the blocks before it and writes the outputs.  Block b of a pass takes a
@@ -168,6 +169,7 @@ struct WalkState {
     uint32_t pad;
     unsigned long long n_far[2], n_near[2];
     uint32_t nf_pass[kMaxPasses];  // frontier size of every pass (sizes the next walk's grids)
+    uint32_t ticket[kMaxPasses];   // tile tickets of the fused passes
 };
 constexpr int kWalkGrid = 1024;
 
@@ -190,7 +192,14 @@ __global__ void walk_init_kernel(WalkState* __restrict__ st, int2* __restrict__ 
         st->n_near[0] = st->n_near[1] = 0ull;
         fr[0] = make_int2(0, 0);
     }
-    for (int k = threadIdx.x; k < kMaxPasses; k += blockDim.x) st->nf_pass[k] = 0u;
+    for (int k = threadIdx.x; k < kMaxPasses; k += blockDim.x) {
+        st->nf_pass[k] = 0u;
+        st->ticket[k] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(TB) void zero_words_kernel(unsigned long long* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) p[i] = 0ull;
 }
 
 // Decision code: bits 0-1 kind (0 near, 1 far, 2 expand self, 3 split);
@@ -299,6 +308,218 @@ __global__ __launch_bounds__(TB) void walk_emit_pass_kernel(WalkNodes w, const i
             int2* q = next + o.a;
             for (int32_t x = 0; x < nc; ++x) q[x] = make_int2(c0 + x, O);
         }
+    }
+}
+
+// ---- fused frontier pass ---------------------------------------------------
+// One kernel per pass for the unsynchronised walk: a block takes tiles of
+// kPassTile frontier pairs in ticket order, decides them, scans the three
+// output counts inside the block, and finds the counts of all earlier tiles
+// by decoupled look-back over per-tile status words (one word per count).
+// Outputs land in frontier order, exactly as with the two-kernel pass.
+// A status word holds (epoch << 44) | (flag << 42) | value; a word written by
+// another pass carries another epoch and reads as unpublished, so the words
+// need no clearing between passes.  The tile that comes last writes the pass
+// totals into the state; with an empty frontier block 0 does.
+constexpr int kPassPPT = 2;                    // consecutive pairs per thread
+constexpr int kPassTile = TB * kPassPPT;       // pairs per tile
+constexpr int kEpochBits = 20;
+constexpr unsigned long long kPstOwn = 1ull << 42;
+constexpr unsigned long long kPstTotal = 2ull << 42;
+constexpr unsigned long long kPstVal = (1ull << 42) - 1;
+constexpr uint32_t kPassSpinLimit = 1u << 20;
+constexpr int kPassGrid = 2048;                // blocks of a fused pass (at most)
+// Passes expected to hold at most this many pairs run fused.  Look-back over
+// many tiles costs more than the second launch saves, so larger passes keep
+// the two-kernel form.
+#ifndef TFMM_FUSE_MAX_PAIRS
+#define TFMM_FUSE_MAX_PAIRS 4096
+#endif
+constexpr int64_t kFuseMaxPairs = TFMM_FUSE_MAX_PAIRS;
+
+__device__ __forceinline__ unsigned long long pst_word(uint32_t epoch, unsigned long long flag,
+                                                       unsigned long long v) {
+    return ((unsigned long long)epoch << 44) | flag | v;
+}
+
+__device__ __forceinline__ void pass_state_write(WalkState* st, int pass, uint32_t nf, U3L T,
+                                                 unsigned long long far0, unsigned long long near0,
+                                                 uint32_t cap_next, unsigned long long cap_far,
+                                                 unsigned long long cap_near) {
+    const int parity = pass & 1;
+    const unsigned long long lim = 0xffffffffull;
+    const bool ovf = T.a > cap_next || T.b > lim || T.c > lim || far0 + T.b > cap_far || near0 + T.c > cap_near;
+    if (ovf) {
+        st->overflow = 1u;
+        st->nf[parity ^ 1] = 0u;
+        return;
+    }
+    st->nf[parity ^ 1] = (uint32_t)T.a;
+    st->n_far[parity ^ 1] = far0 + T.b;
+    st->n_near[parity ^ 1] = near0 + T.c;
+    if (nf > 0u) st->passes += 1u;
+    if ((uint32_t)T.a > st->max_nf) st->max_nf = (uint32_t)T.a;
+    if (pass < kMaxPasses) st->nf_pass[pass] = nf;
+}
+
+__global__ __launch_bounds__(TB) void walk_pass_kernel(WalkNodes w, const int2* __restrict__ fr,
+                                                       WalkState* __restrict__ st, int pass, double theta,
+                                                       int2* __restrict__ next, int2* __restrict__ far,
+                                                       int2* __restrict__ near, uint32_t cap_next,
+                                                       unsigned long long cap_far, unsigned long long cap_near,
+                                                       unsigned long long* __restrict__ pst, uint32_t cap_tiles,
+                                                       uint32_t epoch, uint32_t* __restrict__ err) {
+    __shared__ U3 wsum[TB / kWave];
+    __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_pre[3];
+    const int parity = pass & 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t nf = st->nf[parity];
+    const unsigned long long far0 = st->n_far[parity], near0 = st->n_near[parity];
+    const uint32_t ntiles = (uint32_t)(((uint64_t)nf + kPassTile - 1) / kPassTile);
+    if (ntiles == 0u || ntiles > cap_tiles) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (ntiles == 0u) {
+                pass_state_write(st, pass, 0u, U3L{0ull, 0ull, 0ull}, far0, near0, cap_next, cap_far, cap_near);
+            } else {
+                st->overflow = 1u;
+                st->nf[parity ^ 1] = 0u;
+            }
+        }
+        return;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&st->ticket[pass], 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= ntiles) break;
+
+        // decide this thread's pairs (consecutive in the frontier)
+        const int64_t i0 = (int64_t)tile * kPassTile + (int64_t)threadIdx.x * kPassPPT;
+        int2 pr[kPassPPT];
+        Decision dc[kPassPPT];
+        U3 c{0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < kPassPPT; ++q) {
+            dc[q] = Decision{-1, -1, -1, 0u};
+            if (i0 + q < (int64_t)nf) {
+                pr[q] = fr[i0 + q];
+                dc[q] = decide(w, pr[q].x, pr[q].y, theta);
+                if (dc[q].kind == 0) c.c += 1u;
+                else if (dc[q].kind == 1) c.b += 1u;
+                else c.a += dc[q].nnew;
+            }
+        }
+        U3 tot;
+        const U3 e = block_excl_scan(c, wsum, tot);
+
+        // publish the tile's counts, then look back (first wavefront)
+        if (threadIdx.x < kWave) {
+            unsigned long long* my = pst + (size_t)tile * 3;
+            const unsigned long long f0 = tile == 0u ? kPstTotal : kPstOwn;
+            if (lane == 0) {
+                __hip_atomic_store(&my[0], pst_word(epoch, f0, tot.a), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&my[1], pst_word(epoch, f0, tot.b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&my[2], pst_word(epoch, f0, tot.c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            unsigned long long acc[3] = {0ull, 0ull, 0ull};
+            bool done[3] = {tile == 0u, tile == 0u, tile == 0u};
+            int64_t j0 = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            while (j0 >= 0 && !(done[0] && done[1] && done[2])) {
+                const int64_t j = j0 - lane;
+                unsigned long long y[3];
+                uint64_t need[3];
+                int ft[3];
+                bool stall = false;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    y[k] = 0ull;
+                    need[k] = 0ull;
+                    ft[k] = kWave;
+                    if (done[k]) continue;
+                    // words before the first tile count as a zero running total
+                    y[k] = j >= 0 ? __hip_atomic_load(&pst[j * 3 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : pst_word(epoch, kPstTotal, 0ull);
+                    const bool cur = (uint32_t)(y[k] >> 44) == epoch;
+                    const unsigned long long flag = cur ? (y[k] & (3ull << 42)) : 0ull;
+                    const uint64_t totm = __ballot(flag == kPstTotal);
+                    const uint64_t zerom = __ballot(flag == 0ull);
+                    ft[k] = totm ? __ffsll((long long)totm) - 1 : kWave;
+                    need[k] = ft[k] >= kWave - 1 ? ~0ull : ((2ull << ft[k]) - 1ull);
+                    if (zerom & need[k]) stall = true;
+                }
+                if (stall) {
+                    if (++spins > kPassSpinLimit) {
+                        if (lane == 0) atomicOr(err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    if (done[k]) continue;
+                    unsigned long long v = ((need[k] >> lane) & 1ull) ? (y[k] & kPstVal) : 0ull;
+#pragma unroll
+                    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+                    acc[k] += v;
+                    if (ft[k] < kWave) done[k] = true;
+                }
+                j0 -= kWave;
+            }
+            if (lane == 0) {
+                if (tile > 0u) {
+                    __hip_atomic_store(&my[0], pst_word(epoch, kPstTotal, acc[0] + tot.a), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&my[1], pst_word(epoch, kPstTotal, acc[1] + tot.b), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&my[2], pst_word(epoch, kPstTotal, acc[2] + tot.c), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
+                s_pre[0] = acc[0];
+                s_pre[1] = acc[1];
+                s_pre[2] = acc[2];
+            }
+        }
+        __syncthreads();
+        const U3L P{s_pre[0], s_pre[1], s_pre[2]};
+        const bool fits = P.a + tot.a <= cap_next && far0 + P.b + tot.b <= cap_far &&
+                          near0 + P.c + tot.c <= cap_near;
+        if (!fits) {
+            if (threadIdx.x == 0) atomicOr(&st->overflow, 1u);
+        } else {
+            unsigned long long on = P.a + e.a, ofar = far0 + P.b + e.b, onear = near0 + P.c + e.c;
+#pragma unroll
+            for (int q = 0; q < kPassPPT; ++q) {
+                const Decision d = dc[q];
+                if (d.kind < 0) continue;
+                const int32_t lo = pr[q].x < pr[q].y ? pr[q].x : pr[q].y;
+                const int32_t hi = pr[q].x < pr[q].y ? pr[q].y : pr[q].x;
+                if (d.kind == 0) {
+                    near[onear++] = make_int2(lo, hi);
+                } else if (d.kind == 1) {
+                    far[ofar++] = make_int2(lo, hi);
+                } else if (d.kind == 2) {
+                    const int4 tp = w.top[pr[q].x];
+                    const int32_t c0 = tp.z, nc = tp.x;
+                    int2* o = next + on;
+                    for (int32_t x = 0; x < nc; ++x)
+                        for (int32_t yy = x; yy < nc; ++yy) *o++ = make_int2(c0 + x, c0 + yy);
+                    on += d.nnew;
+                } else {
+                    const int4 tp = w.top[d.S];
+                    const int32_t c0 = tp.z, nc = tp.x;
+                    int2* o = next + on;
+                    for (int32_t x = 0; x < nc; ++x) o[x] = make_int2(c0 + x, d.O);
+                    on += d.nnew;
+                }
+            }
+        }
+        if (tile == ntiles - 1u && threadIdx.x == 0)
+            pass_state_write(st, pass, nf, U3L{P.a + tot.a, P.b + tot.b, P.c + tot.c}, far0, near0, cap_next,
+                             cap_far, cap_near);
+        __syncthreads();
     }
 }
 
@@ -550,8 +771,8 @@ void walk_bfs_sized(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
     t.walk_hint_fr = max_nf;
 }
 
-// Frontier passes with no host synchronisation, sized from the previous walk
-// of this tree plus a quarter.  A pair's level sum grows by at least one per
+// Frontier passes with no host synchronisation (small ones fused into one
+// kernel), sized from the previous walk of this tree plus a quarter.  A pair's level sum grows by at least one per
 // expansion, a non-leaf sits above the deepest level and a pair of leaves is
 // never expanded, so every frontier after pass 2 max_level is empty; the host
 // checks that, and the overflow flag, once at the end.  Returns false (lists
@@ -574,11 +795,23 @@ bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
     const size_t cap_next = std::min({t.w_fr.cap / 8, t.w_fr2.cap / 8, t.w_dec.cap, t.w_cnt.cap / sizeof(U3),
                                       (size_t)UINT32_MAX});
     const unsigned long long cap_far = t.m2l_pairs.cap / 8, cap_near = t.p2p_pairs.cap / 8;
+    const int passes = 2 * t.max_level + 1;
+    if (passes > kMaxPasses) return false;
+    // tile status words (three per tile); cleared when new and when the pass
+    // epoch would wrap, so a stale word never carries the current epoch
+    const uint32_t cap_tiles = (uint32_t)cdiv((int64_t)cap_next, kPassTile);
+    void* old_pst = t.w_pst.p;
+    t.w_pst.ensure(ctx, (size_t)cap_tiles * 3 * 8);
+    if (t.w_pst.p != old_pst || t.w_epoch + (uint32_t)passes >= (1u << kEpochBits)) {
+        const int64_t nw = (int64_t)(t.w_pst.cap / 8);
+        hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)std::min<int64_t>(1024, cdiv(nw, TB))), dim3(TB), 0, s,
+                           t.w_pst.as<unsigned long long>(), nw);
+        TFMM_LAUNCHED();
+        t.w_epoch = 0;
+    }
     WalkState* st = t.w_state.as<WalkState>();
     hipLaunchKernelGGL(walk_init_kernel, dim3(1), dim3(kWave), 0, s, st, t.w_fr.as<int2>());
     TFMM_LAUNCHED();
-    const int passes = 2 * t.max_level + 1;
-    if (passes > kMaxPasses) return false;
     int64_t bound = 1;  // a pass's frontier is at most 36 times the previous one
     for (int k = 0; k < passes; ++k) {
         const int parity = k & 1;
@@ -586,18 +819,28 @@ bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
         // any frontier; a small one keeps small passes cheap)
         int64_t expect = bound;
         if (k < (int)t.walk_hint_nf.size()) expect = std::min(bound, t.walk_hint_nf[k] + t.walk_hint_nf[k] / 4 + 1024);
-        const unsigned g = (unsigned)std::min<int64_t>(kWalkGrid, cdiv(std::max<int64_t>(expect, 1), TB));
         int2* cur = parity ? t.w_fr2.as<int2>() : t.w_fr.as<int2>();
         int2* nxt = parity ? t.w_fr.as<int2>() : t.w_fr2.as<int2>();
-        hipLaunchKernelGGL(walk_count_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur,
-                           (const WalkState*)st, parity, theta, t.w_dec.as<uint8_t>(), t.w_cnt.as<U3>(),
-                           t.w_off.as<U3L>());
-        TFMM_LAUNCHED();
-        hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur, st, k,
-                           (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3*)t.w_cnt.as<U3>(),
-                           (const U3L*)t.w_off.as<U3L>(), nxt, t.m2l_pairs.as<int2>(), t.p2p_pairs.as<int2>(),
-                           (uint32_t)cap_next, cap_far, cap_near);
-        TFMM_LAUNCHED();
+        if (expect <= kFuseMaxPairs) {
+            const unsigned g =
+                (unsigned)std::min<int64_t>(kPassGrid, cdiv(std::max<int64_t>(expect, 1), kPassTile));
+            const uint32_t epoch = ++t.w_epoch;
+            hipLaunchKernelGGL(walk_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur, st, k, theta, nxt,
+                               t.m2l_pairs.as<int2>(), t.p2p_pairs.as<int2>(), (uint32_t)cap_next, cap_far,
+                               cap_near, t.w_pst.as<unsigned long long>(), cap_tiles, epoch, ctx->dev_err);
+            TFMM_LAUNCHED();
+        } else {
+            const unsigned g = (unsigned)std::min<int64_t>(kWalkGrid, cdiv(expect, TB));
+            hipLaunchKernelGGL(walk_count_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur,
+                               (const WalkState*)st, parity, theta, t.w_dec.as<uint8_t>(), t.w_cnt.as<U3>(),
+                               t.w_off.as<U3L>());
+            TFMM_LAUNCHED();
+            hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur, st, k,
+                               (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3*)t.w_cnt.as<U3>(),
+                               (const U3L*)t.w_off.as<U3L>(), nxt, t.m2l_pairs.as<int2>(), t.p2p_pairs.as<int2>(),
+                               (uint32_t)cap_next, cap_far, cap_near);
+            TFMM_LAUNCHED();
+        }
         bound = std::min<int64_t>((int64_t)cap_next, 36 * bound);
     }
     const WalkState h = read_back(ctx, (const WalkState*)st, s);
