@@ -168,6 +168,13 @@ void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* 
                     int64_t n, int bits, void* scratch, uint32_t* err, hipStream_t s);
 void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
                     int64_t n, int bits, void* scratch, uint32_t* err, hipStream_t s);
+// Stable sort by key of the 2 np directed entries of np node pairs: entry 2i
+// is (key x_i, value y_i), entry 2i + 1 is (y_i, x_i); with self_dummy, the
+// second entry of a pair (x, x) gets key self_key instead.  The sorted
+// entries land in (keys, vals); the alternate arrays hold 2 np entries.
+void radix_sort_pairs(const int2* pairs, int64_t np, bool self_dummy, uint32_t self_key, uint32_t* keys,
+                      int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int bits, void* scratch,
+                      uint32_t* err, hipStream_t s);
 
 // Copies one device value to the host together with the context's device
 // error word, with a single synchronisation; fails if a kernel set the word.

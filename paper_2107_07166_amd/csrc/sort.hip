@@ -17,18 +17,30 @@
 // Every wait is bounded: a look-back that spins past kSpinLimit polls sets a
 // device error word, which the host checks at its next read-back; the kernel
 // always runs to its end.
+//
+// The histogram and the first pass read their input through a source: plain
+// key and value arrays, or an array of node pairs read as directed entries
+// (entry 2i = (x_i <- y_i), entry 2i + 1 = (y_i <- x_i)), which spares the
+// lists an expansion pass before the sort.
 #include "common.h"
 
 namespace tfmm {
 namespace {
 
-#ifndef TFMM_SORT_RI
-#define TFMM_SORT_RI 16
+#ifndef TFMM_SORT_LOOK
+#define TFMM_SORT_LOOK 8  // earlier tiles read per look-back step
+#endif
+#ifndef TFMM_SORT_RI64
+#define TFMM_SORT_RI64 16
+#endif
+#ifndef TFMM_SORT_RI32
+#define TFMM_SORT_RI32 16
 #endif
 constexpr int RB = 256;           // threads per block (one digit per thread)
 constexpr int RW = RB / kWave;    // waves per block
-constexpr int RI = TFMM_SORT_RI;  // keys per lane
-constexpr int RTILE = RB * RI;   // keys per tile
+// keys per lane: 64-bit keys stage twice the bytes in LDS
+template <typename K> constexpr int keys_per_lane() { return sizeof(K) == 8 ? TFMM_SORT_RI64 : TFMM_SORT_RI32; }
+template <typename K> constexpr int tile_keys() { return RB * keys_per_lane<K>(); }
 constexpr int RADIX = 256;
 constexpr int MAXP = 8;          // passes of a 64-bit key
 constexpr int kHistBlocks = 1024;
@@ -57,13 +69,43 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d) {
     return peers;
 }
 
+// Input sources.  load(i) gives entry i's key and value.
+template <typename K>
+struct ArraySrc {
+    const K* k;
+    const int32_t* v;
+    __device__ __forceinline__ void load(int64_t i, K& key, int32_t& val) const {
+        key = k[i];
+        val = v[i];
+    }
+};
+
+// Directed entries of node pairs.  With self_dummy set, the second entry of a
+// pair (x, x) gets the key self_key (above every node id), so it sorts after
+// all real entries.
+struct PairSrc {
+    const int2* p;
+    uint32_t self_key;
+    int self_dummy;
+    __device__ __forceinline__ void load(int64_t i, uint32_t& key, int32_t& val) const {
+        const int2 q = p[i >> 1];
+        if (i & 1) {
+            key = (self_dummy && q.x == q.y) ? self_key : (uint32_t)q.y;
+            val = q.x;
+        } else {
+            key = (uint32_t)q.x;
+            val = q.y;
+        }
+    }
+};
+
 __global__ __launch_bounds__(RB) void zero_u64_kernel(unsigned long long* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) p[i] = 0ull;
 }
 
 // Digit totals of every pass: LDS counters per block, then global atomics.
-template <typename K>
-__global__ __launch_bounds__(RB) void radix_hist_all_kernel(const K* __restrict__ kin, int64_t n, int passes,
+template <typename K, typename Src>
+__global__ __launch_bounds__(RB) void radix_hist_all_kernel(Src src, int64_t n, int passes,
                                                             uint32_t* __restrict__ ghist) {
     __shared__ uint32_t h[MAXP][RADIX];
     for (int p = 0; p < MAXP; ++p) h[p][threadIdx.x] = 0u;
@@ -75,7 +117,9 @@ __global__ __launch_bounds__(RB) void radix_hist_all_kernel(const K* __restrict_
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = base + (int64_t)u * RB + threadIdx.x;
-            k[u] = i < n ? kin[i] : (K)0;
+            int32_t unused;
+            k[u] = (K)0;
+            if (i < n) src.load(i, k[u], unused);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -109,15 +153,17 @@ __global__ __launch_bounds__(RB) void radix_digit_base_kernel(uint32_t* __restri
     }
 }
 
-template <typename K>
-__global__ __launch_bounds__(RB) void radix_pass_kernel(const K* __restrict__ kin, const int32_t* __restrict__ vin,
-                                                        K* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
+template <typename K, typename Src>
+__global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__ kout, int32_t* __restrict__ vout,
+                                                        int64_t n,
                                                         int shift, const uint32_t* __restrict__ dbase,
                                                         unsigned long long* __restrict__ status,
                                                         uint32_t* __restrict__ ticket, uint32_t* __restrict__ err) {
     __shared__ uint32_t wcnt[RW][RADIX];
     __shared__ uint32_t dstart[RADIX];
     __shared__ unsigned long long gbase[RADIX];
+    constexpr int RI = keys_per_lane<K>();
+    constexpr int RTILE = tile_keys<K>();
     __shared__ uint32_t wsum[RW];
     __shared__ K skeys[RTILE];
     __shared__ int32_t svals[RTILE];
@@ -139,9 +185,9 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(const K* __restrict__ ki
 #pragma unroll
     for (int r = 0; r < RI; ++r) {
         const int64_t i = wbase + (int64_t)r * kWave + lane;
-        const bool valid = i < n;
-        k[r] = valid ? kin[i] : (K)0;
-        v[r] = valid ? vin[i] : 0;
+        k[r] = (K)0;
+        v[r] = 0;
+        if (i < n) src.load(i, k[r], v[r]);
     }
     const uint64_t lt = lanemask_lt();
 #pragma unroll
@@ -180,7 +226,7 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(const K* __restrict__ ki
     } else {
         __hip_atomic_store(&st[d], kFlagOwn | (unsigned long long)real, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // earlier tiles' words for this digit, kLook at a time (independent loads)
-        constexpr int kLook = 8;
+        constexpr int kLook = TFMM_SORT_LOOK;
         uint32_t spins = 0;
         int64_t j = tile - 1;
         bool done = false;
@@ -255,8 +301,8 @@ struct SortScratch {
     int64_t zero_words;  // u64 words to clear from the start of the scratch
 };
 
-SortScratch carve(void* scratch, int64_t n, int passes) {
-    const int64_t nb = cdiv(n > 0 ? n : 1, RTILE);
+SortScratch carve(void* scratch, int64_t n, int passes, int rtile) {
+    const int64_t nb = cdiv(n > 0 ? n : 1, rtile);
     auto* base = static_cast<unsigned long long*>(scratch);
     SortScratch s;
     s.dbase = reinterpret_cast<uint32_t*>(base);                          // MAXP*RADIX u32 = 1024 u64
@@ -266,37 +312,57 @@ SortScratch carve(void* scratch, int64_t n, int passes) {
     return s;
 }
 
-template <typename K>
-void radix_sort_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int64_t n, int bits, void* scratch,
-                     uint32_t* err, hipStream_t s) {
-    if (n <= 1 || bits <= 0) return;
+// Sorts n entries read from src; pass ps writes (kout, vout) when the
+// number of passes after it is even, else the alternate arrays, so the last
+// pass always lands in (kout, vout).
+template <typename K, typename Src>
+void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int64_t n, int bits, void* scratch,
+                    uint32_t* err, hipStream_t s) {
+    constexpr int RTILE = tile_keys<K>();
     const int passes = (bits + 7) / 8;
     const int nb = (int)cdiv(n, RTILE);
-    const SortScratch sc = carve(scratch, n, passes);
+    const SortScratch sc = carve(scratch, n, passes, RTILE);
     const unsigned zb = (unsigned)std::min<int64_t>(2048, cdiv(sc.zero_words, RB));
     hipLaunchKernelGGL(zero_u64_kernel, dim3(zb), dim3(RB), 0, s, static_cast<unsigned long long*>(scratch),
                        sc.zero_words);
     TFMM_LAUNCHED();
     const unsigned hb = (unsigned)std::min<int64_t>(kHistBlocks, cdiv(n, RB * 4));
-    hipLaunchKernelGGL(radix_hist_all_kernel<K>, dim3(hb), dim3(RB), 0, s, (const K*)keys, n, passes, sc.dbase);
+    hipLaunchKernelGGL((radix_hist_all_kernel<K, Src>), dim3(hb), dim3(RB), 0, s, src, n, passes, sc.dbase);
     TFMM_LAUNCHED();
     hipLaunchKernelGGL(radix_digit_base_kernel, dim3(1), dim3(RB), 0, s, sc.dbase, passes);
     TFMM_LAUNCHED();
-    K* kin = keys;
-    int32_t* vin = vals;
-    K* kout = keys_alt;
-    int32_t* vout = vals_alt;
     for (int ps = 0; ps < passes; ++ps) {
-        hipLaunchKernelGGL(radix_pass_kernel<K>, dim3(nb), dim3(RB), 0, s, (const K*)kin, (const int32_t*)vin, kout,
-                           vout, n, 8 * ps, (const uint32_t*)(sc.dbase + ps * RADIX),
-                           sc.status + (int64_t)ps * nb * RADIX, sc.ticket + ps, err);
+        const bool to_out = ((passes - 1 - ps) & 1) == 0;
+        K* ko = to_out ? kout : kalt;
+        int32_t* vo = to_out ? vout : valt;
+        const uint32_t* db = sc.dbase + ps * RADIX;
+        unsigned long long* st = sc.status + (int64_t)ps * nb * RADIX;
+        if (ps == 0) {
+            hipLaunchKernelGGL((radix_pass_kernel<K, Src>), dim3(nb), dim3(RB), 0, s, src, ko, vo, n, 0, db, st,
+                               sc.ticket, err);
+        } else {
+            // the previous pass wrote the other pair of arrays
+            const ArraySrc<K> prev{to_out ? kalt : kout, to_out ? valt : vout};
+            hipLaunchKernelGGL((radix_pass_kernel<K, ArraySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, ko, vo, n,
+                               8 * ps, db, st, sc.ticket + ps, err);
+        }
         TFMM_LAUNCHED();
-        std::swap(kin, kout);
-        std::swap(vin, vout);
     }
-    if (kin != keys) {
-        TFMM_HIP(hipMemcpyAsync(keys, kin, (size_t)n * sizeof(K), hipMemcpyDeviceToDevice, s));
-        TFMM_HIP(hipMemcpyAsync(vals, vin, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+}
+
+template <typename K>
+void radix_sort_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int64_t n, int bits, void* scratch,
+                     uint32_t* err, hipStream_t s) {
+    if (n <= 1 || bits <= 0) return;
+    const int passes = (bits + 7) / 8;
+    if (passes & 1) {
+        // an odd number of passes ends in the alternate arrays: sort from a
+        // copy there back into the caller's arrays
+        TFMM_HIP(hipMemcpyAsync(keys_alt, keys, (size_t)n * sizeof(K), hipMemcpyDeviceToDevice, s));
+        TFMM_HIP(hipMemcpyAsync(vals_alt, vals, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        radix_sort_run<K>(ArraySrc<K>{keys_alt, vals_alt}, keys, vals, keys_alt, vals_alt, n, bits, scratch, err, s);
+    } else {
+        radix_sort_run<K>(ArraySrc<K>{keys, vals}, keys, vals, keys_alt, vals_alt, n, bits, scratch, err, s);
     }
 }
 
@@ -304,7 +370,8 @@ void radix_sort_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int
 
 size_t sort_scratch_bytes(int64_t n, int bits) {
     const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
-    return (size_t)carve(nullptr, n, passes).zero_words * 8 + 256;
+    const int rtile = std::min(tile_keys<uint32_t>(), tile_keys<uint64_t>());
+    return (size_t)carve(nullptr, n, passes, rtile).zero_words * 8 + 256;
 }
 
 void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
@@ -315,6 +382,15 @@ void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* 
 void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
                     void* scratch, uint32_t* err, hipStream_t s) {
     radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, scratch, err, s);
+}
+
+void radix_sort_pairs(const int2* pairs, int64_t np, bool self_dummy, uint32_t self_key, uint32_t* keys,
+                      int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int bits, void* scratch, uint32_t* err,
+                      hipStream_t s) {
+    const int64_t n = 2 * np;
+    if (n <= 0) return;
+    radix_sort_run<uint32_t>(PairSrc{pairs, self_key, self_dummy ? 1 : 0}, keys, vals, keys_alt, vals_alt, n,
+                             bits > 0 ? bits : 1, scratch, err, s);
 }
 
 }  // namespace tfmm

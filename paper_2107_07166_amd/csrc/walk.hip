@@ -523,49 +523,18 @@ __global__ __launch_bounds__(TB) void walk_pass_kernel(WalkNodes w, const int2* 
     }
 }
 
-// Directed entries of the far list: (A <- B) and (B <- A).
-__global__ __launch_bounds__(TB) void far_entries_kernel(const int2* __restrict__ pairs, int64_t np,
-                                                         uint32_t* __restrict__ tgt, int32_t* __restrict__ src) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i >= np) return;
-    const int2 p = pairs[i];
-    tgt[2 * i] = (uint32_t)p.x;
-    src[2 * i] = p.y;
-    tgt[2 * i + 1] = (uint32_t)p.y;
-    src[2 * i + 1] = p.x;
-}
-
-__global__ __launch_bounds__(TB) void near_count_kernel(const int2* __restrict__ pairs, int64_t np,
-                                                        uint32_t* __restrict__ c) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i >= np) return;
-    const int2 p = pairs[i];
-    c[i] = p.x == p.y ? 1u : 2u;
-}
-
-__global__ __launch_bounds__(TB) void near_entries_kernel(const int2* __restrict__ pairs, int64_t np,
-                                                          const uint32_t* __restrict__ off,
-                                                          uint32_t* __restrict__ tgt, int32_t* __restrict__ src) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i >= np) return;
-    const int2 p = pairs[i];
-    const uint32_t o = off[i];
-    tgt[o] = (uint32_t)p.x;
-    src[o] = p.y;
-    if (p.x != p.y) {
-        tgt[o + 1] = (uint32_t)p.y;
-        src[o + 1] = p.x;
-    }
-}
-
 // CSR offsets from targets sorted ascending: off[t] = first entry with target
-// >= t, for t = 0..nn (each t written by exactly one thread).
+// >= t, for t = 0..nn (each t written by exactly one thread, which also
+// copies off[nn], the number of entries below nn, to *below_nn if given).
+// Keys may equal nn (entries sorted after every real one).
 __global__ __launch_bounds__(TB) void csr_offsets_kernel(const uint32_t* __restrict__ keys, int64_t ne,
-                                                         int64_t nn, uint32_t* __restrict__ off) {
+                                                         int64_t nn, uint32_t* __restrict__ off,
+                                                         uint32_t* __restrict__ below_nn) {
     for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i <= ne; i += (int64_t)gridDim.x * TB) {
         const int64_t lo = (i == 0) ? 0 : (int64_t)keys[i - 1] + 1;
-        const int64_t hi = (i == ne) ? nn : (int64_t)keys[i];
+        const int64_t hi = (i == ne) ? nn : std::min<int64_t>((int64_t)keys[i], nn);
         for (int64_t t = lo; t <= hi; ++t) off[t] = (uint32_t)i;
+        if (below_nn && lo <= nn && nn <= hi) *below_nn = (uint32_t)i;
     }
 }
 
@@ -676,22 +645,30 @@ V read_back(Ctx* ctx, const V* dev, hipStream_t s) {
     return v;
 }
 
-// Stable sort of directed (target, source) entries by target, then CSR
-// offsets from the sorted targets.  The sources of every target stay in the
+// Stable sort by target of the directed entries of np node pairs (read
+// straight from the pair array), then CSR offsets from the sorted targets.
+// With self_dummy, the second entry of a self pair gets key nn and sorts
+// last, so the first off[nn] entries are the real ones; off[nn] is also
+// written to *real_out if given.  The sources of every target stay in the
 // walk's emission order.
-void build_csr(Tree& t, DevBuf& tgtbuf, DevBuf& srcbuf, int64_t ne, DevBuf& off, DevBuf& srcout, DevBuf& scr,
-               DevBuf& scr2, hipStream_t s) {
+void build_csr_pairs(Tree& t, const DevBuf& pairs, int64_t np, bool self_dummy, DevBuf& tgtbuf, DevBuf& srcbuf,
+                     DevBuf& off, DevBuf& srcout, DevBuf& scr, DevBuf& scr2, uint32_t* real_out, hipStream_t s) {
     Ctx* ctx = t.ctx;
     const int64_t nn = t.n_nodes;
-    scr2.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8 + 256);
+    const int64_t ne = 2 * np;
+    const int64_t room = std::max<int64_t>(ne, 1);
+    tgtbuf.ensure(ctx, (size_t)room * 4);
+    srcbuf.ensure(ctx, (size_t)room * 4);
+    scr2.ensure(ctx, (size_t)room * 8 + 256);
     uint32_t* kalt = scr2.as<uint32_t>();
-    int32_t* valt = reinterpret_cast<int32_t*>(kalt + std::max<int64_t>(ne, 1));
-    scr.ensure(ctx, sort_scratch_bytes(ne, bits_for(nn)) + 1024);
-    radix_sort_u32(tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(), kalt, valt, ne, bits_for(nn), scr.p, ctx->dev_err, s);
+    int32_t* valt = reinterpret_cast<int32_t*>(kalt + room);
+    const int bits = bits_for(self_dummy ? nn + 1 : nn);
+    scr.ensure(ctx, sort_scratch_bytes(ne, bits) + 1024);
+    radix_sort_pairs(pairs.as<int2>(), np, self_dummy, (uint32_t)nn, tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(),
+                     kalt, valt, bits, scr.p, ctx->dev_err, s);
     off.ensure(ctx, (size_t)(nn + 1) * 4);
     hipLaunchKernelGGL(csr_offsets_kernel, dim3((unsigned)std::min<int64_t>(2048, grid(ne + 1))), dim3(TB), 0, s,
-                       (const uint32_t*)tgtbuf.as<uint32_t>(),
-                       ne, nn, off.as<uint32_t>());
+                       (const uint32_t*)tgtbuf.as<uint32_t>(), ne, nn, off.as<uint32_t>(), real_out);
     TFMM_LAUNCHED();
     std::swap(srcbuf.p, srcout.p);
     std::swap(srcbuf.cap, srcout.cap);
@@ -912,39 +889,17 @@ void walk_lists_begin(Tree& t, double theta, hipStream_t s) {
     // on s; they share no buffer.
     aux_fork(t, s);
     // far lists: directed, by target
-    {
-        DevBuf& tg = t.w_tg;
-        DevBuf& sr = t.w_sr;
-        const hipStream_t fs = t.aux;
-        const int64_t ne = 2 * n_far;
-        tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
-        sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
-        if (n_far > 0) {
-            hipLaunchKernelGGL(far_entries_kernel, dim3(grid(n_far)), dim3(TB), 0, fs, t.m2l_pairs.as<int2>(),
-                               n_far, tg.as<uint32_t>(), sr.as<int32_t>());
-            TFMM_LAUNCHED();
-        }
-        build_csr(t, tg, sr, ne, t.m2l_off, t.m2l_src, t.scratch, t.scratch2, fs);
-    }
+    build_csr_pairs(t, t.m2l_pairs, n_far, false, t.w_tg, t.w_sr, t.m2l_off, t.m2l_src, t.scratch, t.scratch2,
+                    nullptr, t.aux);
     DevBuf& tg = t.w_tg_b;
     DevBuf& sr = t.w_sr_b;
     // near lists: directed (self pairs once), by target.  Every leaf has
-    // exactly one self pair, so the entry count is 2 n_near - n_leaves.
+    // exactly one self pair, so the entry count is 2 n_near - n_leaves (the
+    // count the sort leaves below its dummies is checked at the end).
     const int64_t ne = 2 * n_near - t.n_leaves;
     {
-        t.w_c.ensure(ctx, (size_t)std::max<int64_t>(n_near, 1) * 8);
-        uint32_t* c = t.w_c.as<uint32_t>();
-        uint32_t* o = c + std::max<int64_t>(n_near, 1);
-        hipLaunchKernelGGL(near_count_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near, c);
-        TFMM_LAUNCHED();
-        t.scratch_b.ensure(ctx, scan_scratch_bytes(n_near) + 256);
-        exclusive_scan_u32(c, o, n_near, t.scratch_b.p, &res->near_entries, ctx->dev_err, s);
-        tg.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
-        sr.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
-        hipLaunchKernelGGL(near_entries_kernel, dim3(grid(n_near)), dim3(TB), 0, s, t.p2p_pairs.as<int2>(), n_near,
-                           (const uint32_t*)o, tg.as<uint32_t>(), sr.as<int32_t>());
-        TFMM_LAUNCHED();
-        build_csr(t, tg, sr, ne, t.p2p_off, t.p2p_src, t.scratch_b, t.scratch2_b, s);
+        build_csr_pairs(t, t.p2p_pairs, n_near, true, tg, sr, t.p2p_off, t.p2p_src, t.scratch_b, t.scratch2_b,
+                        &res->near_entries, s);
         // work items over the sorted near entries (tg holds the sorted targets)
         t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8);
         uint32_t* ec = t.w_c.as<uint32_t>();
