@@ -207,29 +207,23 @@ __global__ __launch_bounds__(TB) void zero_words_kernel(unsigned long long* __re
 __global__ __launch_bounds__(TB) void walk_count_pass_kernel(WalkNodes w, const int2* __restrict__ fr,
                                                              const WalkState* __restrict__ st, int parity,
                                                              double theta, uint8_t* __restrict__ dec,
-                                                             U3* __restrict__ off, U3L* __restrict__ bsum) {
-    __shared__ U3 wsum[TB / kWave];
+                                                             U3L* __restrict__ bsum) {
+    __shared__ U3L wsum[TB / kWave];
     const uint32_t nf = st->overflow ? 0u : st->nf[parity];
     int64_t t0, t1;
     block_tiles(nf, t0, t1);
-    U3L carry{0ull, 0ull, 0ull};
-    for (int64_t t = t0; t < t1; ++t) {
-        const int64_t i = t * TB + threadIdx.x;
-        U3 c{0u, 0u, 0u};
-        if (i < nf) {
-            const int2 pr = fr[i];
-            const Decision d = decide(w, pr.x, pr.y, theta);
-            if (d.kind == 0) c.c = 1u;
-            else if (d.kind == 1) c.b = 1u;
-            else c.a = d.nnew;
-            dec[i] = (uint8_t)(d.kind | ((d.kind == 3 && d.S == pr.y) ? 4 : 0));
-        }
-        U3 tot;
-        const U3 e = block_excl_scan(c, wsum, tot);
-        if (i < nf) off[i] = U3{(uint32_t)carry.a + e.a, (uint32_t)carry.b + e.b, (uint32_t)carry.c + e.c};
-        carry = u3ladd(carry, tot);
+    U3L c{0ull, 0ull, 0ull};
+    const int64_t iend = t1 * TB < (int64_t)nf ? t1 * TB : (int64_t)nf;
+    for (int64_t i = t0 * TB + threadIdx.x; i < iend; i += TB) {
+        const int2 pr = fr[i];
+        const Decision d = decide(w, pr.x, pr.y, theta);
+        if (d.kind == 0) c.c += 1u;
+        else if (d.kind == 1) c.b += 1u;
+        else c.a += d.nnew;
+        dec[i] = (uint8_t)(d.kind | ((d.kind == 3 && d.S == pr.y) ? 4 : 0));
     }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = carry;
+    const U3L tot = block_sum(c, wsum);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
 // Sum of the block totals of a pass (one block), for the host-sized passes.
@@ -243,16 +237,19 @@ __global__ __launch_bounds__(TB) void walk_total_kernel(const U3L* __restrict__ 
 }
 
 // Every block sums the block totals itself (the pass total and its own
-// offset), so no scan launch sits between counting and emitting.
+// offset), so no scan launch sits between counting and emitting; offsets
+// inside the block come from a scan of the counts, recomputed from the
+// stored decisions.
 __global__ __launch_bounds__(TB) void walk_emit_pass_kernel(WalkNodes w, const int2* __restrict__ fr,
                                                             WalkState* __restrict__ st, int pass,
                                                             const uint8_t* __restrict__ dec,
-                                                            const U3* __restrict__ off, const U3L* __restrict__ bsum,
+                                                            const U3L* __restrict__ bsum,
                                                             int2* __restrict__ next, int2* __restrict__ far,
                                                             int2* __restrict__ near, uint32_t cap_next,
                                                             unsigned long long cap_far,
                                                             unsigned long long cap_near) {
     __shared__ U3L wsum[TB / kWave];
+    __shared__ U3 wsum3[TB / kWave];
     U3L before{0ull, 0ull, 0ull}, all{0ull, 0ull, 0ull};
     for (int j = threadIdx.x; j < (int)gridDim.x; j += TB) {
         const U3L x = bsum[j];
@@ -284,30 +281,49 @@ __global__ __launch_bounds__(TB) void walk_emit_pass_kernel(WalkNodes w, const i
     }
     int64_t t0, t1;
     block_tiles(nf, t0, t1);
-    const int64_t iend = t1 * TB < (int64_t)nf ? t1 * TB : (int64_t)nf;
-    for (int64_t i = t0 * TB + threadIdx.x; i < iend; i += TB) {
-        const int2 pr = fr[i];
-        const int code = dec[i];
-        const int kind = code & 3;
-        const U3L o = u3ladd(B, off[i]);
-        const int32_t lo = pr.x < pr.y ? pr.x : pr.y, hi = pr.x < pr.y ? pr.y : pr.x;
-        if (kind == 0) {
-            near[near0 + o.c] = make_int2(lo, hi);
-        } else if (kind == 1) {
-            far[far0 + o.b] = make_int2(lo, hi);
-        } else if (kind == 2) {
-            const int4 tp = w.top[pr.x];
-            const int32_t c0 = tp.z, nc = tp.x;
-            int2* q = next + o.a;
-            for (int32_t x = 0; x < nc; ++x)
-                for (int32_t y = x; y < nc; ++y) *q++ = make_int2(c0 + x, c0 + y);
-        } else {
-            const int32_t S = (code & 4) ? pr.y : pr.x, O = (code & 4) ? pr.x : pr.y;
-            const int4 tp = w.top[S];
-            const int32_t c0 = tp.z, nc = tp.x;
-            int2* q = next + o.a;
-            for (int32_t x = 0; x < nc; ++x) q[x] = make_int2(c0 + x, O);
+    U3L carry = B;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t i = t * TB + threadIdx.x;
+        int2 pr = make_int2(0, 0);
+        int kind = -1;
+        int32_t S = 0, O = 0, c0 = 0, nc = 0;
+        U3 c{0u, 0u, 0u};
+        if (i < (int64_t)nf) {
+            pr = fr[i];
+            const int code = dec[i];
+            kind = code & 3;
+            if (kind == 0) {
+                c.c = 1u;
+            } else if (kind == 1) {
+                c.b = 1u;
+            } else {
+                S = (kind == 3 && (code & 4)) ? pr.y : pr.x;
+                O = (S == pr.x) ? pr.y : pr.x;
+                const int4 tp = w.top[S];
+                c0 = tp.z;
+                nc = tp.x;
+                c.a = kind == 2 ? (uint32_t)(nc * (nc + 1) / 2) : (uint32_t)nc;
+            }
         }
+        U3 tot;
+        const U3 e = block_excl_scan(c, wsum3, tot);
+        if (kind >= 0) {
+            const U3L o = u3ladd(carry, e);
+            const int32_t lo = pr.x < pr.y ? pr.x : pr.y, hi = pr.x < pr.y ? pr.y : pr.x;
+            if (kind == 0) {
+                near[near0 + o.c] = make_int2(lo, hi);
+            } else if (kind == 1) {
+                far[far0 + o.b] = make_int2(lo, hi);
+            } else if (kind == 2) {
+                int2* q = next + o.a;
+                for (int32_t x = 0; x < nc; ++x)
+                    for (int32_t y = x; y < nc; ++y) *q++ = make_int2(c0 + x, c0 + y);
+            } else {
+                int2* q = next + o.a;
+                for (int32_t x = 0; x < nc; ++x) q[x] = make_int2(c0 + x, O);
+            }
+        }
+        carry = u3ladd(carry, tot);
     }
 }
 
@@ -708,10 +724,8 @@ void walk_bfs_sized(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
         const unsigned g = (unsigned)std::min<int64_t>(kWalkGrid, cdiv(nf, TB));
         // buffers resized here are idle: a resize waits for the device
         t.w_dec.ensure(ctx, (size_t)nf);
-        t.w_cnt.ensure(ctx, (size_t)nf * sizeof(U3));
         hipLaunchKernelGGL(walk_count_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur->as<int2>(),
-                           (const WalkState*)st, parity, theta, t.w_dec.as<uint8_t>(), t.w_cnt.as<U3>(),
-                           t.w_off.as<U3L>());
+                           (const WalkState*)st, parity, theta, t.w_dec.as<uint8_t>(), t.w_off.as<U3L>());
         TFMM_LAUNCHED();
         hipLaunchKernelGGL(walk_total_kernel, dim3(1), dim3(TB), 0, s, (const U3L*)t.w_off.as<U3L>(), (int)g, tot);
         TFMM_LAUNCHED();
@@ -729,8 +743,7 @@ void walk_bfs_sized(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
         nxt->ensure(ctx, (size_t)std::max<unsigned long long>(T.a, 1) * 8);
         const size_t cap_next = std::min<size_t>(nxt->cap / 8, UINT32_MAX);
         hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur->as<int2>(), st, k,
-                           (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3*)t.w_cnt.as<U3>(),
-                           (const U3L*)t.w_off.as<U3L>(), nxt->as<int2>(), t.m2l_pairs.as<int2>(),
+                           (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3L*)t.w_off.as<U3L>(), nxt->as<int2>(), t.m2l_pairs.as<int2>(),
                            t.p2p_pairs.as<int2>(), (uint32_t)cap_next, (unsigned long long)(t.m2l_pairs.cap / 8),
                            (unsigned long long)(t.p2p_pairs.cap / 8));
         TFMM_LAUNCHED();
@@ -764,13 +777,11 @@ bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
     t.w_fr.ensure(ctx, (size_t)want_fr * 8);
     t.w_fr2.ensure(ctx, (size_t)want_fr * 8);
     t.w_dec.ensure(ctx, (size_t)want_fr);
-    t.w_cnt.ensure(ctx, (size_t)want_fr * sizeof(U3));
     t.w_off.ensure(ctx, (size_t)kWalkGrid * sizeof(U3L));
     t.m2l_pairs.ensure(ctx, (size_t)want_far * 8);
     t.p2p_pairs.ensure(ctx, (size_t)want_near * 8);
     t.w_state.ensure(ctx, sizeof(WalkState));
-    const size_t cap_next = std::min({t.w_fr.cap / 8, t.w_fr2.cap / 8, t.w_dec.cap, t.w_cnt.cap / sizeof(U3),
-                                      (size_t)UINT32_MAX});
+    const size_t cap_next = std::min({t.w_fr.cap / 8, t.w_fr2.cap / 8, t.w_dec.cap, (size_t)UINT32_MAX});
     const unsigned long long cap_far = t.m2l_pairs.cap / 8, cap_near = t.p2p_pairs.cap / 8;
     const int passes = 2 * t.max_level + 1;
     if (passes > kMaxPasses) return false;
@@ -809,12 +820,10 @@ bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
         } else {
             const unsigned g = (unsigned)std::min<int64_t>(kWalkGrid, cdiv(expect, TB));
             hipLaunchKernelGGL(walk_count_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur,
-                               (const WalkState*)st, parity, theta, t.w_dec.as<uint8_t>(), t.w_cnt.as<U3>(),
-                               t.w_off.as<U3L>());
+                               (const WalkState*)st, parity, theta, t.w_dec.as<uint8_t>(), t.w_off.as<U3L>());
             TFMM_LAUNCHED();
             hipLaunchKernelGGL(walk_emit_pass_kernel, dim3(g), dim3(TB), 0, s, w, (const int2*)cur, st, k,
-                               (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3*)t.w_cnt.as<U3>(),
-                               (const U3L*)t.w_off.as<U3L>(), nxt, t.m2l_pairs.as<int2>(), t.p2p_pairs.as<int2>(),
+                               (const uint8_t*)t.w_dec.as<uint8_t>(), (const U3L*)t.w_off.as<U3L>(), nxt, t.m2l_pairs.as<int2>(), t.p2p_pairs.as<int2>(),
                                (uint32_t)cap_next, cap_far, cap_near);
             TFMM_LAUNCHED();
         }
