@@ -2,7 +2,8 @@
 //
 // One histogram kernel counts the digits of every pass at once (the global
 // digit totals do not depend on the order of the keys).  Each pass is then a
-// single kernel over 4096-key tiles: a tile ranks its keys (wave ballots find
+// single kernel over 4096-key tiles: a tile scans the pass's digit totals
+// itself (the output start of every digit), ranks its keys (wave ballots find
 // the lanes sharing a digit, a per-wave LDS counter carries ranks across
 // rounds), publishes its per-digit counts, and finds the number of keys with
 // the same digit in all earlier tiles by looking back over their published
@@ -44,6 +45,10 @@ template <typename K> constexpr int tile_keys() { return RB * keys_per_lane<K>()
 constexpr int RADIX = 256;
 constexpr int MAXP = 8;          // passes of a 64-bit key
 constexpr int kHistBlocks = 1024;
+#ifndef TFMM_HIST_KPT
+#define TFMM_HIST_KPT 16
+#endif
+constexpr int kHistKeysPerThread = TFMM_HIST_KPT;  // fewer blocks, fewer global atomics
 constexpr uint32_t kSpinLimit = 1u << 20;
 
 // Tile status word: bits 62..63 flag (0 none, 1 own count, 2 running total
@@ -135,28 +140,10 @@ __global__ __launch_bounds__(RB) void radix_hist_all_kernel(Src src, int64_t n, 
     }
 }
 
-// Exclusive scan of each pass's 256 digit totals (one block).
-__global__ __launch_bounds__(RB) void radix_digit_base_kernel(uint32_t* __restrict__ ghist, int passes) {
-    __shared__ uint32_t sh[RB];
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t x = ghist[p * RADIX + threadIdx.x];
-        sh[threadIdx.x] = x;
-        __syncthreads();
-        for (int d = 1; d < RB; d <<= 1) {
-            const uint32_t y = (threadIdx.x >= (unsigned)d) ? sh[threadIdx.x - d] : 0u;
-            __syncthreads();
-            sh[threadIdx.x] += y;
-            __syncthreads();
-        }
-        ghist[p * RADIX + threadIdx.x] = sh[threadIdx.x] - x;
-        __syncthreads();
-    }
-}
-
 template <typename K, typename Src>
 __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__ kout, int32_t* __restrict__ vout,
                                                         int64_t n,
-                                                        int shift, const uint32_t* __restrict__ dbase,
+                                                        int shift, const uint32_t* __restrict__ dcount,
                                                         unsigned long long* __restrict__ status,
                                                         uint32_t* __restrict__ ticket, uint32_t* __restrict__ err) {
     __shared__ uint32_t wcnt[RW][RADIX];
@@ -165,6 +152,7 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
     constexpr int RI = keys_per_lane<K>();
     constexpr int RTILE = tile_keys<K>();
     __shared__ uint32_t wsum[RW];
+    __shared__ uint32_t hsum[RW];
     __shared__ K skeys[RTILE];
     __shared__ int32_t svals[RTILE];
     __shared__ uint32_t s_tile;
@@ -172,6 +160,7 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    const uint32_t hc = dcount[threadIdx.x];  // all keys with this thread's digit
     for (int ww = 0; ww < RW; ++ww) wcnt[ww][threadIdx.x] = 0;
     __syncthreads();
     const int64_t tile = s_tile;
@@ -260,19 +249,29 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
         }
         __hip_atomic_store(&st[d], kFlagTotal | (excl + real), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    gbase[d] = (unsigned long long)dbase[d] + excl;
-
-    uint32_t incl = tot;
+    // digit starts inside the tile and in the output (scans over digits)
+    uint32_t incl = tot, hincl = hc;
 #pragma unroll
     for (int s = 1; s < kWave; s <<= 1) {
         const uint32_t u = __shfl_up(incl, s, kWave);
-        if (lane >= s) incl += u;
+        const uint32_t hu = __shfl_up(hincl, s, kWave);
+        if (lane >= s) {
+            incl += u;
+            hincl += hu;
+        }
     }
-    if (lane == kWave - 1) wsum[w] = incl;
+    if (lane == kWave - 1) {
+        wsum[w] = incl;
+        hsum[w] = hincl;
+    }
     __syncthreads();
-    uint32_t woff = 0;
-    for (int ww = 0; ww < w; ++ww) woff += wsum[ww];
+    uint32_t woff = 0, hoff = 0;
+    for (int ww = 0; ww < w; ++ww) {
+        woff += wsum[ww];
+        hoff += hsum[ww];
+    }
     dstart[d] = woff + incl - tot;
+    gbase[d] = (unsigned long long)(hoff + hincl - hc) + excl;
     __syncthreads();
 
 #pragma unroll
@@ -292,10 +291,10 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
     }
 }
 
-// Scratch layout: digit bases [MAXP][RADIX] u32, tickets [MAXP] u32 (padded),
+// Scratch layout: digit counts [MAXP][RADIX] u32, tickets [MAXP] u32 (padded),
 // then the tile status words [passes][tiles][RADIX] u64.
 struct SortScratch {
-    uint32_t* dbase;
+    uint32_t* dcount;
     uint32_t* ticket;
     unsigned long long* status;
     int64_t zero_words;  // u64 words to clear from the start of the scratch
@@ -305,7 +304,7 @@ SortScratch carve(void* scratch, int64_t n, int passes, int rtile) {
     const int64_t nb = cdiv(n > 0 ? n : 1, rtile);
     auto* base = static_cast<unsigned long long*>(scratch);
     SortScratch s;
-    s.dbase = reinterpret_cast<uint32_t*>(base);                          // MAXP*RADIX u32 = 1024 u64
+    s.dcount = reinterpret_cast<uint32_t*>(base);                          // MAXP*RADIX u32 = 1024 u64
     s.ticket = reinterpret_cast<uint32_t*>(base + MAXP * RADIX / 2);      // 64 u64 of room
     s.status = base + MAXP * RADIX / 2 + 64;
     s.zero_words = MAXP * RADIX / 2 + 64 + (int64_t)passes * nb * RADIX;
@@ -326,16 +325,14 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
     hipLaunchKernelGGL(zero_u64_kernel, dim3(zb), dim3(RB), 0, s, static_cast<unsigned long long*>(scratch),
                        sc.zero_words);
     TFMM_LAUNCHED();
-    const unsigned hb = (unsigned)std::min<int64_t>(kHistBlocks, cdiv(n, RB * 4));
-    hipLaunchKernelGGL((radix_hist_all_kernel<K, Src>), dim3(hb), dim3(RB), 0, s, src, n, passes, sc.dbase);
-    TFMM_LAUNCHED();
-    hipLaunchKernelGGL(radix_digit_base_kernel, dim3(1), dim3(RB), 0, s, sc.dbase, passes);
+    const unsigned hb = (unsigned)std::min<int64_t>(kHistBlocks, cdiv(n, RB * kHistKeysPerThread));
+    hipLaunchKernelGGL((radix_hist_all_kernel<K, Src>), dim3(hb), dim3(RB), 0, s, src, n, passes, sc.dcount);
     TFMM_LAUNCHED();
     for (int ps = 0; ps < passes; ++ps) {
         const bool to_out = ((passes - 1 - ps) & 1) == 0;
         K* ko = to_out ? kout : kalt;
         int32_t* vo = to_out ? vout : valt;
-        const uint32_t* db = sc.dbase + ps * RADIX;
+        const uint32_t* db = sc.dcount + ps * RADIX;
         unsigned long long* st = sc.status + (int64_t)ps * nb * RADIX;
         if (ps == 0) {
             hipLaunchKernelGGL((radix_pass_kernel<K, Src>), dim3(nb), dim3(RB), 0, s, src, ko, vo, n, 0, db, st,
