@@ -107,7 +107,8 @@ struct Tree {
     double walk_theta = -1.0;
     int64_t n_m2l = -1, n_p2p = -1, n_near_int = -1;
     DevBuf m2l_pairs, p2p_pairs;  // int2, lower node id first
-    DevBuf m2l_off, m2l_src;      // per-target CSR (node ids), directed
+    DevBuf m2l_off, m2l_src;      // per-target CSR, directed: source = m2l_src[q] & m2l_src_mask
+    uint32_t m2l_src_mask = 0xffffffffu;  // 0xffff when entries are packed (target << 16) | source
     DevBuf p2p_off, p2p_src;
     DevBuf w_fr, w_fr2, w_cnt, w_off, w_tg, w_sr, w_fl, w_c;  // walk and list-building scratch
     DevBuf w_state, w_res, w_dec; // device-side walk counters, list totals, pair decisions
@@ -175,6 +176,10 @@ void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* 
 void radix_sort_pairs(const int2* pairs, int64_t np, bool self_dummy, uint32_t self_key, uint32_t* keys,
                       int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int bits, void* scratch,
                       uint32_t* err, hipStream_t s);
+// The same entries packed as (x << 16) | y words (node ids below 2^16),
+// stably sorted by their high half (its low `bits` bits); no values.
+void radix_sort_pairs_packed16(const int2* pairs, int64_t np, uint32_t* keys, uint32_t* keys_alt, int bits,
+                               void* scratch, uint32_t* err, hipStream_t s);
 
 // Copies one device value to the host together with the context's device
 // error word, with a single synchronisation; fails if a kernel set the word.

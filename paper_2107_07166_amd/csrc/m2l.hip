@@ -57,7 +57,7 @@ __device__ __forceinline__ T half_wave_sum_last(T v) {
 template <int P, int VAR, typename T>
 __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
                                                  const uint32_t* __restrict__ off,
-                                                 const int32_t* __restrict__ src,
+                                                 const uint32_t* __restrict__ src, uint32_t src_mask,
                                                  const double4* __restrict__ Z, const T* __restrict__ W,
                                                  double eps2, double* __restrict__ loc) {
     using E = Expansion<P>;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
     for (int k = 0; k < NOUT; ++k) acc[k] = T(0);
     const uint32_t q0 = has ? off[A] : 0u, q1 = has ? off[A + 1] : 0u;
     for (uint32_t q = q0 + sl; q < q1; q += LPT) {
-        const int32_t B = src[q];
+        const int32_t B = (int32_t)(src[q] & src_mask);
         const double4 zb = Z[B];
         const T Rx = (T)(za.x - zb.x), Ry = (T)(za.y - zb.y), Rz = (T)(za.z - zb.z);
         const T s = Rx * Rx + Ry * Ry + Rz * Rz + (T)eps2;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
 template <int P, int POLY, typename T>
 __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
                                                            const uint32_t* __restrict__ off,
-                                                           const int32_t* __restrict__ src,
+                                                           const uint32_t* __restrict__ src, uint32_t src_mask,
                                                            const double4* __restrict__ Z, const T* __restrict__ W,
                                                            double eps2, double* __restrict__ loc) {
     using E = Expansion<P>;
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
     for (int k = 0; k < NC1; ++k) acc[k] = T(0);
     const uint32_t q0 = has ? off[A] : 0u, q1 = has ? off[A + 1] : 0u;
     for (uint32_t q = q0 + sl; q < q1; q += LPT) {
-        const int32_t B = src[q];
+        const int32_t B = (int32_t)(src[q] & src_mask);
         const double4 zb = Z[B];
         const T Rx = (T)(za.x - zb.x), Ry = (T)(za.y - zb.y), Rz = (T)(za.z - zb.z);
         const T s = Rx * Rx + Ry * Ry + Rz * Rz + (T)eps2;
@@ -199,24 +199,24 @@ void launch(Tree& t, double eps2, hipStream_t s) {
     const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, MB));
     if constexpr (VAR == TFMM_CONSERVING && P >= kConsSplitP) {
         hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 0, T>), grid, dim3(MB), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
         hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 1, T>), grid, dim3(MB), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
         hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 2, T>), grid, dim3(MB), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
         hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 3, T>), grid, dim3(MB), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
     } else {
         hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), grid, dim3(MB), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<int32_t>(), t.nd_Z.as<double4>(), W, eps2,
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
     }

@@ -23,6 +23,8 @@
 // key and value arrays, or an array of node pairs read as directed entries
 // (entry 2i = (x_i <- y_i), entry 2i + 1 = (y_i <- x_i)), which spares the
 // lists an expansion pass before the sort.
+#include <algorithm>
+
 #include "common.h"
 
 namespace tfmm {
@@ -39,9 +41,15 @@ namespace {
 #endif
 constexpr int RB = 256;           // threads per block (one digit per thread)
 constexpr int RW = RB / kWave;    // waves per block
-// keys per lane: 64-bit keys stage twice the bytes in LDS
-template <typename K> constexpr int keys_per_lane() { return sizeof(K) == 8 ? TFMM_SORT_RI64 : TFMM_SORT_RI32; }
-template <typename K> constexpr int tile_keys() { return RB * keys_per_lane<K>(); }
+#ifndef TFMM_SORT_RI32K
+#define TFMM_SORT_RI32K 16
+#endif
+// keys per lane: 64-bit keys stage twice the bytes in LDS; keys without
+// values stage half
+template <typename K, bool HV> constexpr int keys_per_lane() {
+    return sizeof(K) == 8 ? TFMM_SORT_RI64 : (HV ? TFMM_SORT_RI32 : TFMM_SORT_RI32K);
+}
+template <typename K, bool HV> constexpr int tile_keys() { return RB * keys_per_lane<K, HV>(); }
 constexpr int RADIX = 256;
 constexpr int MAXP = 8;          // passes of a 64-bit key
 constexpr int kHistBlocks = 1024;
@@ -104,13 +112,35 @@ struct PairSrc {
     }
 };
 
+// Keys alone.
+template <typename K>
+struct KeySrc {
+    const K* k;
+    __device__ __forceinline__ void load(int64_t i, K& key, int32_t& val) const {
+        key = k[i];
+        val = 0;
+    }
+};
+
+// Directed entries of node pairs packed into one word, (target << 16) |
+// source, for node ids below 2^16; no values.
+struct PairPack16Src {
+    const int2* p;
+    __device__ __forceinline__ void load(int64_t i, uint32_t& key, int32_t& val) const {
+        const int2 q = p[i >> 1];
+        const uint32_t x = (uint32_t)q.x, y = (uint32_t)q.y;
+        key = (i & 1) ? ((y << 16) | x) : ((x << 16) | y);
+        val = 0;
+    }
+};
+
 __global__ __launch_bounds__(RB) void zero_u64_kernel(unsigned long long* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) p[i] = 0ull;
 }
 
 // Digit totals of every pass: LDS counters per block, then global atomics.
 template <typename K, typename Src>
-__global__ __launch_bounds__(RB) void radix_hist_all_kernel(Src src, int64_t n, int passes,
+__global__ __launch_bounds__(RB) void radix_hist_all_kernel(Src src, int64_t n, int shift0, int passes,
                                                             uint32_t* __restrict__ ghist) {
     __shared__ uint32_t h[MAXP][RADIX];
     for (int p = 0; p < MAXP; ++p) h[p][threadIdx.x] = 0u;
@@ -129,7 +159,8 @@ __global__ __launch_bounds__(RB) void radix_hist_all_kernel(Src src, int64_t n, 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (base + (int64_t)u * RB + threadIdx.x < n) {
-                for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(k[u] >> (8 * p)) & (RADIX - 1)], 1u);
+                for (int p = 0; p < passes; ++p)
+                    atomicAdd(&h[p][(uint32_t)(k[u] >> (shift0 + 8 * p)) & (RADIX - 1)], 1u);
             }
         }
     }
@@ -140,7 +171,7 @@ __global__ __launch_bounds__(RB) void radix_hist_all_kernel(Src src, int64_t n, 
     }
 }
 
-template <typename K, typename Src>
+template <typename K, bool HV, typename Src>
 __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__ kout, int32_t* __restrict__ vout,
                                                         int64_t n,
                                                         int shift, const uint32_t* __restrict__ dcount,
@@ -149,12 +180,12 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
     __shared__ uint32_t wcnt[RW][RADIX];
     __shared__ uint32_t dstart[RADIX];
     __shared__ unsigned long long gbase[RADIX];
-    constexpr int RI = keys_per_lane<K>();
-    constexpr int RTILE = tile_keys<K>();
+    constexpr int RI = keys_per_lane<K, HV>();
+    constexpr int RTILE = tile_keys<K, HV>();
     __shared__ uint32_t wsum[RW];
     __shared__ uint32_t hsum[RW];
     __shared__ K skeys[RTILE];
-    __shared__ int32_t svals[RTILE];
+    __shared__ int32_t svals[HV ? RTILE : 1];
     __shared__ uint32_t s_tile;
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -278,7 +309,7 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
     for (int r = 0; r < RI; ++r) {
         const uint32_t pos = dstart[dig[r]] + wcnt[w][dig[r]] + rank[r];
         skeys[pos] = k[r];
-        svals[pos] = v[r];
+        if constexpr (HV) svals[pos] = v[r];
     }
     __syncthreads();
 
@@ -287,7 +318,7 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
         const uint32_t dd = (uint32_t)((kk >> shift) & (RADIX - 1));
         const int64_t dst = (int64_t)gbase[dd] + (i - (int64_t)dstart[dd]);
         kout[dst] = kk;
-        vout[dst] = svals[i];
+        if constexpr (HV) vout[dst] = svals[i];
     }
 }
 
@@ -311,13 +342,14 @@ SortScratch carve(void* scratch, int64_t n, int passes, int rtile) {
     return s;
 }
 
-// Sorts n entries read from src; pass ps writes (kout, vout) when the
-// number of passes after it is even, else the alternate arrays, so the last
-// pass always lands in (kout, vout).
-template <typename K, typename Src>
-void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int64_t n, int bits, void* scratch,
-                    uint32_t* err, hipStream_t s) {
-    constexpr int RTILE = tile_keys<K>();
+// Sorts n entries read from src by bits [shift0, shift0 + bits) of the key;
+// pass ps writes (kout, vout) when the number of passes after it is even,
+// else the alternate arrays, so the last pass always lands in (kout, vout).
+// Without values (HV false) the value arrays are not touched.
+template <typename K, bool HV, typename Src>
+void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int64_t n, int shift0, int bits,
+                    void* scratch, uint32_t* err, hipStream_t s) {
+    constexpr int RTILE = tile_keys<K, HV>();
     const int passes = (bits + 7) / 8;
     const int nb = (int)cdiv(n, RTILE);
     const SortScratch sc = carve(scratch, n, passes, RTILE);
@@ -326,7 +358,8 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
                        sc.zero_words);
     TFMM_LAUNCHED();
     const unsigned hb = (unsigned)std::min<int64_t>(kHistBlocks, cdiv(n, RB * kHistKeysPerThread));
-    hipLaunchKernelGGL((radix_hist_all_kernel<K, Src>), dim3(hb), dim3(RB), 0, s, src, n, passes, sc.dcount);
+    hipLaunchKernelGGL((radix_hist_all_kernel<K, Src>), dim3(hb), dim3(RB), 0, s, src, n, shift0, passes,
+                       sc.dcount);
     TFMM_LAUNCHED();
     for (int ps = 0; ps < passes; ++ps) {
         const bool to_out = ((passes - 1 - ps) & 1) == 0;
@@ -334,14 +367,19 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
         int32_t* vo = to_out ? vout : valt;
         const uint32_t* db = sc.dcount + ps * RADIX;
         unsigned long long* st = sc.status + (int64_t)ps * nb * RADIX;
+        const int shift = shift0 + 8 * ps;
         if (ps == 0) {
-            hipLaunchKernelGGL((radix_pass_kernel<K, Src>), dim3(nb), dim3(RB), 0, s, src, ko, vo, n, 0, db, st,
-                               sc.ticket, err);
-        } else {
+            hipLaunchKernelGGL((radix_pass_kernel<K, HV, Src>), dim3(nb), dim3(RB), 0, s, src, ko, vo, n, shift,
+                               db, st, sc.ticket, err);
+        } else if constexpr (HV) {
             // the previous pass wrote the other pair of arrays
             const ArraySrc<K> prev{to_out ? kalt : kout, to_out ? valt : vout};
-            hipLaunchKernelGGL((radix_pass_kernel<K, ArraySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, ko, vo, n,
-                               8 * ps, db, st, sc.ticket + ps, err);
+            hipLaunchKernelGGL((radix_pass_kernel<K, HV, ArraySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, ko, vo, n,
+                               shift, db, st, sc.ticket + ps, err);
+        } else {
+            const KeySrc<K> prev{to_out ? kalt : kout};
+            hipLaunchKernelGGL((radix_pass_kernel<K, HV, KeySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, ko, vo, n,
+                               shift, db, st, sc.ticket + ps, err);
         }
         TFMM_LAUNCHED();
     }
@@ -357,9 +395,11 @@ void radix_sort_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int
         // copy there back into the caller's arrays
         TFMM_HIP(hipMemcpyAsync(keys_alt, keys, (size_t)n * sizeof(K), hipMemcpyDeviceToDevice, s));
         TFMM_HIP(hipMemcpyAsync(vals_alt, vals, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        radix_sort_run<K>(ArraySrc<K>{keys_alt, vals_alt}, keys, vals, keys_alt, vals_alt, n, bits, scratch, err, s);
+        radix_sort_run<K, true>(ArraySrc<K>{keys_alt, vals_alt}, keys, vals, keys_alt, vals_alt, n, 0, bits, scratch,
+                                err, s);
     } else {
-        radix_sort_run<K>(ArraySrc<K>{keys, vals}, keys, vals, keys_alt, vals_alt, n, bits, scratch, err, s);
+        radix_sort_run<K, true>(ArraySrc<K>{keys, vals}, keys, vals, keys_alt, vals_alt, n, 0, bits, scratch, err,
+                                s);
     }
 }
 
@@ -367,7 +407,7 @@ void radix_sort_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int
 
 size_t sort_scratch_bytes(int64_t n, int bits) {
     const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
-    const int rtile = std::min(tile_keys<uint32_t>(), tile_keys<uint64_t>());
+    const int rtile = std::min({tile_keys<uint32_t, true>(), tile_keys<uint32_t, false>(), tile_keys<uint64_t, true>()});
     return (size_t)carve(nullptr, n, passes, rtile).zero_words * 8 + 256;
 }
 
@@ -386,8 +426,16 @@ void radix_sort_pairs(const int2* pairs, int64_t np, bool self_dummy, uint32_t s
                       hipStream_t s) {
     const int64_t n = 2 * np;
     if (n <= 0) return;
-    radix_sort_run<uint32_t>(PairSrc{pairs, self_key, self_dummy ? 1 : 0}, keys, vals, keys_alt, vals_alt, n,
-                             bits > 0 ? bits : 1, scratch, err, s);
+    radix_sort_run<uint32_t, true>(PairSrc{pairs, self_key, self_dummy ? 1 : 0}, keys, vals, keys_alt, vals_alt, n,
+                                   0, bits > 0 ? bits : 1, scratch, err, s);
+}
+
+void radix_sort_pairs_packed16(const int2* pairs, int64_t np, uint32_t* keys, uint32_t* keys_alt, int bits,
+                               void* scratch, uint32_t* err, hipStream_t s) {
+    const int64_t n = 2 * np;
+    if (n <= 0) return;
+    radix_sort_run<uint32_t, false>(PairPack16Src{pairs}, keys, nullptr, keys_alt, nullptr, n, 16,
+                                    bits > 0 ? std::min(bits, 16) : 1, scratch, err, s);
 }
 
 }  // namespace tfmm

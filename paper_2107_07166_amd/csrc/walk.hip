@@ -539,19 +539,20 @@ __global__ __launch_bounds__(TB) void walk_pass_kernel(WalkNodes w, const int2* 
     }
 }
 
-// CSR offsets from targets sorted ascending: off[t] = first entry with target
-// >= t, for t = 0..nn (each t written by exactly one thread, which also
-// copies off[nn], the number of entries below nn, to *below_nn if given).
-// Keys may equal nn (entries sorted after every real one).
+// CSR offsets from targets sorted ascending (target = keys[i] >> shift):
+// off[t] = first entry with target >= t, for t = 0..nn, one thread per entry
+// boundary (each t written by exactly one thread, which also copies off[nn],
+// the number of entries below nn, to *below_nn if given).  Targets may equal
+// nn (entries sorted after every real one).
 __global__ __launch_bounds__(TB) void csr_offsets_kernel(const uint32_t* __restrict__ keys, int64_t ne,
-                                                         int64_t nn, uint32_t* __restrict__ off,
+                                                         int64_t nn, int shift, uint32_t* __restrict__ off,
                                                          uint32_t* __restrict__ below_nn) {
-    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i <= ne; i += (int64_t)gridDim.x * TB) {
-        const int64_t lo = (i == 0) ? 0 : (int64_t)keys[i - 1] + 1;
-        const int64_t hi = (i == ne) ? nn : std::min<int64_t>((int64_t)keys[i], nn);
-        for (int64_t t = lo; t <= hi; ++t) off[t] = (uint32_t)i;
-        if (below_nn && lo <= nn && nn <= hi) *below_nn = (uint32_t)i;
-    }
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i > ne) return;
+    const int64_t lo = (i == 0) ? 0 : (int64_t)(keys[i - 1] >> shift) + 1;
+    const int64_t hi = (i == ne) ? nn : std::min<int64_t>((int64_t)(keys[i] >> shift), nn);
+    for (int64_t t = lo; t <= hi; ++t) off[t] = (uint32_t)i;
+    if (below_nn && lo <= nn && nn <= hi) *below_nn = (uint32_t)i;
 }
 
 __global__ __launch_bounds__(TB) void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
@@ -683,12 +684,36 @@ void build_csr_pairs(Tree& t, const DevBuf& pairs, int64_t np, bool self_dummy, 
     radix_sort_pairs(pairs.as<int2>(), np, self_dummy, (uint32_t)nn, tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(),
                      kalt, valt, bits, scr.p, ctx->dev_err, s);
     off.ensure(ctx, (size_t)(nn + 1) * 4);
-    hipLaunchKernelGGL(csr_offsets_kernel, dim3((unsigned)std::min<int64_t>(2048, grid(ne + 1))), dim3(TB), 0, s,
-                       (const uint32_t*)tgtbuf.as<uint32_t>(), ne, nn, off.as<uint32_t>(), real_out);
+    hipLaunchKernelGGL(csr_offsets_kernel, dim3(grid(ne + 1)), dim3(TB), 0, s,
+                       (const uint32_t*)tgtbuf.as<uint32_t>(), ne, nn, 0, off.as<uint32_t>(), real_out);
     TFMM_LAUNCHED();
     std::swap(srcbuf.p, srcout.p);
     std::swap(srcbuf.cap, srcout.cap);
     std::swap(srcbuf.ctx, srcout.ctx);
+}
+
+// The far lists with node ids below 2^16: entries packed as (target << 16) |
+// source and sorted as single words (half the bytes of separate arrays); the
+// sorted words become the source list, read through the mask 0xffff.
+void build_far_csr_packed(Tree& t, int64_t np, hipStream_t s) {
+    Ctx* ctx = t.ctx;
+    const int64_t nn = t.n_nodes;
+    const int64_t ne = 2 * np;
+    const int64_t room = std::max<int64_t>(ne, 1);
+    t.w_tg.ensure(ctx, (size_t)room * 4);
+    t.scratch2.ensure(ctx, (size_t)room * 4 + 256);
+    const int bits = bits_for(nn);
+    t.scratch.ensure(ctx, sort_scratch_bytes(ne, bits) + 1024);
+    radix_sort_pairs_packed16(t.m2l_pairs.as<int2>(), np, t.w_tg.as<uint32_t>(), t.scratch2.as<uint32_t>(), bits,
+                              t.scratch.p, ctx->dev_err, s);
+    t.m2l_off.ensure(ctx, (size_t)(nn + 1) * 4);
+    hipLaunchKernelGGL(csr_offsets_kernel, dim3(grid(ne + 1)), dim3(TB), 0, s, (const uint32_t*)t.w_tg.as<uint32_t>(),
+                       ne, nn, 16, t.m2l_off.as<uint32_t>(), nullptr);
+    TFMM_LAUNCHED();
+    std::swap(t.w_tg.p, t.m2l_src.p);
+    std::swap(t.w_tg.cap, t.m2l_src.cap);
+    std::swap(t.w_tg.ctx, t.m2l_src.ctx);
+    t.m2l_src_mask = 0xffffu;
 }
 
 // Frontier passes sized on the host: the totals of every pass are read back
@@ -898,8 +923,13 @@ void walk_lists_begin(Tree& t, double theta, hipStream_t s) {
     // on s; they share no buffer.
     aux_fork(t, s);
     // far lists: directed, by target
-    build_csr_pairs(t, t.m2l_pairs, n_far, false, t.w_tg, t.w_sr, t.m2l_off, t.m2l_src, t.scratch, t.scratch2,
-                    nullptr, t.aux);
+    if (nn <= 65536) {
+        build_far_csr_packed(t, n_far, t.aux);
+    } else {
+        build_csr_pairs(t, t.m2l_pairs, n_far, false, t.w_tg, t.w_sr, t.m2l_off, t.m2l_src, t.scratch, t.scratch2,
+                        nullptr, t.aux);
+        t.m2l_src_mask = 0xffffffffu;
+    }
     DevBuf& tg = t.w_tg_b;
     DevBuf& sr = t.w_sr_b;
     // near lists: directed (self pairs once), by target.  Every leaf has

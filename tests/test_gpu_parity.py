@@ -242,6 +242,29 @@ def test_full_size_plummer_1m(ctx):
     gt.close()
 
 
+def test_wide_node_ids(ctx):
+    """A tree with more than 2^16 nodes: its far lists cannot be packed into
+    16-bit target and source halves and take the separate-array sort.  Lists
+    and sampled forces must still match the oracle."""
+    pos, m = uniform_ball(150000, 5)
+    n_leaf, theta, p, eps = 4, 0.5, 4, 1e-3
+    ot = oracle.Tree(pos, m, n_leaf=n_leaf, theta=theta)
+    gt = _gpu_tree(ctx, pos, m, n_leaf)
+    assert gt.info()["nodes"] > 65536
+    gt.walk(theta)
+    gf, gn = gt.lists()
+    of, onr = ot.lists()
+    assert np.array_equal(_pairset(gf), _pairset(of))
+    assert np.array_equal(_pairset(gn), _pairset(onr))
+    sample = np.random.default_rng(2).choice(len(m), 32, replace=False)
+    for variant in ("standard", "conserving"):
+        ref = ot.forces(p, eps, variant, targets=sample)
+        for prec, tol in (("fp64", TOL_FP64), ("mixed32", TOL_MIXED)):
+            f = gt.evaluate(p=p, theta=theta, eps=eps, variant=variant, precision=prec).cpu().numpy()
+            assert _erms(f[sample], ref) <= tol, (variant, prec, _erms(f[sample], ref))
+    gt.close()
+
+
 @pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
 def test_nonfinite_positions_rejected(ctx, bad):
     """A non-finite coordinate is an argument error (detected on the device,
