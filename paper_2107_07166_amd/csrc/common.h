@@ -160,6 +160,9 @@ size_t scan_scratch_bytes(int64_t n);
 // *total_dev (device).  err: the context's device error word.
 void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
                         uint32_t* total_dev, uint32_t* err, hipStream_t s);
+// The same over gathered values: value i = val[idx[i]] (val non-negative).
+void exclusive_scan_gather_u32(const int32_t* idx, const int32_t* val, uint32_t* out, int64_t n, void* scratch,
+                               uint32_t* total_dev, uint32_t* err, hipStream_t s);
 
 // ---- radix sort (sort.hip) ----------------------------------------------------
 size_t sort_scratch_bytes(int64_t n, int bits);

@@ -9,7 +9,8 @@
 // earlier words at a time; a tile publishes before it waits and only waits
 // for tiles already running).  Each wait is bounded:
 // past kSpinLimit polls the device error word is set and the kernel ends.
-// In-place use (in == out) is allowed.
+// In-place use (in == out) is allowed.  The input may also be gathered:
+// value i = val[idx[i]].
 #include "common.h"
 
 namespace tfmm {
@@ -30,7 +31,18 @@ __global__ __launch_bounds__(SB) void scan_zero_kernel(unsigned long long* __res
     for (int64_t i = (int64_t)blockIdx.x * SB + threadIdx.x; i < n; i += (int64_t)gridDim.x * SB) p[i] = 0ull;
 }
 
-__global__ __launch_bounds__(SB) void scan_lookback_kernel(const uint32_t* in, uint32_t* out, int64_t n,
+struct ArrayIn {
+    const uint32_t* p;
+    __device__ __forceinline__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+struct GatherIn {
+    const int32_t* idx;
+    const int32_t* val;
+    __device__ __forceinline__ uint32_t operator()(int64_t i) const { return (uint32_t)val[idx[i]]; }
+};
+
+template <typename In>
+__global__ __launch_bounds__(SB) void scan_lookback_kernel(In in, uint32_t* out, int64_t n,
                                                            unsigned long long* __restrict__ status,
                                                            uint32_t* __restrict__ ticket,
                                                            uint32_t* __restrict__ total, uint32_t* __restrict__ err) {
@@ -46,7 +58,7 @@ __global__ __launch_bounds__(SB) void scan_lookback_kernel(const uint32_t* in, u
 #pragma unroll
     for (int r = 0; r < SI; ++r) {
         const int64_t i = t0 + r * SB + tid;
-        sv[pad(r * SB + tid)] = i < n ? in[i] : 0u;
+        sv[pad(r * SB + tid)] = i < n ? in(i) : 0u;
     }
     __syncthreads();
     uint32_t x[SI];
@@ -133,8 +145,8 @@ __global__ __launch_bounds__(SB) void scan_lookback_kernel(const uint32_t* in, u
 
 size_t scan_scratch_bytes(int64_t n) { return (size_t)(cdiv(n > 0 ? n : 1, STILE) + 64) * 8 + 256; }
 
-void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch, uint32_t* total_dev,
-                        uint32_t* err, hipStream_t s) {
+template <typename In>
+void scan_run(In in, uint32_t* out, int64_t n, void* scratch, uint32_t* total_dev, uint32_t* err, hipStream_t s) {
     const int64_t nb = cdiv(n > 0 ? n : 1, STILE);
     auto* words = static_cast<unsigned long long*>(scratch);
     uint32_t* ticket = reinterpret_cast<uint32_t*>(words);  // first 64 words: ticket
@@ -143,9 +155,19 @@ void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scra
     hipLaunchKernelGGL(scan_zero_kernel, dim3((unsigned)std::min<int64_t>(1024, cdiv(nz, SB))), dim3(SB), 0, s, words,
                        nz);
     TFMM_LAUNCHED();
-    hipLaunchKernelGGL(scan_lookback_kernel, dim3((unsigned)nb), dim3(SB), 0, s, in, out, n, status, ticket,
+    hipLaunchKernelGGL((scan_lookback_kernel<In>), dim3((unsigned)nb), dim3(SB), 0, s, in, out, n, status, ticket,
                        total_dev, err);
     TFMM_LAUNCHED();
+}
+
+void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch, uint32_t* total_dev,
+                        uint32_t* err, hipStream_t s) {
+    scan_run(ArrayIn{in}, out, n, scratch, total_dev, err, s);
+}
+
+void exclusive_scan_gather_u32(const int32_t* idx, const int32_t* val, uint32_t* out, int64_t n, void* scratch,
+                               uint32_t* total_dev, uint32_t* err, hipStream_t s) {
+    scan_run(GatherIn{idx, val}, out, n, scratch, total_dev, err, s);
 }
 
 }  // namespace tfmm

@@ -53,6 +53,11 @@ template <typename K, bool HV> constexpr int tile_keys() { return RB * keys_per_
 constexpr int RADIX = 256;
 constexpr int MAXP = 8;          // passes of a 64-bit key
 constexpr int kHistBlocks = 1024;
+// Sorts of at least this many tiles run reduce-then-scan passes.
+#ifndef TFMM_RTS_MIN_TILES
+#define TFMM_RTS_MIN_TILES 1024
+#endif
+constexpr int kRtsMinTiles = TFMM_RTS_MIN_TILES;
 #ifndef TFMM_HIST_KPT
 #define TFMM_HIST_KPT 16
 #endif
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(RB) void radix_hist_all_kernel(Src src, int64_t n, 
     __shared__ uint32_t h[MAXP][RADIX];
     for (int p = 0; p < MAXP; ++p) h[p][threadIdx.x] = 0u;
     __syncthreads();
-    constexpr int U = 4;
+    constexpr int U = kHistKeysPerThread;  // loads in flight per thread
     const int64_t stride = (int64_t)gridDim.x * RB * U;
     for (int64_t base = (int64_t)blockIdx.x * RB * U; base < n; base += stride) {
         K k[U];
@@ -322,6 +327,136 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
     }
 }
 
+// ---- reduce-then-scan passes (large inputs) --------------------------------
+// With thousands of tiles in flight, the look-back's chain of device-scope
+// reads sets the pace of a pass.  Large sorts therefore split a pass into
+// three launches with no waits: every tile counts its digits
+// (radix_up_kernel), one scan over the counts in digit-major order gives
+// every (digit, tile) run its output start, and every tile ranks its keys
+// again and scatters them (radix_down_kernel).  The tile layout and ranking
+// are those of the single-kernel pass, so the order is the same (stable).
+
+template <typename K, bool HV, typename Src>
+__global__ __launch_bounds__(RB) void radix_up_kernel(Src src, int64_t n, int shift, int64_t ntiles,
+                                                      uint32_t* __restrict__ cnt) {
+    constexpr int RI = keys_per_lane<K, HV>();
+    constexpr int RTILE = tile_keys<K, HV>();
+    __shared__ uint32_t wcnt[RW][RADIX];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    for (int ww = 0; ww < RW; ++ww) wcnt[ww][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t tile = blockIdx.x;
+    const int64_t wbase = tile * RTILE + (int64_t)w * (kWave * RI);
+    K k[RI];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+        const int64_t i = wbase + (int64_t)r * kWave + lane;
+        int32_t unused;
+        k[r] = (K)0;
+        if (i < n) src.load(i, k[r], unused);
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+        const bool valid = wbase + (int64_t)r * kWave + lane < n;
+        const uint32_t d = (uint32_t)((k[r] >> shift) & (RADIX - 1));
+        const uint64_t peers = digit_peers(d) & __ballot(valid);
+        if (valid && (peers & lt) == 0ull) wcnt[w][d] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    for (int ww = 0; ww < RW; ++ww) tot += wcnt[ww][threadIdx.x];
+    cnt[(int64_t)threadIdx.x * ntiles + tile] = tot;
+}
+
+template <typename K, bool HV, typename Src>
+__global__ __launch_bounds__(RB) void radix_down_kernel(Src src, K* __restrict__ kout, int32_t* __restrict__ vout,
+                                                        int64_t n, int shift, int64_t ntiles,
+                                                        const uint32_t* __restrict__ off) {
+    constexpr int RI = keys_per_lane<K, HV>();
+    constexpr int RTILE = tile_keys<K, HV>();
+    __shared__ uint32_t wcnt[RW][RADIX];
+    __shared__ uint32_t dstart[RADIX];
+    __shared__ uint32_t gbase[RADIX];
+    __shared__ uint32_t wsum[RW];
+    __shared__ K skeys[RTILE];
+    __shared__ int32_t svals[HV ? RTILE : 1];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int64_t tile = blockIdx.x;
+    const uint32_t gb = off[(int64_t)threadIdx.x * ntiles + tile];  // output start of this tile's digit run
+    for (int ww = 0; ww < RW; ++ww) wcnt[ww][threadIdx.x] = 0;
+    __syncthreads();
+
+    const int64_t tile0 = tile * RTILE;
+    const int64_t wbase = tile0 + (int64_t)w * (kWave * RI);
+    K k[RI];
+    int32_t v[RI];
+    uint32_t rank[RI];
+    uint32_t dig[RI];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+        const int64_t i = wbase + (int64_t)r * kWave + lane;
+        k[r] = (K)0;
+        v[r] = 0;
+        if (i < n) src.load(i, k[r], v[r]);
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+        const int64_t i = wbase + (int64_t)r * kWave + lane;
+        const uint32_t d = i < n ? (uint32_t)((k[r] >> shift) & (RADIX - 1)) : (uint32_t)RADIX - 1;
+        dig[r] = d;
+        const uint64_t peers = digit_peers(d);
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint32_t base = wcnt[w][d];
+        rank[r] = base + below;
+        if (below == 0) wcnt[w][d] = base + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+
+    const int d = threadIdx.x;
+    uint32_t tot = 0;
+    for (int ww = 0; ww < RW; ++ww) {
+        const uint32_t c = wcnt[ww][d];
+        wcnt[ww][d] = tot;
+        tot += c;
+    }
+    const int64_t rem = n - tile0;
+    const int valid_count = (int)(rem < RTILE ? rem : RTILE);
+    uint32_t incl = tot;
+#pragma unroll
+    for (int sh = 1; sh < kWave; sh <<= 1) {
+        const uint32_t u = __shfl_up(incl, sh, kWave);
+        if (lane >= sh) incl += u;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t woff = 0;
+    for (int ww = 0; ww < w; ++ww) woff += wsum[ww];
+    dstart[d] = woff + incl - tot;
+    gbase[d] = gb;
+    __syncthreads();
+
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+        const uint32_t pos = dstart[dig[r]] + wcnt[w][dig[r]] + rank[r];
+        skeys[pos] = k[r];
+        if constexpr (HV) svals[pos] = v[r];
+    }
+    __syncthreads();
+
+    // padding keys of the last tile sit after every valid key (digit 255, last)
+    for (int i = threadIdx.x; i < valid_count; i += RB) {
+        const K kk = skeys[i];
+        const uint32_t dd = (uint32_t)((kk >> shift) & (RADIX - 1));
+        const int64_t dst = (int64_t)gbase[dd] + (i - (int64_t)dstart[dd]);
+        kout[dst] = kk;
+        if constexpr (HV) vout[dst] = svals[i];
+    }
+}
+
 // Scratch layout: digit counts [MAXP][RADIX] u32, tickets [MAXP] u32 (padded),
 // then the tile status words [passes][tiles][RADIX] u64.
 struct SortScratch {
@@ -352,6 +487,48 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
     constexpr int RTILE = tile_keys<K, HV>();
     const int passes = (bits + 7) / 8;
     const int nb = (int)cdiv(n, RTILE);
+    if (nb >= kRtsMinTiles && (int64_t)nb * RADIX <= (int64_t)UINT32_MAX && n <= (int64_t)UINT32_MAX) {
+        // reduce-then-scan: counts [RADIX][nb] (in place: output starts), then the scan's scratch
+        auto* base = static_cast<uint32_t*>(scratch);
+        uint32_t* total = base;  // the scan's total (unused)
+        uint32_t* cnt = base + 64;
+        void* sscr = cnt + round_up((int64_t)nb * RADIX, 64);
+        const int64_t nc = (int64_t)nb * RADIX;
+        for (int ps = 0; ps < passes; ++ps) {
+            const bool to_out = ((passes - 1 - ps) & 1) == 0;
+            K* ko = to_out ? kout : kalt;
+            int32_t* vo = to_out ? vout : valt;
+            const int shift = shift0 + 8 * ps;
+            if (ps == 0) {
+                hipLaunchKernelGGL((radix_up_kernel<K, HV, Src>), dim3(nb), dim3(RB), 0, s, src, n, shift,
+                                   (int64_t)nb, cnt);
+                TFMM_LAUNCHED();
+                exclusive_scan_u32(cnt, cnt, nc, sscr, total, err, s);
+                hipLaunchKernelGGL((radix_down_kernel<K, HV, Src>), dim3(nb), dim3(RB), 0, s, src, ko, vo, n, shift,
+                                   (int64_t)nb, (const uint32_t*)cnt);
+                TFMM_LAUNCHED();
+            } else if constexpr (HV) {
+                const ArraySrc<K> prev{to_out ? kalt : kout, to_out ? valt : vout};
+                hipLaunchKernelGGL((radix_up_kernel<K, HV, ArraySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, n, shift,
+                                   (int64_t)nb, cnt);
+                TFMM_LAUNCHED();
+                exclusive_scan_u32(cnt, cnt, nc, sscr, total, err, s);
+                hipLaunchKernelGGL((radix_down_kernel<K, HV, ArraySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, ko, vo, n,
+                                   shift, (int64_t)nb, (const uint32_t*)cnt);
+                TFMM_LAUNCHED();
+            } else {
+                const KeySrc<K> prev{to_out ? kalt : kout};
+                hipLaunchKernelGGL((radix_up_kernel<K, HV, KeySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, n, shift,
+                                   (int64_t)nb, cnt);
+                TFMM_LAUNCHED();
+                exclusive_scan_u32(cnt, cnt, nc, sscr, total, err, s);
+                hipLaunchKernelGGL((radix_down_kernel<K, HV, KeySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, ko, vo, n,
+                                   shift, (int64_t)nb, (const uint32_t*)cnt);
+                TFMM_LAUNCHED();
+            }
+        }
+        return;
+    }
     const SortScratch sc = carve(scratch, n, passes, RTILE);
     const unsigned zb = (unsigned)std::min<int64_t>(2048, cdiv(sc.zero_words, RB));
     hipLaunchKernelGGL(zero_u64_kernel, dim3(zb), dim3(RB), 0, s, static_cast<unsigned long long*>(scratch),
@@ -408,7 +585,10 @@ void radix_sort_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int
 size_t sort_scratch_bytes(int64_t n, int bits) {
     const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
     const int rtile = std::min({tile_keys<uint32_t, true>(), tile_keys<uint32_t, false>(), tile_keys<uint64_t, true>()});
-    return (size_t)carve(nullptr, n, passes, rtile).zero_words * 8 + 256;
+    const size_t onesweep = (size_t)carve(nullptr, n, passes, rtile).zero_words * 8 + 256;
+    const int64_t nc = cdiv(n > 0 ? n : 1, rtile) * RADIX;
+    const size_t rts = (size_t)(64 + round_up(nc, 64)) * 4 + scan_scratch_bytes(nc) + 256;
+    return std::max(onesweep, rts);
 }
 
 void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,

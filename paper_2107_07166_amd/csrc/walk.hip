@@ -590,13 +590,6 @@ __global__ __launch_bounds__(TB) void near_work_kernel(const uint32_t* __restric
 // prefix is taken modulo 2^32; only differences inside one list are used.)
 constexpr uint32_t kItemSources = 4096;
 
-__global__ __launch_bounds__(TB) void entry_sources_kernel(const int32_t* __restrict__ src, int64_t ne,
-                                                           const int32_t* __restrict__ count,
-                                                           uint32_t* __restrict__ c) {
-    const int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (q < ne) c[q] = (uint32_t)count[src[q]];
-}
-
 // Items of a node's near list: entry q (list start q0) belongs to item
 // k = floor((P[q] - P[q0]) / kItemSources) of its leaf.  A source leaf holds
 // at most 4096 particles, so k grows by at most one per entry and a list
@@ -940,14 +933,12 @@ void walk_lists_begin(Tree& t, double theta, hipStream_t s) {
         build_csr_pairs(t, t.p2p_pairs, n_near, true, tg, sr, t.p2p_off, t.p2p_src, t.scratch_b, t.scratch2_b,
                         &res->near_entries, s);
         // work items over the sorted near entries (tg holds the sorted targets)
-        t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 8);
-        uint32_t* ec = t.w_c.as<uint32_t>();
-        uint32_t* P = ec + std::max<int64_t>(ne, 1);
+        t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
+        uint32_t* P = t.w_c.as<uint32_t>();
         t.scratch_b.ensure(ctx, scan_scratch_bytes(ne) + 256);
-        hipLaunchKernelGGL(entry_sources_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const int32_t*)t.p2p_src.as<int32_t>(),
-                           ne, t.nd_count.as<int32_t>(), ec);
-        TFMM_LAUNCHED();
-        exclusive_scan_u32(ec, P, ne, t.scratch_b.p, junk, ctx->dev_err, s);
+        // P[q] = source particles before entry q (gathered from the source leaf counts)
+        exclusive_scan_gather_u32(t.p2p_src.as<int32_t>(), t.nd_count.as<int32_t>(), P, ne, t.scratch_b.p, junk,
+                                  ctx->dev_err, s);
         // per node: items and partial rows, then their offsets
         t.w_fl.ensure(ctx, (size_t)(nn + 1) * 16);
         uint32_t* nit = t.w_fl.as<uint32_t>();
