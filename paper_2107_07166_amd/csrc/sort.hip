@@ -336,7 +336,10 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
 // again and scatters them (radix_down_kernel).  The tile layout and ranking
 // are those of the single-kernel pass, so the order is the same (stable).
 
-template <typename K, bool HV, typename Src>
+// ATOM: count with LDS adds (for digits that vary across neighbouring keys);
+// otherwise one add per distinct digit of a row, found with ballots (for
+// digits that repeat, where per-lane adds would serialise).
+template <typename K, bool HV, bool ATOM, typename Src>
 __global__ __launch_bounds__(RB) void radix_up_kernel(Src src, int64_t n, int shift, int64_t ntiles,
                                                       uint32_t* __restrict__ cnt) {
     constexpr int RI = keys_per_lane<K, HV>();
@@ -356,13 +359,30 @@ __global__ __launch_bounds__(RB) void radix_up_kernel(Src src, int64_t n, int sh
         k[r] = (K)0;
         if (i < n) src.load(i, k[r], unused);
     }
-    const uint64_t lt = lanemask_lt();
+    if constexpr (ATOM) {
+        // counts only: order does not matter (a row whose lanes all share one
+        // digit adds once)
 #pragma unroll
-    for (int r = 0; r < RI; ++r) {
-        const bool valid = wbase + (int64_t)r * kWave + lane < n;
-        const uint32_t d = (uint32_t)((k[r] >> shift) & (RADIX - 1));
-        const uint64_t peers = digit_peers(d) & __ballot(valid);
-        if (valid && (peers & lt) == 0ull) wcnt[w][d] += (uint32_t)__popcll(peers);
+        for (int r = 0; r < RI; ++r) {
+            const bool valid = wbase + (int64_t)r * kWave + lane < n;
+            const uint32_t d = (uint32_t)((k[r] >> shift) & (RADIX - 1));
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+            const uint64_t vm = __ballot(valid);
+            if (__ballot(valid && d != d0) == 0ull) {
+                if (lane == 0 && vm) wcnt[w][d0] += (uint32_t)__popcll(vm);
+            } else if (valid) {
+                atomicAdd(&wcnt[w][d], 1u);
+            }
+        }
+    } else {
+        const uint64_t lt = lanemask_lt();
+#pragma unroll
+        for (int r = 0; r < RI; ++r) {
+            const bool valid = wbase + (int64_t)r * kWave + lane < n;
+            const uint32_t d = (uint32_t)((k[r] >> shift) & (RADIX - 1));
+            const uint64_t peers = digit_peers(d) & __ballot(valid);
+            if (valid && (peers & lt) == 0ull) wcnt[w][d] += (uint32_t)__popcll(peers);
+        }
     }
     __syncthreads();
     uint32_t tot = 0;
@@ -500,7 +520,7 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
             int32_t* vo = to_out ? vout : valt;
             const int shift = shift0 + 8 * ps;
             if (ps == 0) {
-                hipLaunchKernelGGL((radix_up_kernel<K, HV, Src>), dim3(nb), dim3(RB), 0, s, src, n, shift,
+                hipLaunchKernelGGL((radix_up_kernel<K, HV, true, Src>), dim3(nb), dim3(RB), 0, s, src, n, shift,
                                    (int64_t)nb, cnt);
                 TFMM_LAUNCHED();
                 exclusive_scan_u32(cnt, cnt, nc, sscr, total, err, s);
@@ -509,7 +529,7 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
                 TFMM_LAUNCHED();
             } else if constexpr (HV) {
                 const ArraySrc<K> prev{to_out ? kalt : kout, to_out ? valt : vout};
-                hipLaunchKernelGGL((radix_up_kernel<K, HV, ArraySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, n, shift,
+                hipLaunchKernelGGL((radix_up_kernel<K, HV, false, ArraySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, n, shift,
                                    (int64_t)nb, cnt);
                 TFMM_LAUNCHED();
                 exclusive_scan_u32(cnt, cnt, nc, sscr, total, err, s);
@@ -518,7 +538,7 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
                 TFMM_LAUNCHED();
             } else {
                 const KeySrc<K> prev{to_out ? kalt : kout};
-                hipLaunchKernelGGL((radix_up_kernel<K, HV, KeySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, n, shift,
+                hipLaunchKernelGGL((radix_up_kernel<K, HV, false, KeySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, n, shift,
                                    (int64_t)nb, cnt);
                 TFMM_LAUNCHED();
                 exclusive_scan_u32(cnt, cnt, nc, sscr, total, err, s);

@@ -540,19 +540,38 @@ __global__ __launch_bounds__(TB) void walk_pass_kernel(WalkNodes w, const int2* 
 }
 
 // CSR offsets from targets sorted ascending (target = keys[i] >> shift):
-// off[t] = first entry with target >= t, for t = 0..nn, one thread per entry
-// boundary (each t written by exactly one thread, which also copies off[nn],
-// the number of entries below nn, to *below_nn if given).  Targets may equal
-// nn (entries sorted after every real one).
+// off[t] = first entry with target >= t, for t = 0..nn.  Entry boundary i
+// (0..ne) writes off[t] for targets t in (target[i-1], target[i]], so each t
+// is written by exactly one boundary, which also copies off[nn] (the number
+// of entries below nn) to *below_nn if given.  Targets may equal nn (entries
+// sorted after every real one).  A thread takes four boundaries and reads
+// their keys with one 16-byte load.
 __global__ __launch_bounds__(TB) void csr_offsets_kernel(const uint32_t* __restrict__ keys, int64_t ne,
                                                          int64_t nn, int shift, uint32_t* __restrict__ off,
                                                          uint32_t* __restrict__ below_nn) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i > ne) return;
-    const int64_t lo = (i == 0) ? 0 : (int64_t)(keys[i - 1] >> shift) + 1;
-    const int64_t hi = (i == ne) ? nn : std::min<int64_t>((int64_t)(keys[i] >> shift), nn);
-    for (int64_t t = lo; t <= hi; ++t) off[t] = (uint32_t)i;
-    if (below_nn && lo <= nn && nn <= hi) *below_nn = (uint32_t)i;
+    const int64_t i0 = ((int64_t)blockIdx.x * TB + threadIdx.x) * 4;
+    if (i0 > ne) return;
+    int64_t kv[5];  // targets of entries i0 - 1 .. i0 + 3 (-1 before the first, nn after the last)
+    kv[0] = i0 == 0 ? -1 : (int64_t)(keys[i0 - 1] >> shift);
+    if (i0 + 4 <= ne) {
+        const uint4 q = *reinterpret_cast<const uint4*>(keys + i0);
+        kv[1] = q.x >> shift;
+        kv[2] = q.y >> shift;
+        kv[3] = q.z >> shift;
+        kv[4] = q.w >> shift;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) kv[j + 1] = i0 + j < ne ? (int64_t)(keys[i0 + j] >> shift) : nn;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = i0 + j;
+        if (i > ne) break;
+        const int64_t lo = kv[j] + 1;
+        const int64_t hi = kv[j + 1] < nn ? kv[j + 1] : nn;
+        for (int64_t t = lo; t <= hi; ++t) off[t] = (uint32_t)i;
+        if (below_nn && lo <= nn && nn <= hi) *below_nn = (uint32_t)i;
+    }
 }
 
 __global__ __launch_bounds__(TB) void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
@@ -677,7 +696,7 @@ void build_csr_pairs(Tree& t, const DevBuf& pairs, int64_t np, bool self_dummy, 
     radix_sort_pairs(pairs.as<int2>(), np, self_dummy, (uint32_t)nn, tgtbuf.as<uint32_t>(), srcbuf.as<int32_t>(),
                      kalt, valt, bits, scr.p, ctx->dev_err, s);
     off.ensure(ctx, (size_t)(nn + 1) * 4);
-    hipLaunchKernelGGL(csr_offsets_kernel, dim3(grid(ne + 1)), dim3(TB), 0, s,
+    hipLaunchKernelGGL(csr_offsets_kernel, dim3(grid(cdiv(ne + 1, 4))), dim3(TB), 0, s,
                        (const uint32_t*)tgtbuf.as<uint32_t>(), ne, nn, 0, off.as<uint32_t>(), real_out);
     TFMM_LAUNCHED();
     std::swap(srcbuf.p, srcout.p);
@@ -700,8 +719,8 @@ void build_far_csr_packed(Tree& t, int64_t np, hipStream_t s) {
     radix_sort_pairs_packed16(t.m2l_pairs.as<int2>(), np, t.w_tg.as<uint32_t>(), t.scratch2.as<uint32_t>(), bits,
                               t.scratch.p, ctx->dev_err, s);
     t.m2l_off.ensure(ctx, (size_t)(nn + 1) * 4);
-    hipLaunchKernelGGL(csr_offsets_kernel, dim3(grid(ne + 1)), dim3(TB), 0, s, (const uint32_t*)t.w_tg.as<uint32_t>(),
-                       ne, nn, 16, t.m2l_off.as<uint32_t>(), nullptr);
+    hipLaunchKernelGGL(csr_offsets_kernel, dim3(grid(cdiv(ne + 1, 4))), dim3(TB), 0, s,
+                       (const uint32_t*)t.w_tg.as<uint32_t>(), ne, nn, 16, t.m2l_off.as<uint32_t>(), nullptr);
     TFMM_LAUNCHED();
     std::swap(t.w_tg.p, t.m2l_src.p);
     std::swap(t.w_tg.cap, t.m2l_src.cap);
