@@ -33,7 +33,8 @@ _LIB_PATH = _HERE / "liboracle.so"
 
 STANDARD = 0
 CONSERVING = 1
-VARIANTS = {"standard": STANDARD, "conserving": CONSERVING}
+CONSERVING_R2 = 2  # zeroth order, realigned by magnitude (Eq. realign2); p must be 1
+VARIANTS = {"standard": STANDARD, "conserving": CONSERVING, "conserving_r2": CONSERVING_R2}
 
 _lib = None
 

@@ -26,6 +26,15 @@
  *               degree p-1, the force's own degree; this is exactly
  *             = -m_b T_{p-1}[g](R; delta) (R + delta)
  *               which is central and antisymmetric, so pair torques vanish.
+ *   conserving_r2 (zeroth order only, p = 1): the magnitude of the zeroth-
+ *               order acceleration along n_ab (Eq. realign2), with n_ab
+ *               expanded to first order in delta / |R| as in Eq.
+ *               nab-expansion (the sum over b gives Eq. aaB0):
+ *             = -m_b |grad phi(R)| (1 - n_R . delta / |R|)(n_R + delta / |R|)
+ *             = -m_b (R.R + eps^2)^(-3/2) (1 - R . delta / |R|^2) (R + delta)
+ *               with |grad phi(R)| = |R| (R.R + eps^2)^(-3/2), the softened
+ *               zeroth-order magnitude (the paper writes the unsoftened
+ *               1 / |R|^2); also central and antisymmetric.
  * T_k[f](R; delta) is the Taylor polynomial of total degree k of f about R,
  * evaluated at R + delta.  Its degree-n part is the coefficient of t^n in
  * f(R + t delta) = (c0 + c1 t + c2 t^2)^alpha with c0 = R.R + eps^2,
@@ -75,7 +84,7 @@
 #define ORC_LEVELS 21
 #define ORC_QMAX ((1u << ORC_LEVELS) - 1u)
 
-enum { ORC_STANDARD = 0, ORC_CONSERVING = 1 };
+enum { ORC_STANDARD = 0, ORC_CONSERVING = 1, ORC_CONSERVING_R2 = 2 };
 
 /* ------------------------------------------------------------------------ */
 /* Neumaier-compensated summation                                            */
@@ -164,7 +173,13 @@ static void pair_far(const double R[3], const double d[3], double mb, int p,
         if (n <= p - 2) t_lo += gam[n];
         t_hi += gam[n];
     }
-    if (variant == ORC_CONSERVING) {
+    if (variant == ORC_CONSERVING_R2) {
+        /* scalar (R.R + eps^2)^(-3/2) (1 - R.delta / |R|^2) along R + delta */
+        double rr = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
+        double rd = (R[0] * d[0] + R[1] * d[1]) + R[2] * d[2];
+        double sc = gam[0] * (1.0 - rd / rr);
+        for (int k = 0; k < 3; ++k) acc[k] = -mb * ((R[k] + d[k]) * sc);
+    } else if (variant == ORC_CONSERVING) {
         for (int k = 0; k < 3; ++k) acc[k] = -mb * ((R[k] + d[k]) * t_hi);
     } else {
         for (int k = 0; k < 3; ++k) acc[k] = -mb * (R[k] * t_hi + d[k] * t_lo);
@@ -600,7 +615,8 @@ int orc_fmm_forces(orc_tree *t, int p, double eps, double G, int variant,
                    int64_t n_targets, const int64_t *targets, double *force, double *pot)
 {
     if (!t || p < 1 || p > ORC_PMAX || !(eps >= 0.0) || !force) return -1;
-    if (variant != ORC_STANDARD && variant != ORC_CONSERVING) return -1;
+    if (variant != ORC_STANDARD && variant != ORC_CONSERVING && variant != ORC_CONSERVING_R2) return -1;
+    if (variant == ORC_CONSERVING_R2 && p != 1) return -1;
     if (build_adjacency(t)) return -2;
     int64_t nt = targets ? n_targets : t->n;
     int64_t *pos_of = (int64_t *)malloc((size_t)t->n * sizeof(int64_t));
