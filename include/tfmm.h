@@ -12,14 +12,21 @@
  * truncated at total degree p about the two centres of mass; all other pairs
  * of leaves interact exactly (Eq. jia).  Both directions of every pair use
  * the same expression (mutual interactions), so linear momentum is conserved
- * (Eq. netforce).  Two variants:
+ * (Eq. netforce).  Three variants:
  *   TFMM_STANDARD   -- the symmetric expansion itself (leaves the spurious
  *                      torques of Eq. total_torque);
  *   TFMM_CONSERVING -- each far-field pair force re-projected onto the line
  *                      joining the two particles (Eq. realign), with the
  *                      projection scalar expanded in (x_a - y_b) to degree
  *                      p-1 (Eqs. nab-expansion, abnab-expansion; equal to
- *                      Eq. aaB1 at p = 2): no spurious torque.
+ *                      Eq. aaB1 at p = 2): no spurious torque;
+ *   TFMM_CONSERVING_R2 -- zeroth order only (p must be 1): each far-field pair
+ *                      force is the zeroth-order magnitude along the line
+ *                      joining the particles (Eq. realign2), that line
+ *                      expanded to first order in (x_a - y_b)/|R|
+ *                      (Eq. nab-expansion); summed over a node this is
+ *                      Eq. aaB0, which needs the node quadrupoles.  With
+ *                      softening the magnitude is |R| (R^2 + eps^2)^(-3/2).
  * Softening: the kernel is -(r^2 + eps^2)^(-1/2) in the near and far field.
  *
  * Conventions for every entry point:
@@ -52,7 +59,7 @@ typedef enum {
     TFMM_ESTATE = -4   /* object used out of order (e.g. lists before a walk) */
 } tfmm_status;
 
-typedef enum { TFMM_STANDARD = 0, TFMM_CONSERVING = 1 } tfmm_variant;
+typedef enum { TFMM_STANDARD = 0, TFMM_CONSERVING = 1, TFMM_CONSERVING_R2 = 2 } tfmm_variant;
 
 /* TFMM_FP64: every step in FP64.  TFMM_MIXED32: near field (P2P) and M2L in
  * FP32 with FP64 accumulation across source leaves / per node; tree, centres
@@ -118,7 +125,8 @@ int tfmm_tree_walk(tfmm_tree *tree, double theta, void *stream);
  * and joined back into it before the forces are written, so the call is
  * ordered on `stream` like a single kernel.
  * Errors: EINVAL (p outside 1..8, theta outside [0,1), eps < 0, bad variant
- * or precision, NULL force), ENOMEM, EDEVICE. */
+ * or precision, TFMM_CONSERVING_R2 with p != 1, NULL force), ENOMEM,
+ * EDEVICE. */
 int tfmm_evaluate_forces(tfmm_tree *tree, const tfmm_params *params, double *force,
                          double *potential, void *stream);
 

@@ -13,7 +13,7 @@ from pathlib import Path
 LIB_PATH = Path(__file__).resolve().parent / "libtfmm.so"
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
-STANDARD, CONSERVING = 0, 1
+STANDARD, CONSERVING, CONSERVING_R2 = 0, 1, 2
 FP64, MIXED32 = 0, 1
 
 STATUS_NAMES = {OK: "TFMM_OK", EINVAL: "TFMM_EINVAL", ENOMEM: "TFMM_ENOMEM",

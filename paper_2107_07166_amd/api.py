@@ -23,7 +23,7 @@ import torch
 from . import _lib
 from ._lib import Params, TfmmError
 
-VARIANTS = {"standard": _lib.STANDARD, "conserving": _lib.CONSERVING}
+VARIANTS = {"standard": _lib.STANDARD, "conserving": _lib.CONSERVING, "conserving_r2": _lib.CONSERVING_R2}
 PRECISIONS = {"fp64": _lib.FP64, "mixed32": _lib.MIXED32}
 
 

@@ -97,7 +97,10 @@ void check_params(const tfmm_params* p) {
     if (!(p->theta >= 0.0) || !(p->theta < 1.0)) fail(TFMM_EINVAL, "theta must satisfy 0 <= theta < 1");
     if (!(p->softening >= 0.0) || !std::isfinite(p->softening)) fail(TFMM_EINVAL, "softening must be >= 0");
     if (!std::isfinite(p->G)) fail(TFMM_EINVAL, "G must be finite");
-    if (p->variant != TFMM_STANDARD && p->variant != TFMM_CONSERVING) fail(TFMM_EINVAL, "unknown variant");
+    if (p->variant != TFMM_STANDARD && p->variant != TFMM_CONSERVING && p->variant != TFMM_CONSERVING_R2)
+        fail(TFMM_EINVAL, "unknown variant");
+    if (p->variant == TFMM_CONSERVING_R2 && p->p != 1)
+        fail(TFMM_EINVAL, "the conserving_r2 variant is zeroth order: p must be 1");
     if (p->precision != TFMM_FP64 && p->precision != TFMM_MIXED32) fail(TFMM_EINVAL, "unknown precision");
 }
 
@@ -108,6 +111,12 @@ void check_params(const tfmm_params* p) {
 // alone on the device.
 void evaluate(Tree& t, const tfmm_params* prm, double* force, hipStream_t s) {
     const bool need_walk = !t.walk_valid || t.walk_theta != prm->theta;
+    // The zeroth-order magnitude realignment (Eq. aaB0) is quadratic in the
+    // target offset and needs the node quadrupoles: it runs through the
+    // conserving locals (P, Q') of order 2, with its own M2L.
+    const bool r2 = prm->variant == TFMM_CONSERVING_R2;
+    const int pe = r2 ? 2 : prm->p;
+    const int ve = r2 ? TFMM_CONSERVING : prm->variant;
     const double eps2 = prm->softening * prm->softening;
     if (t.timing && !t.ev_ready) {
         for (auto& e : t.ev) TFMM_HIP(hipEventCreate(&e));
@@ -116,7 +125,7 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, hipStream_t s) {
     aux_fork(t, s);
     const hipStream_t a = t.aux;
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[0], a));
-    compute_moments(t, prm->p, a);
+    compute_moments(t, pe, a);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[1], a));
     prepare_sources(t, prm->precision, s);
     if (need_walk) {
@@ -124,16 +133,16 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, hipStream_t s) {
         walk_lists_begin(t, prm->theta, s);
     }
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[7], a));
-    run_m2l(t, prm->p, prm->variant, prm->precision, eps2, a);
+    run_m2l(t, pe, prm->variant, prm->precision, eps2, a);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[2], a));
-    run_l2l(t, prm->p, prm->variant, a);
+    run_l2l(t, pe, ve, a);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[3], a));
     if (need_walk) walk_lists_end(t, s);
     aux_join(t, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[6], s));
     run_p2p(t, prm->precision, eps2, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[4], s));
-    run_l2p(t, prm->p, prm->variant, prm->G, force, s);
+    run_l2p(t, pe, ve, prm->G, force, s);
     if (t.timing) {
         TFMM_HIP(hipEventRecord(t.ev[5], s));
         t.have_times = true;

@@ -222,7 +222,7 @@ void run_drift(int64_t n, double* pos, const double* vel, double dt, hipStream_t
 
 // number of FP64 local values per node for a variant
 inline int n_local(int p, int variant) {
-    return variant == TFMM_CONSERVING ? 4 * c_le(p - 1) : c_le(p);
+    return variant != TFMM_STANDARD ? 4 * c_le(p - 1) : c_le(p);
 }
 
 }  // namespace tfmm

@@ -7,6 +7,10 @@
 //   standard  : L_j(A) += sum_i D_{i+j}(R) W_i(B)    (Taylor series of Eq. taylor)
 //   conserving: P_j(A) += sum_i G_{i+j}(R) W_i(B), Q'_ej(A) += Q_ej - R_e P_j
 //               (realigned force, Eq. realign, scalar kept to degree p-1).
+//   conserving_r2 (order 2 locals only): the same contraction with G replaced
+//               by the scalar of Eq. realign2 / nab-expansion, (R.R + eps^2)
+//               ^(-3/2) (1 - R.delta / |R|^2): G_0 = (R.R+eps^2)^(-3/2),
+//               G_e = -G_0 R_e / |R|^2 (Eq. aaB0 after the sum over B).
 // Each half wavefront (32 lanes) owns one target node: its lanes stride over
 // the target's source list, each lane accumulating a private local expansion,
 // and a DPP reduction across the half wave produces the node's locals (written
@@ -64,7 +68,9 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
     constexpr int NC = E::NC;
     constexpr int NC1 = E::NC1;
     constexpr int NCP = (NC + 3) / 4 * 4;
-    constexpr int NOUT = (VAR == TFMM_CONSERVING) ? 4 * NC1 : NC;
+    constexpr bool CONS = VAR != TFMM_STANDARD;
+    static_assert(VAR != TFMM_CONSERVING_R2 || P == 2, "the r2 locals are of order 2");
+    constexpr int NOUT = CONS ? 4 * NC1 : NC;
     // wave index through readfirstlane: the compiler then keeps the target's
     // list bounds in scalar registers
     const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (MB / kWave) + threadIdx.x / kWave));
@@ -100,7 +106,16 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
             w[4 * k + 2] = v.z;
             w[4 * k + 3] = v.w;
         }
-        if constexpr (VAR == TFMM_CONSERVING) {
+        if constexpr (VAR == TFMM_CONSERVING_R2) {
+            T G[NC1];
+            const T rr = Rx * Rx + Ry * Ry + Rz * Rz;
+            const T c = -F[1] / rr;
+            G[0] = F[1];
+            G[1] = Rx * c;
+            G[2] = Ry * c;
+            G[3] = Rz * c;
+            E::m2l_cons(G, w, Rx, Ry, Rz, acc, acc + NC1);
+        } else if constexpr (VAR == TFMM_CONSERVING) {
             T G[NC1];
             E::g_derivs(Rx, Ry, Rz, F, G);
             E::m2l_cons(G, w, Rx, Ry, Rz, acc, acc + NC1);
@@ -224,7 +239,14 @@ void launch(Tree& t, double eps2, hipStream_t s) {
 
 template <int P>
 void dispatch_var(Tree& t, int variant, int precision, double eps2, hipStream_t s) {
-    if (variant == TFMM_CONSERVING) {
+    if (variant == TFMM_CONSERVING_R2) {
+        if constexpr (P == 2) {
+            if (precision == TFMM_MIXED32) launch<P, TFMM_CONSERVING_R2, float>(t, eps2, s);
+            else launch<P, TFMM_CONSERVING_R2, double>(t, eps2, s);
+        } else {
+            fail(TFMM_EINVAL, "conserving_r2 locals are of order 2");
+        }
+    } else if (variant == TFMM_CONSERVING) {
         if (precision == TFMM_MIXED32) launch<P, TFMM_CONSERVING, float>(t, eps2, s);
         else launch<P, TFMM_CONSERVING, double>(t, eps2, s);
     } else {

@@ -151,6 +151,45 @@ def exponential_disk(n: int, seed: int, r_scale: float = 1.0, z_scale: float = 0
     return np.ascontiguousarray(pos), mass, np.ascontiguousarray(vel)
 
 
+def _irregular_shape(rng: np.random.Generator, n: int) -> np.ndarray:
+    """One irregular body: a union of 3-5 random ellipsoids (uniform density,
+    rejection sampled), recentred on its centroid and scaled to unit maximum
+    radius."""
+    k = int(rng.integers(3, 6))
+    centres = rng.normal(size=(k, 3)) * 0.45
+    axes = rng.uniform(0.25, 0.7, size=(k, 3))
+    rots = []
+    for _ in range(k):
+        q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+        rots.append(q * np.sign(np.diag(r)))
+    lo = (centres - axes.max(1, keepdims=True)).min(0)
+    hi = (centres + axes.max(1, keepdims=True)).max(0)
+    out = np.empty((0, 3))
+    while len(out) < n:
+        cand = lo + (hi - lo) * rng.random((4 * n, 3))
+        inside = np.zeros(len(cand), dtype=bool)
+        for c, a, q in zip(centres, axes, rots):
+            u = (cand - c) @ q / a
+            inside |= (u * u).sum(1) <= 1.0
+        out = np.concatenate([out, cand[inside]])
+    out = out[:n]
+    out -= out.mean(0)
+    return out / np.sqrt((out * out).sum(1)).max()
+
+
+def irregular_pair(n_each: int, seed: int, separation: float):
+    """Two irregular bodies of n_each particles (equal masses, total 1), unit
+    maximum radius about their centres, with centres at -/+ (separation /
+    (2 sqrt 3)) (1, 1, 1): distance `separation` along the cube diagonal, so
+    for separation > 2 sqrt 3 each body sits in its own octant of the
+    bounding cube."""
+    rng = _rng(seed)
+    c = separation / (2.0 * math.sqrt(3.0))
+    a = _irregular_shape(rng, n_each) - c
+    b = _irregular_shape(rng, n_each) + c
+    return np.ascontiguousarray(np.concatenate([a, b])), np.full(2 * n_each, 0.5 / n_each)
+
+
 @dataclass(frozen=True)
 class Workload:
     """One named solve configuration: input recipe plus FMM parameters."""

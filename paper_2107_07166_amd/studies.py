@@ -20,6 +20,14 @@
         rebuild + walk + evaluate steps with per-phase event times.
     python -m paper_2107_07166_amd.studies copy
         Counter calibration: three device copies of a 256 MiB buffer.
+    python -m paper_2107_07166_amd.studies shapes [--n 4000]
+        Two irregular bodies of n particles each at distances 3.6-16 (units of
+        their radius), each body one leaf, theta = 0.99: error of the inter-body
+        force for orders 0 and 1 with and without realignment (both
+        realignments at order 0), net force and torque (FP64, eps = 0).
+    python -m paper_2107_07166_amd.studies zeroth [--n-leaf 64] [--reps 5]
+        The benchmark workload at orders 0 and 1 with and without
+        realignment: time per evaluation, net torque, error against p = 4.
 """
 
 from __future__ import annotations
@@ -152,6 +160,80 @@ def study_profile(steps: int, n_leaf: int, workload: str = "plummer1m", variant:
     return out
 
 
+SHAPE_CASES = (("order0", 1, "standard"), ("order0_realigned_r2", 1, "conserving_r2"),
+               ("order0_projected", 1, "conserving"), ("order1", 2, "standard"),
+               ("order1_realigned", 2, "conserving"))
+
+
+def _rel_rms(err, ref):
+    return float(np.sqrt(np.mean((err * err).sum(1) / (ref * ref).sum(1))))
+
+
+def study_shapes(n_each: int, seps, seed: int) -> dict:
+    """Two irregular bodies at a varying distance (in units of their radius),
+    each body one leaf (n_leaf = n_each) and theta = 0.99, so the only far
+    interaction is the one body-body node pair, FP64, eps = 0.  Error of the
+    inter-body force per particle (relative to the exact inter-body force,
+    rms over both bodies) for orders 0 and 1 with and without realignment,
+    plus the net force and torque of the whole evaluation."""
+    ctx = api.Context(0)
+    rows = []
+    for sep in seps:
+        pos, mass = generators.irregular_pair(n_each, seed, sep)
+        t = api.Tree(ctx, _dev(pos), _dev(mass), n_leaf=n_each)
+        exact = t.evaluate(p=1, theta=0.0, eps=0.0, variant="standard", precision="fp64").cpu().numpy()
+        alone = []
+        for half in (slice(0, n_each), slice(n_each, 2 * n_each)):
+            ta = api.Tree(ctx, _dev(pos[half]), _dev(mass[half]), n_leaf=n_each)
+            alone.append(ta.evaluate(p=1, theta=0.0, eps=0.0, variant="standard", precision="fp64").cpu().numpy())
+            ta.close()
+        inter = exact - np.concatenate(alone)
+        row = {"separation": sep}
+        for label, p, variant in SHAPE_CASES:
+            ft = t.evaluate(p=p, theta=0.99, eps=0.0, variant=variant, precision="fp64")
+            d = ctx.diagnostics(_dev(pos), _dev(mass), ft)
+            f = ft.cpu().numpy()
+            row[label] = {"err": _rel_rms(f - exact, inter), "net_force_rel": float(d[18]),
+                          "net_torque_rel": float(d[19])}
+        info = t.info()
+        row["far_pairs"] = info["far_pairs"]
+        row["leaves"] = info["leaves"]
+        rows.append(row)
+        t.close()
+    ctx.close()
+    return {"study": "shapes", "n_each": n_each, "seed": seed, "theta": 0.99, "rows": rows}
+
+
+def study_zeroth(n_leaf: int, reps: int) -> dict:
+    """The benchmark workload (Plummer N = 2^20, theta = 0.5, mixed) at orders
+    0 and 1 with and without realignment: time per evaluation (tree and walk
+    kept), net torque, and the rms error against the p = 4 conserving FP64
+    evaluation of the same tree."""
+    w = generators.WORKLOADS["plummer1m"]
+    pos, mass = w.make()
+    ctx = api.Context(0)
+    pd, md = _dev(pos), _dev(mass)
+    t = api.Tree(ctx, pd, md, n_leaf=n_leaf)
+    ref = t.evaluate(p=4, theta=w.theta, eps=w.eps, variant="conserving", precision="fp64").cpu().numpy()
+    out = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
+    rows = {}
+    for label, p, variant in SHAPE_CASES:
+        t.evaluate(p=p, theta=w.theta, eps=w.eps, variant=variant, precision="mixed32", out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            t.evaluate(p=p, theta=w.theta, eps=w.eps, variant=variant, precision="mixed32", out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        d = ctx.diagnostics(pd, md, out)
+        rows[label] = {"p": p, "variant": variant, "ms_per_eval": ms,
+                       "err_vs_p4_fp64": _rel_rms(out.cpu().numpy() - ref, ref),
+                       "net_torque_rel": float(d[19])}
+    t.close()
+    ctx.close()
+    return {"study": "zeroth", "workload": w.name, "n_leaf": n_leaf, "theta": w.theta, "rows": rows}
+
+
 def study_copy() -> dict:
     x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     y = torch.empty_like(x)
@@ -165,7 +247,7 @@ def study_copy() -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["binary", "disk", "serve", "profile", "copy"])
+    ap.add_argument("study", choices=["binary", "disk", "serve", "profile", "copy", "shapes", "zeroth"])
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--dt", type=float, default=1e-3)
@@ -187,6 +269,10 @@ def main():
         r = study_profile(a.steps, a.n_leaf, a.workload, a.variant)
     elif a.study == "copy":
         r = study_copy()
+    elif a.study == "shapes":
+        r = study_shapes(a.n or 4000, (3.6, 4.0, 5.0, 6.0, 8.0, 12.0, 16.0), 210707170)
+    elif a.study == "zeroth":
+        r = study_zeroth(a.n_leaf, a.reps)
     else:
         r = study_serve(a.requests, a.sessions, a.rate, a.slots, a.budget_gb)
     print(json.dumps(r), flush=True)

@@ -181,6 +181,42 @@ def test_forces_mixed(ctx, name, n_leaf, theta, p, eps, variant):
         assert d[19] <= TORQUE_MIXED
 
 
+R2_CASES = [
+    ("ball2k", 16, 0.5, 1e-3), ("ball2k", 64, 0.7, 0.0), ("ball2k", 8, 0.3, 0.05),
+    ("plummer20k", 16, 0.5, 1e-3), ("coplanar_dups", 16, 0.6, 1e-2),
+]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("mixed32", TOL_MIXED)])
+@pytest.mark.parametrize("name,n_leaf,theta,eps", R2_CASES)
+def test_forces_conserving_r2(ctx, name, n_leaf, theta, eps, prec, tol):
+    """Zeroth-order far field realigned by magnitude (Eq. realign2, summed over
+    a node: Eq. aaB0) against the oracle's particle-by-particle sum; the pair
+    forces are central, so the net torque stays at rounding level."""
+    pos, m = _case(name)
+    ref = _oracle_forces(name, n_leaf, theta, 1, eps, "conserving_r2")
+    gt = _gpu_tree(ctx, pos, m, n_leaf)
+    ft = gt.evaluate(p=1, theta=theta, eps=eps, variant="conserving_r2", precision=prec)
+    d = ctx.diagnostics(_dev(pos), _dev(m), ft)
+    f = ft.cpu().numpy()
+    gt.close()
+    assert _erms(f, ref) <= tol, _erms(f, ref)
+    assert d[19] <= (1e-13 if prec == "fp64" else TORQUE_MIXED), d[19]
+
+
+def test_conserving_r2_is_zeroth_order_only(ctx):
+    from paper_2107_07166_amd import api
+    pos, m = uniform_ball(500, 8)
+    gt = _gpu_tree(ctx, pos, m, 16)
+    from paper_2107_07166_amd import _lib
+    with pytest.raises(api.TfmmError) as e:
+        gt.evaluate(p=2, theta=0.5, eps=1e-3, variant="conserving_r2", precision="fp64")
+    assert e.value.status == _lib.EINVAL and "p must be 1" in str(e.value)
+    f = gt.evaluate(p=1, theta=0.5, eps=1e-3, variant="conserving_r2", precision="fp64").cpu().numpy()
+    gt.close()
+    assert np.isfinite(f).all()
+
+
 def test_direct_limit_theta0(ctx):
     pos, m = uniform_ball(1500, 3)
     ref = oracle.direct(pos, m, 1e-3)
