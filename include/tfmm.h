@@ -119,7 +119,12 @@ int tfmm_tree_walk(tfmm_tree *tree, double theta, void *stream);
 
 /* Forces on every particle: force (device, n x 3 FP64 row-major, original
  * particle order) = G m_a (near + far) for the tree's particles.
- * potential: must be NULL (not provided).  Asynchronous except for the walk
+ * potential: NULL, or device n FP64 (original order) that receives
+ * G phi(X_a): the exact softened near-field potential of the other particles
+ * -sum m_b (r^2 + eps^2)^(-1/2) plus the far field from the standard
+ * expansion of Eq. taylor (potential coefficient L_0 included) truncated at
+ * degree p, for every variant (the realigned variants change the forces,
+ * not this potential).  It costs an extra far-field pass after the forces.  Asynchronous except for the walk
  * when params->theta differs from the tree's last walk.  Part of the work
  * runs on a second stream owned by the tree, forked from `stream` at the call
  * and joined back into it before the forces are written, so the call is

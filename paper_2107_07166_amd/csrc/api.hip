@@ -109,7 +109,7 @@ void check_params(const tfmm_params* p) {
 //   s: sources -> frontier passes -> near-list chain -> [join a] -> P2P -> L2P
 // The latency-bound chains hide behind each other; P2P runs after the join,
 // alone on the device.
-void evaluate(Tree& t, const tfmm_params* prm, double* force, hipStream_t s) {
+void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential, hipStream_t s) {
     const bool need_walk = !t.walk_valid || t.walk_theta != prm->theta;
     // The zeroth-order magnitude realignment (Eq. aaB0) is quadratic in the
     // target offset and needs the node quadrupoles: it runs through the
@@ -140,9 +140,15 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, hipStream_t s) {
     if (need_walk) walk_lists_end(t, s);
     aux_join(t, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[6], s));
-    run_p2p(t, prm->precision, eps2, s);
+    run_p2p(t, prm->precision, eps2, potential != nullptr, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[4], s));
     run_l2p(t, pe, ve, prm->G, force, s);
+    if (potential) {
+        // far-field potential from the standard expansion of order p (every
+        // variant), after the forces on the same stream
+        run_m2l_pot(t, prm->p, pe, prm->precision, eps2, s);
+        run_potential_down(t, prm->p, prm->precision, eps2, prm->G, potential, s);
+    }
     if (t.timing) {
         TFMM_HIP(hipEventRecord(t.ev[5], s));
         t.have_times = true;
@@ -257,9 +263,8 @@ int tfmm_evaluate_forces(tfmm_tree* tree, const tfmm_params* params, double* for
     return guarded(tree->ctx, [&] {
         check_params(params);
         if (!force) fail(TFMM_EINVAL, "force must be a device pointer");
-        if (potential) fail(TFMM_EINVAL, "potential output is not provided; pass NULL");
         set_device(tree->ctx);
-        evaluate(*tree, params, force, (hipStream_t)stream);
+        evaluate(*tree, params, force, potential, (hipStream_t)stream);
     });
 }
 
@@ -291,13 +296,13 @@ int tfmm_leapfrog(tfmm_tree* tree, const tfmm_params* params, double* pos, doubl
         const hipStream_t s = (hipStream_t)stream;
         if (!force_valid) {
             build_tree(t, pos, mass, s);
-            evaluate(t, params, force, s);
+            evaluate(t, params, force, nullptr, s);
         }
         for (int k = 0; k < nsteps; ++k) {
             run_kick(t.n, vel, force, mass, 0.5 * dt, s);
             run_drift(t.n, pos, vel, dt, s);
             build_tree(t, pos, mass, s);
-            evaluate(t, params, force, s);
+            evaluate(t, params, force, nullptr, s);
             run_kick(t.n, vel, force, mass, 0.5 * dt, s);
         }
     });

@@ -68,6 +68,18 @@ struct Ctx {
     void free(void* p, size_t bytes);
 };
 
+// 1/sqrt(x) in FP64: the v_rsq_f64 seed (about 2^-23 relative) refined by
+// two Newton steps.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    return y;
+}
+
 // Per-precision scalar types for the interaction kernels.
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
@@ -132,6 +144,8 @@ struct Tree {
     DevBuf loc;                   // FP64 M2L locals per node (NLOC per node)
     DevBuf loc_leaf;              // FP64 gathered locals per leaf
     DevBuf near3;                 // FP64 near-field acceleration (3 per sorted particle)
+    DevBuf near_pot, partial_pot; // FP64 near-field potential (per sorted particle / per partial row)
+    DevBuf loc_pot, loc_pot_leaf; // FP64 standard locals with L_0 (potential output only)
 
     // scratch
     DevBuf scratch;               // scans and sorts
@@ -212,7 +226,9 @@ int64_t near_interactions(Tree& t);
 void compute_moments(Tree& t, int p, hipStream_t s);
 void prepare_sources(Tree& t, int precision, hipStream_t s);
 void run_m2l(Tree& t, int p, int variant, int precision, double eps2, hipStream_t s);
-void run_p2p(Tree& t, int precision, double eps2, hipStream_t s);
+void run_p2p(Tree& t, int precision, double eps2, bool with_pot, hipStream_t s);
+void run_m2l_pot(Tree& t, int p, int mom_p, int precision, double eps2, hipStream_t s);
+void run_potential_down(Tree& t, int p, int precision, double eps2, double G, double* pot, hipStream_t s);
 void run_l2l(Tree& t, int p, int variant, hipStream_t s);
 void run_l2p(Tree& t, int p, int variant, double G, double* force, hipStream_t s);
 void run_diagnostics(int64_t n, const double* pos, const double* vel, const double* mass,

@@ -290,6 +290,17 @@ def gen_struct(P):
         out.append(f"    a[{e}] = -({expr});")
     out.append("  }")
 
+    # L2P potential (standard locals, L_0 included): phi = sum_{|j| <= P} L_j x^j/j!
+    out.append("  template <typename T>")
+    out.append("  __device__ __forceinline__ static T l2p_pot(const T* L, T dx, T dy, T dz) {")
+    out.append(f"    T Mo[{NC}];")
+    out += ["    " + s for s in mono_lines(P)]
+    expr = None
+    for j in all_upto(P):
+        expr = f"L[{idx(j)}] * Mo[{idx(j)}]" if expr is None else f"fma(L[{idx(j)}], Mo[{idx(j)}], {expr})"
+    out.append(f"    return {expr};")
+    out.append("  }")
+
     # L2P (conserving): a_e = -x_e P(x) + Q'_e(x)
     out.append("  template <typename T>")
     out.append("  __device__ __forceinline__ static void l2p_cons(const T* Pl, const T* Ql, T dx, T dy, T dz, T* a) {")

@@ -126,6 +126,51 @@ __global__ __launch_bounds__(LB) void l2p_kernel(int64_t n, const double4* __res
     force[3 * o + 2] = s * (near[3 * j + 2] + a[2]);
 }
 
+// Potential output: phi_a = sum_{|j| <= p} L_j x^j / j! (standard locals with
+// L_0, of the same node pairs) + the near-field sum, less the particle's own
+// term -m_a / eps that the near-field kernel includes when eps > 0 (removed
+// in the precision it was added in); pot[a] = G phi_a in caller order.
+template <int P, typename TS>
+__global__ __launch_bounds__(LB) void l2p_pot_kernel(int64_t n, const double4* __restrict__ Xm,
+                                                     const int32_t* __restrict__ leaf_of,
+                                                     const int32_t* __restrict__ perm,
+                                                     const double4* __restrict__ Z,
+                                                     const double* __restrict__ loc_leaf,
+                                                     const double* __restrict__ near_pot, double eps2, double G,
+                                                     double* __restrict__ pot) {
+    using E = Expansion<P>;
+    const int64_t j = (int64_t)blockIdx.x * LB + threadIdx.x;
+    if (j >= n) return;
+    const int32_t leaf = leaf_of[j];
+    const double4 x = Xm[j];
+    const double4 z = Z[leaf];
+    double phi = E::l2p_pot(loc_leaf + (int64_t)leaf * E::NC, x.x - z.x, x.y - z.y, x.z - z.z) + near_pot[j];
+    if (eps2 > 0.0) {
+        if constexpr (sizeof(TS) == 4) phi += (double)((float)x.w * __builtin_amdgcn_rsqf((float)eps2));
+        else phi += x.w * rsqrt_refined(eps2);
+    }
+    pot[perm[j]] = G * phi;
+}
+
+template <int P>
+void potential_down(Tree& t, int precision, double eps2, double G, double* pot, hipStream_t s) {
+    const int64_t nl = t.n_leaves, n = t.n;
+    t.loc_pot_leaf.ensure(t.ctx, (size_t)t.n_nodes * Expansion<P>::NC * 8);
+    hipLaunchKernelGGL(l2l_std_kernel<P>, dim3((unsigned)cdiv(nl, LB)), dim3(LB), 0, s, nl, t.leaves.as<int32_t>(),
+                       t.nd_parent.as<int32_t>(), t.nd_Z.as<double4>(), t.m2l_off.as<uint32_t>(),
+                       t.loc_pot.as<double>(), t.loc_pot_leaf.as<double>());
+    TFMM_LAUNCHED();
+    if (precision == TFMM_MIXED32)
+        hipLaunchKernelGGL((l2p_pot_kernel<P, float>), dim3((unsigned)cdiv(n, LB)), dim3(LB), 0, s, n,
+                           t.Xm.as<double4>(), t.leaf_of.as<int32_t>(), t.perm.as<int32_t>(), t.nd_Z.as<double4>(),
+                           t.loc_pot_leaf.as<double>(), t.near_pot.as<double>(), eps2, G, pot);
+    else
+        hipLaunchKernelGGL((l2p_pot_kernel<P, double>), dim3((unsigned)cdiv(n, LB)), dim3(LB), 0, s, n,
+                           t.Xm.as<double4>(), t.leaf_of.as<int32_t>(), t.perm.as<int32_t>(), t.nd_Z.as<double4>(),
+                           t.loc_pot_leaf.as<double>(), t.near_pot.as<double>(), eps2, G, pot);
+    TFMM_LAUNCHED();
+}
+
 template <int P>
 void l2l_dispatch(Tree& t, int variant, hipStream_t s) {
     const int64_t nl = t.n_leaves;
@@ -168,6 +213,21 @@ void run_l2l(Tree& t, int p, int variant, hipStream_t s) {
         case 6: l2l_dispatch<6>(t, variant, s); break;
         case 7: l2l_dispatch<7>(t, variant, s); break;
         case 8: l2l_dispatch<8>(t, variant, s); break;
+        default: fail(TFMM_EINVAL, "p must be in 1..8");
+    }
+}
+
+// L2L of the potential locals (t.loc_pot) and the potential at every particle.
+void run_potential_down(Tree& t, int p, int precision, double eps2, double G, double* pot, hipStream_t s) {
+    switch (p) {
+        case 1: potential_down<1>(t, precision, eps2, G, pot, s); break;
+        case 2: potential_down<2>(t, precision, eps2, G, pot, s); break;
+        case 3: potential_down<3>(t, precision, eps2, G, pot, s); break;
+        case 4: potential_down<4>(t, precision, eps2, G, pot, s); break;
+        case 5: potential_down<5>(t, precision, eps2, G, pot, s); break;
+        case 6: potential_down<6>(t, precision, eps2, G, pot, s); break;
+        case 7: potential_down<7>(t, precision, eps2, G, pot, s); break;
+        case 8: potential_down<8>(t, precision, eps2, G, pot, s); break;
         default: fail(TFMM_EINVAL, "p must be in 1..8");
     }
 }

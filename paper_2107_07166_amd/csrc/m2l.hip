@@ -58,12 +58,15 @@ __device__ __forceinline__ T half_wave_sum_last(T v) {
     return v;
 }
 
-template <int P, int VAR, typename T>
+// POTL (standard only): also L_0, the potential's constant term.  wstride:
+// moments per node in W (the moments may be of a higher order than P; the
+// graded order puts the first c(<=P) of them first).
+template <int P, int VAR, typename T, bool POTL = false>
 __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
                                                  const uint32_t* __restrict__ off,
                                                  const uint32_t* __restrict__ src, uint32_t src_mask,
                                                  const double4* __restrict__ Z, const T* __restrict__ W,
-                                                 double eps2, double* __restrict__ loc) {
+                                                 int64_t wstride, double eps2, double* __restrict__ loc) {
     using E = Expansion<P>;
     constexpr int NC = E::NC;
     constexpr int NC1 = E::NC1;
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
 #pragma unroll
         for (int n = 1; n <= P; ++n) F[n] = (T)(-(2 * n - 1)) * F[n - 1] * inv_s;
         T w[NCP];
-        const typename Vec4<T>::type* wb = reinterpret_cast<const typename Vec4<T>::type*>(W + (int64_t)B * NCP);
+        const typename Vec4<T>::type* wb = reinterpret_cast<const typename Vec4<T>::type*>(W + (int64_t)B * wstride);
 #pragma unroll
         for (int k = 0; k < NCP / 4; ++k) {
             const typename Vec4<T>::type v = wb[k];
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
         } else {
             T D[NC];
             E::phi_derivs(Rx, Ry, Rz, F, D);
-            E::template m2l_std<T, false>(D, w, acc);
+            E::template m2l_std<T, POTL>(D, w, acc);
         }
     }
 #pragma unroll
@@ -231,8 +234,8 @@ void launch(Tree& t, double eps2, hipStream_t s) {
         TFMM_LAUNCHED();
     } else {
         hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), grid, dim3(MB), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
-                           t.loc.as<double>());
+                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W,
+                           (int64_t)round_up(c_le(P), 4), eps2, t.loc.as<double>());
         TFMM_LAUNCHED();
     }
 }
@@ -255,7 +258,46 @@ void dispatch_var(Tree& t, int variant, int precision, double eps2, hipStream_t 
     }
 }
 
+template <int P, typename T>
+void launch_pot(Tree& t, int mom_p, double eps2, hipStream_t s) {
+    const int64_t nt = t.n_nodes;
+    if (nt <= 0) return;
+    const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
+    const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, MB));
+    hipLaunchKernelGGL((m2l_kernel<P, TFMM_STANDARD, T, true>), grid, dim3(MB), 0, s, nt, t.m2l_off.as<uint32_t>(),
+                       t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W,
+                       (int64_t)round_up(c_le(mom_p), 4), eps2, t.loc_pot.as<double>());
+    TFMM_LAUNCHED();
+}
+
+template <int P>
+void dispatch_pot(Tree& t, int mom_p, int precision, double eps2, hipStream_t s) {
+    if (precision == TFMM_MIXED32) launch_pot<P, float>(t, mom_p, eps2, s);
+    else launch_pot<P, double>(t, mom_p, eps2, s);
+}
+
 }  // namespace
+
+// Standard locals with their constant term (the far-field potential of
+// Eq. taylor truncated at degree p) into t.loc_pot, for every variant; the
+// moments on the device are of order mom_p >= p.
+void run_m2l_pot(Tree& t, int p, int mom_p, int precision, double eps2, hipStream_t s) {
+    const int64_t tot = t.n_nodes * (int64_t)c_le(p);
+    t.loc_pot.ensure(t.ctx, (size_t)tot * 8);
+    hipLaunchKernelGGL(zero_f64_kernel, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, t.loc_pot.as<double>(), tot);
+    TFMM_LAUNCHED();
+    switch (p) {
+        case 1: dispatch_pot<1>(t, mom_p, precision, eps2, s); break;
+        case 2: dispatch_pot<2>(t, mom_p, precision, eps2, s); break;
+        case 3: dispatch_pot<3>(t, mom_p, precision, eps2, s); break;
+        case 4: dispatch_pot<4>(t, mom_p, precision, eps2, s); break;
+        case 5: dispatch_pot<5>(t, mom_p, precision, eps2, s); break;
+        case 6: dispatch_pot<6>(t, mom_p, precision, eps2, s); break;
+        case 7: dispatch_pot<7>(t, mom_p, precision, eps2, s); break;
+        case 8: dispatch_pot<8>(t, mom_p, precision, eps2, s); break;
+        default: fail(TFMM_EINVAL, "p must be in 1..8");
+    }
+}
 
 void run_m2l(Tree& t, int p, int variant, int precision, double eps2, hipStream_t s) {
     const int nloc = n_local(p, variant);

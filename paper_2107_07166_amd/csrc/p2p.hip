@@ -27,33 +27,27 @@ constexpr int CH = 256;   // staged source particles per chunk
 constexpr int UNR = 4;    // inner-loop unroll
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_t(double x) {
-    // v_rsq_f64 seed (about 2^-23 relative) refined by two Newton steps.
-    double y = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    double e = fma(-h * y, y, 0.5);
-    y = fma(y, e, y);
-    e = fma(-h * y, y, 0.5);
-    y = fma(y, e, y);
-    return y;
-}
+__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt_refined(x); }
 
 template <typename T>
 __device__ __forceinline__ T far_away();
 template <> __device__ __forceinline__ float far_away<float>() { return 1.0e18f; }
 template <> __device__ __forceinline__ double far_away<double>() { return 1.0e100; }
 
-template <typename T, bool SAFE>
+// POT: also the potential -m_b (r^2 + eps^2)^(-1/2) into ph.
+template <typename T, bool SAFE, bool POT>
 __device__ __forceinline__ void interact(const typename Vec4<T>::type& s, T tx, T ty, T tz, T eps2, T& ax,
-                                         T& ay, T& az) {
+                                         T& ay, T& az, T& ph) {
     const T dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
     const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
     const T ri = rsqrt_t(r2);
-    T w = s.w * ri * (ri * ri);
+    const T mri = s.w * ri;
+    T w = mri * (ri * ri);
     if (SAFE) w = (r2 > T(0)) ? w : T(0);
     ax = fma(w, dx, ax);
     ay = fma(w, dy, ay);
     az = fma(w, dz, az);
+    if constexpr (POT) ph -= (SAFE && !(r2 > T(0))) ? T(0) : mri;
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
@@ -87,9 +81,9 @@ __device__ __forceinline__ void chunk_layout(int nt, int& R, int& L, int& G) {
 }
 
 // Interactions of one staged chunk for a lane's R targets: sources g, g + G, ...
-template <typename T, bool SAFE, int R>
+template <typename T, bool SAFE, bool POT, int R>
 __device__ __forceinline__ void consume(const typename Vec4<T>::type* stage, int g, int G, int cp, const T* tx,
-                                        const T* ty, const T* tz, T eps2, T* sx, T* sy, T* sz) {
+                                        const T* ty, const T* tz, T eps2, T* sx, T* sy, T* sz, T* sp) {
     constexpr int U = (R >= 4) ? 1 : 4 / R;
     const int step = G * U;
     const int cmain = cp / step * step;
@@ -99,17 +93,20 @@ __device__ __forceinline__ void consume(const typename Vec4<T>::type* stage, int
         for (int u = 0; u < U; ++u) {
             const typename Vec4<T>::type v = stage[k + u * G];
 #pragma unroll
-            for (int r = 0; r < R; ++r) interact<T, SAFE>(v, tx[r], ty[r], tz[r], eps2, sx[r], sy[r], sz[r]);
+            for (int r = 0; r < R; ++r)
+                interact<T, SAFE, POT>(v, tx[r], ty[r], tz[r], eps2, sx[r], sy[r], sz[r], sp[r]);
         }
     }
     for (; k < cp; k += G) {
         const typename Vec4<T>::type v = stage[k];
 #pragma unroll
-        for (int r = 0; r < R; ++r) interact<T, SAFE>(v, tx[r], ty[r], tz[r], eps2, sx[r], sy[r], sz[r]);
+        for (int r = 0; r < R; ++r) interact<T, SAFE, POT>(v, tx[r], ty[r], tz[r], eps2, sx[r], sy[r], sz[r], sp[r]);
     }
 }
 
-template <typename T, bool SAFE>
+// POT: the near-field potential too (-sum m_b (r^2 + eps^2)^(-1/2), the
+// particle's own term included when eps > 0; the caller removes it).
+template <typename T, bool SAFE, bool POT>
 __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ it_leaf,
                                                     const uint32_t* __restrict__ it_q0,
                                                     const uint32_t* __restrict__ it_q1,
@@ -120,21 +117,26 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                                                     const double4* __restrict__ Z,
                                                     const typename Vec4<T>::type* __restrict__ P, T eps2,
                                                     const int32_t* __restrict__ leaf_nitems,
-                                                    double* __restrict__ partial, double* __restrict__ near) {
+                                                    double* __restrict__ partial, double* __restrict__ near,
+                                                    double* __restrict__ partial_pot,
+                                                    double* __restrict__ near_pot) {
     using V4 = typename Vec4<T>::type;
     constexpr int SPL = CH / kWave;  // staged sources per lane per chunk
     __shared__ V4 stage[CH + kWave];
     __shared__ int e_start[kWave];
     __shared__ int e_first[kWave];
     __shared__ double e_off[3][kWave];
-    __shared__ double red[3][kWave];
+    __shared__ double red[POT ? 4 : 3][kWave];
     const int lane = threadIdx.x;
     const int32_t A = it_leaf[blockIdx.x];
     const int32_t fa = first[A], na = count[A];
     const double4 za = Z[A];
     const uint32_t q0 = it_q0[blockIdx.x], q1 = it_q1[blockIdx.x];
     // a leaf served by one item writes the result, otherwise its own partial slot
-    double* out = (leaf_nitems[A] == 1) ? near + 3 * (int64_t)fa : partial + 3 * (int64_t)it_pbase[blockIdx.x];
+    const bool whole = leaf_nitems[A] == 1;
+    double* out = whole ? near + 3 * (int64_t)fa : partial + 3 * (int64_t)it_pbase[blockIdx.x];
+    double* pout = nullptr;
+    if constexpr (POT) pout = whole ? near_pot + fa : partial_pot + it_pbase[blockIdx.x];
     V4 pad;
     pad.x = far_away<T>();
     pad.y = far_away<T>();
@@ -159,9 +161,9 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
             ty[r] = me.y;
             tz[r] = me.z;
         }
-        double ax[RMAX], ay[RMAX], az[RMAX];
+        double ax[RMAX], ay[RMAX], az[RMAX], ap[RMAX];
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r) ax[r] = ay[r] = az[r] = 0.0;
+        for (int r = 0; r < RMAX; ++r) ax[r] = ay[r] = az[r] = ap[r] = 0.0;
 
         for (uint32_t qb = q0; qb < q1; qb += kWave) {
             // one list entry per lane: source leaf, its range and its offset
@@ -214,15 +216,15 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                 const int cp = (cnt + G - 1) / G * G;
                 if (cnt + lane < cp) stage[cnt + lane] = pad;
                 __syncthreads();
-                T sx[RMAX], sy[RMAX], sz[RMAX];
+                T sx[RMAX], sy[RMAX], sz[RMAX], sp[RMAX];
 #pragma unroll
-                for (int r = 0; r < RMAX; ++r) sx[r] = sy[r] = sz[r] = T(0);
+                for (int r = 0; r < RMAX; ++r) sx[r] = sy[r] = sz[r] = sp[r] = T(0);
                 if (act) {
                     switch (R) {
-                        case 1: consume<T, SAFE, 1>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz); break;
-                        case 2: consume<T, SAFE, 2>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz); break;
-                        case 3: consume<T, SAFE, 3>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz); break;
-                        default: consume<T, SAFE, 4>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz); break;
+                        case 1: consume<T, SAFE, POT, 1>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz, sp); break;
+                        case 2: consume<T, SAFE, POT, 2>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz, sp); break;
+                        case 3: consume<T, SAFE, POT, 3>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz, sp); break;
+                        default: consume<T, SAFE, POT, 4>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz, sp); break;
                     }
                 }
 #pragma unroll
@@ -230,6 +232,7 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                     ax[r] += (double)sx[r];
                     ay[r] += (double)sy[r];
                     az[r] += (double)sz[r];
+                    if constexpr (POT) ap[r] += (double)sp[r];
                 }
                 __syncthreads();
             }
@@ -238,19 +241,21 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
         // target t = l R + r sits in slot r of lanes l, l + L, ..., one per
         // group; slot by slot, through LDS
         const int tl = lane / R, tr = lane % R;
-        double fx = 0.0, fy = 0.0, fz = 0.0;
+        double fx = 0.0, fy = 0.0, fz = 0.0, fp = 0.0;
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             if (r < R) {
                 red[0][lane] = ax[r];
                 red[1][lane] = ay[r];
                 red[2][lane] = az[r];
+                if constexpr (POT) red[POT ? 3 : 0][lane] = ap[r];
                 __syncthreads();
                 if (lane < nt && tr == r) {
                     for (int q = 0; q < G; ++q) {
                         fx += red[0][q * L + tl];
                         fy += red[1][q * L + tl];
                         fz += red[2][q * L + tl];
+                        if constexpr (POT) fp += red[POT ? 3 : 0][q * L + tl];
                     }
                 }
                 __syncthreads();
@@ -261,12 +266,14 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
             out[3 * j] = fx;
             out[3 * j + 1] = fy;
             out[3 * j + 2] = fz;
+            if constexpr (POT) pout[j] = fp;
         }
     }
 }
 
 // Leaves served by several items: one wavefront per such leaf (launched on its
 // first item) adds the items' partial sums in item order.
+template <bool POT>
 __global__ __launch_bounds__(kWave) void p2p_reduce_kernel(const int32_t* __restrict__ it_leaf,
                                                            const int32_t* __restrict__ leaf_item0,
                                                            const int32_t* __restrict__ leaf_nitems,
@@ -274,57 +281,72 @@ __global__ __launch_bounds__(kWave) void p2p_reduce_kernel(const int32_t* __rest
                                                            const int32_t* __restrict__ count,
                                                            const uint32_t* __restrict__ it_pbase,
                                                            const double* __restrict__ partial,
-                                                           double* __restrict__ near) {
+                                                           double* __restrict__ near,
+                                                           const double* __restrict__ partial_pot,
+                                                           double* __restrict__ near_pot) {
     const int32_t L = it_leaf[blockIdx.x];
     const int32_t ni = leaf_nitems[L];
     if (ni == 1 || leaf_item0[L] != (int32_t)blockIdx.x) return;
     const int32_t fa = first[L], na = count[L];
     for (int32_t r = threadIdx.x; r < na; r += kWave) {
-        double sx = 0.0, sy = 0.0, sz = 0.0;
+        double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
         for (int32_t i = 0; i < ni; ++i) {
-            const double* p = partial + 3 * ((int64_t)it_pbase[blockIdx.x + i] + r);
+            const int64_t row = (int64_t)it_pbase[blockIdx.x + i] + r;
+            const double* p = partial + 3 * row;
             sx += p[0];
             sy += p[1];
             sz += p[2];
+            if constexpr (POT) sp += partial_pot[row];
         }
         near[3 * (int64_t)(fa + r)] = sx;
         near[3 * (int64_t)(fa + r) + 1] = sy;
         near[3 * (int64_t)(fa + r) + 2] = sz;
+        if constexpr (POT) near_pot[fa + r] = sp;
     }
 }
 
-template <typename T>
+template <typename T, bool POT>
 void launch(Tree& t, double eps2, hipStream_t s) {
     using V4 = typename Vec4<T>::type;
     const int64_t ni = t.n_items;
     if (ni <= 0) return;
     const dim3 g((unsigned)ni);
+    double* ppot = POT ? t.partial_pot.as<double>() : nullptr;
+    double* npot = POT ? t.near_pot.as<double>() : nullptr;
     if (eps2 > 0.0)
-        hipLaunchKernelGGL((p2p_kernel<T, false>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
+        hipLaunchKernelGGL((p2p_kernel<T, false, POT>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
                            t.it_q0.as<uint32_t>(), t.it_q1.as<uint32_t>(), t.it_pbase.as<uint32_t>(),
                            t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(), t.p2p_src.as<int32_t>(),
                            t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.leaf_nitems.as<int32_t>(),
-                           t.partial.as<double>(), t.near3.as<double>());
+                           t.partial.as<double>(), t.near3.as<double>(), ppot, npot);
     else
-        hipLaunchKernelGGL((p2p_kernel<T, true>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
+        hipLaunchKernelGGL((p2p_kernel<T, true, POT>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
                            t.it_q0.as<uint32_t>(), t.it_q1.as<uint32_t>(), t.it_pbase.as<uint32_t>(),
                            t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(), t.p2p_src.as<int32_t>(),
                            t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.leaf_nitems.as<int32_t>(),
-                           t.partial.as<double>(), t.near3.as<double>());
+                           t.partial.as<double>(), t.near3.as<double>(), ppot, npot);
     TFMM_LAUNCHED();
-    hipLaunchKernelGGL(p2p_reduce_kernel, g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(), t.leaf_item0.as<int32_t>(),
-                       t.leaf_nitems.as<int32_t>(), t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(),
-                       t.it_pbase.as<uint32_t>(), t.partial.as<double>(), t.near3.as<double>());
+    hipLaunchKernelGGL((p2p_reduce_kernel<POT>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
+                       t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>(), t.nd_first.as<int32_t>(),
+                       t.nd_count.as<int32_t>(), t.it_pbase.as<uint32_t>(), t.partial.as<double>(),
+                       t.near3.as<double>(), (const double*)ppot, npot);
     TFMM_LAUNCHED();
 }
 
 }  // namespace
 
-void run_p2p(Tree& t, int precision, double eps2, hipStream_t s) {
+void run_p2p(Tree& t, int precision, double eps2, bool with_pot, hipStream_t s) {
     t.near3.ensure(t.ctx, (size_t)t.n * 24);
     t.partial.ensure(t.ctx, (size_t)std::max<int64_t>(t.n_partial, 1) * 24);
-    if (precision == TFMM_MIXED32) launch<float>(t, eps2, s);
-    else launch<double>(t, eps2, s);
+    if (with_pot) {
+        t.near_pot.ensure(t.ctx, (size_t)t.n * 8);
+        t.partial_pot.ensure(t.ctx, (size_t)std::max<int64_t>(t.n_partial, 1) * 8);
+        if (precision == TFMM_MIXED32) launch<float, true>(t, eps2, s);
+        else launch<double, true>(t, eps2, s);
+    } else {
+        if (precision == TFMM_MIXED32) launch<float, false>(t, eps2, s);
+        else launch<double, false>(t, eps2, s);
+    }
 }
 
 }  // namespace tfmm

@@ -217,6 +217,37 @@ def test_conserving_r2_is_zeroth_order_only(ctx):
     assert np.isfinite(f).all()
 
 
+POT_CASES = [
+    ("ball2k", 16, 0.5, 4, 1e-3, "standard"), ("ball2k", 8, 0.6, 3, 0.05, "conserving"),
+    ("ball2k", 16, 0.5, 1, 0.0, "conserving_r2"), ("ball2k", 16, 0.7, 6, 1e-3, "standard"),
+    ("plummer20k", 16, 0.5, 4, 1e-3, "conserving"), ("coplanar_dups", 16, 0.6, 2, 1e-2, "standard"),
+]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("mixed32", TOL_MIXED)])
+@pytest.mark.parametrize("name,n_leaf,theta,p,eps,variant", POT_CASES)
+def test_potential_matches_oracle(ctx, name, n_leaf, theta, p, eps, variant, prec, tol):
+    """Potential output: exact near field (the particle's own softened term
+    removed) plus the far field from the standard expansion of order p, for
+    every variant; the forces of the same call equal those of a call without
+    the potential."""
+    pos, m = _case(name)
+    key = ("pot", name, n_leaf, theta, p, eps, variant)
+    if key not in _oracle_cache:
+        _oracle_cache[key] = oracle.Tree(pos, m, n_leaf=n_leaf, theta=theta).forces(p, eps, variant,
+                                                                                    with_potential=True)
+    ref_f, ref_pot = _oracle_cache[key]
+    gt = _gpu_tree(ctx, pos, m, n_leaf)
+    pot = torch.empty(len(m), dtype=torch.float64, device="cuda")
+    f = gt.evaluate(p=p, theta=theta, eps=eps, variant=variant, precision=prec, pot=pot).cpu().numpy()
+    f0 = gt.evaluate(p=p, theta=theta, eps=eps, variant=variant, precision=prec).cpu().numpy()
+    gt.close()
+    ph = pot.cpu().numpy()
+    assert float(np.sqrt(np.mean((ph - ref_pot) ** 2) / np.mean(ref_pot ** 2))) <= tol
+    assert _erms(f, ref_f) <= tol
+    np.testing.assert_allclose(f, f0, rtol=1e-14, atol=0)
+
+
 def test_direct_limit_theta0(ctx):
     pos, m = uniform_ball(1500, 3)
     ref = oracle.direct(pos, m, 1e-3)
