@@ -80,6 +80,22 @@ class Session:
         return {"net_force": d[0:3], "net_torque": d[4:7], "P": d[8:11], "L": d[11:14], "mass": d[14],
                 "com": d[15:18], "force_rel": float(d[18]), "torque_rel": float(d[19])}
 
+    def energy(self) -> dict:
+        """Kinetic, potential and total energy at the current state (FP64
+        sums on the GPU): K = sum m v^2 / 2, W = sum m_a phi_a / 2 with phi from
+        the library's potential output (an extra evaluation with the
+        session's parameters; the resident forces are left as they are)."""
+        self.forces()
+        q = self.params
+        with self._stream_ctx():
+            f = torch.empty_like(self.pos)
+            phi = torch.empty_like(self.mass)
+            self.tree.evaluate(p=q["p"], theta=q["theta"], eps=q["eps"], variant=q["variant"],
+                               precision=q["precision"], G=q["G"], out=f, pot=phi)
+            K = 0.5 * float((self.mass * (self.vel * self.vel).sum(1)).sum())
+            W = 0.5 * float((self.mass * phi).sum())
+        return {"K": K, "W": W, "E": K + W}
+
     def snapshot(self, path) -> None:
         """Write the resident state and parameters to an .npz file."""
         torch.cuda.synchronize(self.pos.device)

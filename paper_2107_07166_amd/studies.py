@@ -3,7 +3,8 @@
     python -m paper_2107_07166_amd.studies binary [--n N] [--steps 200] [--dt 1e-3]
         Two n=1 polytropes on a circular orbit (p=4, theta=0.7, mixed): the
         angular momentum drift of the standard and the conserving variant over
-        leapfrog steps, and the time per step.
+        leapfrog steps, the relative energy change over the run, and the time
+        per step.
     python -m paper_2107_07166_amd.studies disk [--n N]
         Exponential disk (p=6, theta=0.8): time of both variants (the cost of
         realignment), net torque, mixed vs FP64 force difference.
@@ -58,6 +59,7 @@ def study_binary(n: int, steps: int, dt: float, n_leaf: int) -> dict:
                     precision="mixed32", n_leaf=n_leaf)
         d0 = s.diagnostics()
         L0 = d0["L"]
+        E0 = s.energy()["E"]
         drift, torque = [], []
         t_total = 0.0
         for k in range(steps):
@@ -69,9 +71,11 @@ def study_binary(n: int, steps: int, dt: float, n_leaf: int) -> dict:
             d = s.diagnostics()
             drift.append(float(np.linalg.norm(d["L"] - L0) / np.linalg.norm(L0)))
             torque.append(d["torque_rel"])
+        E1 = s.energy()["E"]
         out[variant] = {"L_drift_final": drift[-1], "L_drift_max": max(drift),
                         "L_drift_every_20": drift[19::20], "torque_rel_mean": float(np.mean(torque)),
-                        "P_final": [float(x) for x in d["P"]], "ms_per_step": 1e3 * t_total / steps}
+                        "P_final": [float(x) for x in d["P"]], "ms_per_step": 1e3 * t_total / steps,
+                        "E0": E0, "E_drift_final": abs(E1 - E0) / abs(E0)}
         s.close()
         ctx.close()
     return out

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2107_07166_amd.generators import polytrope_binary
+from paper_2107_07166_amd.generators import polytrope_binary, uniform_ball
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -104,3 +104,20 @@ def test_snapshot_restore_is_bitwise(ctx, tmp_path):
     out = c.pos.cpu().numpy()
     c.close()
     assert np.array_equal(out, ref)
+
+
+def test_energy_matches_oracle_potential(ctx):
+    """Session.energy: K from the resident velocities, W = sum m phi / 2 with phi
+    the library's potential output, against the oracle's potential (FP64)."""
+    from paper_2107_07166_amd.session import Session
+    pos, m = uniform_ball(3000, 21)
+    vel = np.random.default_rng(22).normal(size=pos.shape) * 0.1
+    s = Session(ctx, _dev(pos), _dev(vel), _dev(m), p=4, theta=0.5, eps=1e-3, variant="conserving",
+                precision="fp64", n_leaf=16)
+    e = s.energy()
+    s.close()
+    _, phi = oracle.Tree(pos, m, n_leaf=16, theta=0.5).forces(4, 1e-3, "conserving", with_potential=True)
+    K = 0.5 * float((m * (vel * vel).sum(1)).sum())
+    W = 0.5 * float((m * phi).sum())
+    assert abs(e["K"] - K) <= 1e-13 * abs(K)
+    assert abs(e["W"] - W) <= 1e-12 * abs(W)
