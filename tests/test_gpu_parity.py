@@ -306,6 +306,15 @@ def test_full_size_plummer_1m(ctx):
         for prec, tol in (("fp64", TOL_FP64), ("mixed32", TOL_MIXED)):
             f = gt.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision=prec).cpu().numpy()
             assert _erms(f[sample], ref) <= tol, (variant, prec, _erms(f[sample], ref))
+    # the zeroth-order magnitude realignment and the potential output at full size
+    ref_f, ref_pot = ot.forces(1, w.eps, "conserving_r2", targets=sample, with_potential=True)
+    for prec, tol in (("fp64", TOL_FP64), ("mixed32", TOL_MIXED)):
+        pot = torch.empty(len(m), dtype=torch.float64, device="cuda")
+        f = gt.evaluate(p=1, theta=w.theta, eps=w.eps, variant="conserving_r2", precision=prec,
+                        pot=pot).cpu().numpy()
+        ph = pot.cpu().numpy()[sample]
+        assert _erms(f[sample], ref_f) <= tol, (prec, _erms(f[sample], ref_f))
+        assert float(np.sqrt(np.mean((ph - ref_pot) ** 2) / np.mean(ref_pot ** 2))) <= tol, prec
     gt.close()
 
 
