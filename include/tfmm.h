@@ -91,7 +91,11 @@ int tfmm_ctx_destroy(tfmm_ctx *ctx);
  * the next call on the context. */
 const char *tfmm_last_error(const tfmm_ctx *ctx);
 
-/* Device memory currently held by the context's trees and scratch. */
+/* Device memory currently held by the context's trees and scratch.  Buffers
+ * released by destroyed or resized trees stay with the context for reuse by
+ * later trees (they count against hbm_budget_bytes, and are given back to the
+ * device when a new allocation would exceed the budget or fail, and when the
+ * context is destroyed); they are not included here. */
 size_t tfmm_ctx_bytes_in_use(const tfmm_ctx *ctx);
 
 /* Build the tree for n particles.  pos: device, n x 3 FP64 row-major (x, y, z

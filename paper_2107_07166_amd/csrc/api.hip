@@ -22,15 +22,17 @@ void DevBuf::ensure(Ctx* c, size_t bytes) {
     release();
     ctx = c;
     const size_t want = (size_t)round_up((int64_t)bytes, 256);
-    p = c->alloc(want);
-    cap = want;
+    size_t got = 0;
+    p = c->alloc(want, &got);
+    cap = got;
 }
 
 void DevBuf::ensure_keep(Ctx* c, size_t bytes, hipStream_t s) {
     if (bytes == 0) bytes = 16;
     if (p && cap >= bytes) return;
     const size_t want = (size_t)round_up((int64_t)bytes, 256);
-    void* q = c->alloc(want);
+    size_t got = 0;
+    void* q = c->alloc(want, &got);
     if (p) {
         TFMM_HIP(hipMemcpyAsync(q, p, cap, hipMemcpyDeviceToDevice, s));
         TFMM_HIP(hipStreamSynchronize(s));
@@ -38,31 +40,60 @@ void DevBuf::ensure_keep(Ctx* c, size_t bytes, hipStream_t s) {
     release();
     ctx = c;
     p = q;
-    cap = want;
+    cap = got;
 }
 
-void* Ctx::alloc(size_t bytes) {
+// A cached block of size in [bytes, 2 bytes] is reused as is; otherwise new
+// memory, after giving the cache back if the budget or the device is short.
+void* Ctx::alloc(size_t bytes, size_t* got) {
+    auto it = cache.lower_bound(bytes);
+    if (it != cache.end() && it->first <= 2 * bytes) {
+        void* q = it->second;
+        *got = it->first;
+        cached -= it->first;
+        cache.erase(it);
+        return q;
+    }
+    if (budget && used + bytes > budget) trim_cache();
     if (budget && used + bytes > budget)
         fail(TFMM_ENOMEM, "device memory budget exceeded (" + std::to_string(used + bytes) + " > " +
                               std::to_string(budget) + " bytes)");
     void* q = nullptr;
-    const hipError_t e = hipMalloc(&q, bytes);
+    hipError_t e = hipMalloc(&q, bytes);
+    if ((e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) && !cache.empty()) {
+        (void)hipGetLastError();
+        trim_cache();
+        e = hipMalloc(&q, bytes);
+    }
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
         (void)hipGetLastError();
         fail(TFMM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: out of device memory");
     }
     if (e != hipSuccess) fail(TFMM_EDEVICE, std::string("hipMalloc failed: ") + hipGetErrorString(e));
     used += bytes;
+    *got = bytes;
     return q;
 }
 
+// A buffer is only released when it grows or its owner goes away; kernels
+// queued earlier may still read it, so the device must be idle before the
+// block can serve a new owner.
 void Ctx::free(void* q, size_t bytes) {
     if (!q) return;
-    // a buffer is only released when it grows or its owner goes away; kernels
-    // queued earlier may still read it
+    if (!idle_release) (void)hipDeviceSynchronize();
+    cache.emplace(bytes, q);
+    cached += bytes;
+}
+
+void Ctx::trim_cache() {
+    if (cache.empty()) return;
     (void)hipDeviceSynchronize();
-    (void)hipFree(q);
-    used -= std::min(used, bytes);
+    for (auto& kv : cache) {
+        (void)hipFree(kv.second);
+        used -= std::min(used, kv.first);
+    }
+    cache.clear();
+    cached = 0;
 }
 
 namespace {
@@ -195,6 +226,7 @@ int tfmm_ctx_destroy(tfmm_ctx* ctx) {
     }
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    ctx->trim_cache();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->dev_err) (void)hipFree(ctx->dev_err);
     delete ctx;
@@ -203,7 +235,7 @@ int tfmm_ctx_destroy(tfmm_ctx* ctx) {
 
 const char* tfmm_last_error(const tfmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
 
-size_t tfmm_ctx_bytes_in_use(const tfmm_ctx* ctx) { return ctx ? ctx->used : 0; }
+size_t tfmm_ctx_bytes_in_use(const tfmm_ctx* ctx) { return ctx ? ctx->used - ctx->cached : 0; }
 
 int tfmm_build_tree(tfmm_ctx* ctx, int64_t n, const double* pos, const double* mass, int n_leaf, void* stream,
                     tfmm_tree** out) {
@@ -399,7 +431,10 @@ int tfmm_tree_destroy(tfmm_tree* tree) {
         (void)hipEventDestroy(tree->join_ev);
         (void)hipStreamDestroy(tree->aux);
     }
+    // the device is idle: the tree's buffers go to the context's cache directly
+    ctx->idle_release = true;
     delete tree;
+    ctx->idle_release = false;
     ctx->live_trees--;
     return TFMM_OK;
 }

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -57,14 +58,20 @@ struct DevBuf {
 struct Ctx {
     int device = 0;
     size_t budget = 0;  // 0 = unlimited
-    size_t used = 0;
+    size_t used = 0;    // device bytes held: live buffers plus the cache below
+    // Released blocks kept for reuse (keyed by size): a block enters the cache
+    // only once the device is idle, so a new owner never races an old kernel.
+    std::multimap<size_t, void*> cache;
+    size_t cached = 0;
+    bool idle_release = false;  // set while an owner known to be idle releases its buffers
+    void trim_cache();          // waits for the device, frees every cached block
     std::string err;
     bool broken = false;
     void* pinned = nullptr;  // small pinned host staging area
     size_t pinned_bytes = 0;
     uint32_t* dev_err = nullptr;  // device word set by a kernel whose bounded wait ran out
     int live_trees = 0;
-    void* alloc(size_t bytes);
+    void* alloc(size_t bytes, size_t* got);  // *got: the block's size (>= bytes)
     void free(void* p, size_t bytes);
 };
 

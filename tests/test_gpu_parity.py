@@ -358,3 +358,26 @@ def test_nonfinite_positions_rejected(ctx, bad):
     ot = oracle.Tree(pos, m, n_leaf=16, theta=0.5)
     assert np.array_equal(gt.export()["keys"], ot.keys()[0])
     gt.close()
+
+
+def test_released_buffers_are_reused_safely(ctx):
+    """Buffers of a destroyed tree stay with the context and serve the next
+    tree; results are those of a fresh context, and the context reports no
+    live bytes once its trees are gone."""
+    from paper_2107_07166_amd import api
+    pos1, m1 = plummer(20000, 31)
+    pos2, m2 = uniform_ball(15000, 32)
+    base = ctx.bytes_in_use()
+    t1 = _gpu_tree(ctx, pos1, m1, 16)
+    t1.evaluate(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32")
+    t1.close()
+    assert ctx.bytes_in_use() == base
+    t2 = _gpu_tree(ctx, pos2, m2, 16)
+    f2 = t2.evaluate(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32").cpu().numpy()
+    t2.close()
+    fresh = api.Context(0)
+    t3 = _gpu_tree(fresh, pos2, m2, 16)
+    f3 = t3.evaluate(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32").cpu().numpy()
+    t3.close()
+    fresh.close()
+    assert np.array_equal(f2, f3)
