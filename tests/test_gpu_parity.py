@@ -381,3 +381,64 @@ def test_released_buffers_are_reused_safely(ctx):
     t3.close()
     fresh.close()
     assert np.array_equal(f2, f3)
+
+
+def test_invalid_arguments_rejected(ctx):
+    """Empty input and out-of-range parameters are argument errors (status
+    TFMM_EINVAL with a message), raised before any device work; the tree and
+    the context stay usable and later results are unchanged."""
+    import ctypes
+    from paper_2107_07166_amd import _lib, api
+    empty_pos = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    empty_m = torch.empty((0,), dtype=torch.float64, device="cuda")
+    with pytest.raises(api.TfmmError) as e:
+        api.Tree(ctx, empty_pos, empty_m, n_leaf=16)
+    assert e.value.status == _lib.EINVAL and "n must be" in str(e.value)
+    pos, m = uniform_ball(2048, 210707166)
+    for n_leaf in (0, 5000):
+        with pytest.raises(api.TfmmError) as e:
+            _gpu_tree(ctx, pos, m, n_leaf)
+        assert e.value.status == _lib.EINVAL and "n_leaf" in str(e.value)
+    gt = _gpu_tree(ctx, pos, m, 16)
+    ref = gt.evaluate(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32").cpu().numpy()
+    bad = [dict(p=0), dict(p=9), dict(theta=1.0), dict(theta=-0.1), dict(eps=-1.0), dict(eps=float("inf")),
+           dict(G=float("nan"))]
+    for kw in bad:
+        args = dict(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32")
+        args.update(kw)
+        with pytest.raises(api.TfmmError) as e:
+            gt.evaluate(**args)
+        assert e.value.status == _lib.EINVAL, kw
+    out = torch.empty((len(m), 3), dtype=torch.float64, device="cuda")
+    for variant, precision in ((7, _lib.MIXED32), (_lib.CONSERVING, 9)):
+        prm = _lib.Params(4, 0.5, 1e-3, 1.0, variant, precision)
+        rc = ctx.lib.tfmm_evaluate_forces(gt.handle, ctypes.byref(prm), out.data_ptr(), None, None)
+        assert rc == _lib.EINVAL, (variant, precision)
+    with pytest.raises(api.TfmmError) as e:
+        gt.walk(1.0)
+    assert e.value.status == _lib.EINVAL
+    again = gt.evaluate(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32").cpu().numpy()
+    assert np.array_equal(again, ref)
+    gt.close()
+
+
+def test_ragged_rebuilds_match_fresh_trees(ctx):
+    """One tree rebuilt for inputs of different sizes (smaller, larger, the
+    same again) gives, each time, the forces of a tree built fresh for that
+    input, bit for bit, and the oracle's lists."""
+    sets = [plummer(20000, 41), uniform_ball(777, 42), plummer(33333, 43), plummer(20000, 41)]
+    gt = None
+    for pos, m in sets:
+        if gt is None:
+            gt = _gpu_tree(ctx, pos, m, 16)
+        else:
+            gt.rebuild(_dev(pos), _dev(m))
+        f = gt.evaluate(p=4, theta=0.6, eps=1e-3, variant="conserving", precision="mixed32").cpu().numpy()
+        fresh = _gpu_tree(ctx, pos, m, 16)
+        f0 = fresh.evaluate(p=4, theta=0.6, eps=1e-3, variant="conserving", precision="mixed32").cpu().numpy()
+        fresh.close()
+        assert np.array_equal(f, f0), len(m)
+        gf, gn = gt.lists()
+        of, on = oracle.Tree(pos, m, n_leaf=16, theta=0.6).lists()
+        assert np.array_equal(_pairset(gf), _pairset(of)) and np.array_equal(_pairset(gn), _pairset(on))
+    gt.close()
