@@ -169,10 +169,10 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
     run_l2l(t, pe, ve, a);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[3], a));
     if (need_walk) walk_lists_end(t, s);
-    aux_join(t, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[6], s));
     run_p2p(t, prm->precision, eps2, potential != nullptr, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[4], s));
+    aux_join(t, s);
     run_l2p(t, pe, ve, prm->G, force, s);
     if (potential) {
         // far-field potential from the standard expansion of order p (every

@@ -143,6 +143,8 @@ struct Tree {
     int64_t n_items = 0, n_partial = 0;
     DevBuf it_leaf, it_q0, it_q1, it_pbase;  // per item: leaf, entry range, partial offset
     DevBuf leaf_item0, leaf_nitems;           // per node: first item and item count of a leaf
+    DevBuf multi_leaf;                        // leaves split into several items (any order)
+    const uint32_t* multi_count = nullptr;    // device: number of entries in multi_leaf
     DevBuf partial;                           // FP64 partial near-field sums, 3 per (item, target)
 
     // expansions

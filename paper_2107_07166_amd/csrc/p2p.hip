@@ -271,10 +271,12 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
     }
 }
 
-// Leaves served by several items: one wavefront per such leaf (launched on its
-// first item) adds the items' partial sums in item order.
+// Leaves served by several items (listed in multi_leaf, in any order): one
+// wavefront per such leaf adds the items' partial sums in item order.  The
+// grid is an upper bound of the list length; the surplus wavefronts exit.
 template <bool POT>
-__global__ __launch_bounds__(kWave) void p2p_reduce_kernel(const int32_t* __restrict__ it_leaf,
+__global__ __launch_bounds__(kWave) void p2p_reduce_kernel(const int32_t* __restrict__ multi_leaf,
+                                                           const uint32_t* __restrict__ multi_count,
                                                            const int32_t* __restrict__ leaf_item0,
                                                            const int32_t* __restrict__ leaf_nitems,
                                                            const int32_t* __restrict__ first,
@@ -284,14 +286,14 @@ __global__ __launch_bounds__(kWave) void p2p_reduce_kernel(const int32_t* __rest
                                                            double* __restrict__ near,
                                                            const double* __restrict__ partial_pot,
                                                            double* __restrict__ near_pot) {
-    const int32_t L = it_leaf[blockIdx.x];
-    const int32_t ni = leaf_nitems[L];
-    if (ni == 1 || leaf_item0[L] != (int32_t)blockIdx.x) return;
+    if (blockIdx.x >= *multi_count) return;
+    const int32_t L = multi_leaf[blockIdx.x];
+    const int32_t ni = leaf_nitems[L], i0 = leaf_item0[L];
     const int32_t fa = first[L], na = count[L];
     for (int32_t r = threadIdx.x; r < na; r += kWave) {
         double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
         for (int32_t i = 0; i < ni; ++i) {
-            const int64_t row = (int64_t)it_pbase[blockIdx.x + i] + r;
+            const int64_t row = (int64_t)it_pbase[i0 + i] + r;
             const double* p = partial + 3 * row;
             sx += p[0];
             sy += p[1];
@@ -326,11 +328,16 @@ void launch(Tree& t, double eps2, hipStream_t s) {
                            t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.leaf_nitems.as<int32_t>(),
                            t.partial.as<double>(), t.near3.as<double>(), ppot, npot);
     TFMM_LAUNCHED();
-    hipLaunchKernelGGL((p2p_reduce_kernel<POT>), g, dim3(kWave), 0, s, t.it_leaf.as<int32_t>(),
-                       t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>(), t.nd_first.as<int32_t>(),
-                       t.nd_count.as<int32_t>(), t.it_pbase.as<uint32_t>(), t.partial.as<double>(),
-                       t.near3.as<double>(), (const double*)ppot, npot);
-    TFMM_LAUNCHED();
+    // every leaf has at least one item, so at most n_items - n_leaves leaves have several
+    const int64_t nmulti = ni - t.n_leaves;
+    if (nmulti > 0) {
+        hipLaunchKernelGGL((p2p_reduce_kernel<POT>), dim3((unsigned)nmulti), dim3(kWave), 0, s,
+                           t.multi_leaf.as<int32_t>(), t.multi_count, t.leaf_item0.as<int32_t>(),
+                           t.leaf_nitems.as<int32_t>(), t.nd_first.as<int32_t>(), t.nd_count.as<int32_t>(),
+                           t.it_pbase.as<uint32_t>(), t.partial.as<double>(), t.near3.as<double>(),
+                           (const double*)ppot, npot);
+        TFMM_LAUNCHED();
+    }
 }
 
 }  // namespace

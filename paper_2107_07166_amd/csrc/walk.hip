@@ -637,7 +637,9 @@ __global__ __launch_bounds__(TB) void item_write_kernel(const uint32_t* __restri
                                                         int32_t* __restrict__ it_leaf, uint32_t* __restrict__ it_q0,
                                                         uint32_t* __restrict__ it_q1, uint32_t* __restrict__ it_pbase,
                                                         int32_t* __restrict__ leaf_item0,
-                                                        int32_t* __restrict__ leaf_nitems) {
+                                                        int32_t* __restrict__ leaf_nitems,
+                                                        int32_t* __restrict__ multi_leaf,
+                                                        uint32_t* __restrict__ multi_count) {
     const int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (q >= ne) return;
     const uint32_t L = tgt[q];
@@ -654,6 +656,7 @@ __global__ __launch_bounds__(TB) void item_write_kernel(const uint32_t* __restri
     if (k == 0u) {
         leaf_item0[L] = (int32_t)item0[L];
         leaf_nitems[L] = (int32_t)n;
+        if (n > 1u) multi_leaf[atomicAdd(multi_count, 1u)] = (int32_t)L;
     }
 }
 
@@ -878,7 +881,7 @@ bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
 
 // Device slots of the list-building totals, read back together at the end.
 struct WalkTotals {
-    uint32_t unused0;
+    uint32_t multi;        // leaves split into several near-field items
     uint32_t near_entries; // directed near entries (check of 2 n_near - n_leaves)
     uint32_t items;        // near-field work items
     uint32_t partial;      // partial-sum rows of multi-item leaves
@@ -977,11 +980,14 @@ void walk_lists_begin(Tree& t, double theta, hipStream_t s) {
         t.it_pbase.ensure(ctx, ni * 4);
         t.leaf_item0.ensure(ctx, (size_t)(nn + 1) * 4);
         t.leaf_nitems.ensure(ctx, (size_t)(nn + 1) * 4);
+        t.multi_leaf.ensure(ctx, (size_t)(nn + 1) * 4);
+        t.multi_count = &res->multi;
         hipLaunchKernelGGL(item_write_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
                            (const uint32_t*)P, (const uint32_t*)t.p2p_off.as<uint32_t>(), ne, (const uint32_t*)nit,
                            (const uint32_t*)it0, (const uint32_t*)pbs, t.nd_count.as<int32_t>(),
                            t.it_leaf.as<int32_t>(), t.it_q0.as<uint32_t>(), t.it_q1.as<uint32_t>(),
-                           t.it_pbase.as<uint32_t>(), t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>());
+                           t.it_pbase.as<uint32_t>(), t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>(),
+                           t.multi_leaf.as<int32_t>(), &res->multi);
         TFMM_LAUNCHED();
     }
     t.walk_theta = theta;

@@ -442,3 +442,46 @@ def test_ragged_rebuilds_match_fresh_trees(ctx):
         of, on = oracle.Tree(pos, m, n_leaf=16, theta=0.6).lists()
         assert np.array_equal(_pairset(gf), _pairset(of)) and np.array_equal(_pairset(gn), _pairset(on))
     gt.close()
+
+
+def _split_list_case():
+    """A dense clump of 20000 particles inside a sparse shell of 300: the
+    shell leaves next to the clump are near to most of it, so their near
+    lists hold up to ~2 x 10^4 source particles and are cut into several
+    work items (more than 4096 sources each)."""
+    rng = np.random.default_rng(77)
+    v = rng.normal(size=(20000, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    core = v * (0.01 * rng.random(20000) ** (1 / 3))[:, None]
+    u = rng.normal(size=(300, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    shell = u * rng.uniform(0.02, 0.06, 300)[:, None]
+    pos = np.vstack([core, shell]) + 0.5
+    m = rng.uniform(0.5, 1.5, len(pos)) / len(pos)
+    return pos, m
+
+
+@pytest.mark.parametrize("variant", ["standard", "conserving"])
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("mixed32", TOL_MIXED)])
+def test_split_near_lists(ctx, variant, prec, tol):
+    """Leaves whose near list is cut into several items (partial sums added
+    by the reduction pass) get the oracle's forces, like every other leaf."""
+    pos, m = _split_list_case()
+    ot = oracle.Tree(pos, m, n_leaf=32, theta=0.5)
+    nd = ot.nodes()
+    cnt = np.asarray(nd["count"], dtype=np.int64)
+    near = np.asarray(ot.lists()[1])
+    tot = np.zeros(len(cnt), np.int64)
+    np.add.at(tot, near[:, 0], cnt[near[:, 1]])
+    np.add.at(tot, near[:, 1], np.where(near[:, 0] != near[:, 1], cnt[near[:, 0]], 0))
+    split = np.flatnonzero(tot > 4096)
+    assert len(split) >= 4 and tot.max() > 3 * 4096
+    order = ot.keys()[1]
+    first = np.asarray(nd["first"], dtype=np.int64)
+    in_split = np.concatenate([order[first[L]:first[L] + cnt[L]] for L in split])
+    ref = ot.forces(4, 1e-3, variant)
+    gt = _gpu_tree(ctx, pos, m, 32)
+    f = gt.evaluate(p=4, theta=0.5, eps=1e-3, variant=variant, precision=prec).cpu().numpy()
+    gt.close()
+    assert _erms(f, ref) <= tol
+    assert _erms(f[in_split], ref[in_split]) <= tol
