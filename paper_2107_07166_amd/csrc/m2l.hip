@@ -21,7 +21,18 @@
 namespace tfmm {
 namespace {
 
-constexpr int MB = 256;         // threads per block = 4 waves
+constexpr int MB = 256;         // largest block (4 waves); launches may use fewer
+// Block size of the force M2L launch.  M2L runs beside the near-field kernel
+// (one-wave blocks, most of the device); smaller M2L blocks get a larger share
+// of the compute units.  The conserving far field is the heavier one and
+// finishes with the near field only with one-wave blocks; the standard one
+// already does with four-wave blocks and would only slow the near field.
+#ifndef TFMM_M2L_CONS_MB
+#define TFMM_M2L_CONS_MB 64
+#endif
+#ifndef TFMM_M2L_STD_MB
+#define TFMM_M2L_STD_MB 256
+#endif
 constexpr int LPT = 32;         // lanes per target node
 constexpr int TPW = kWave / LPT;  // target nodes per wavefront
 
@@ -76,7 +87,7 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
     constexpr int NOUT = CONS ? 4 * NC1 : NC;
     // wave index through readfirstlane: the compiler then keeps the target's
     // list bounds in scalar registers
-    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (MB / kWave) + threadIdx.x / kWave));
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     if (wave * TPW >= n_targets) return;
     const int half = lane / LPT, sl = lane % LPT;
@@ -151,7 +162,7 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
     constexpr int NC = E::NC;
     constexpr int NC1 = E::NC1;
     constexpr int NCP = (NC + 3) / 4 * 4;
-    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (MB / kWave) + threadIdx.x / kWave));
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     if (wave * TPW >= n_targets) return;
     const int half = lane / LPT, sl = lane % LPT;
@@ -214,26 +225,27 @@ void launch(Tree& t, double eps2, hipStream_t s) {
     const int64_t nt = t.n_nodes;  // every node; nodes with an empty far list write nothing
     if (nt <= 0) return;
     const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
-    const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, MB));
+    const int mb = VAR == TFMM_STANDARD ? TFMM_M2L_STD_MB : TFMM_M2L_CONS_MB;
+    const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, mb));
     if constexpr (VAR == TFMM_CONSERVING && P >= kConsSplitP) {
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 0, T>), grid, dim3(MB), 0, s, nt,
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 0, T>), grid, dim3(mb), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 1, T>), grid, dim3(MB), 0, s, nt,
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 1, T>), grid, dim3(mb), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 2, T>), grid, dim3(MB), 0, s, nt,
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 2, T>), grid, dim3(mb), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 3, T>), grid, dim3(MB), 0, s, nt,
+        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 3, T>), grid, dim3(mb), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
                            t.loc.as<double>());
         TFMM_LAUNCHED();
     } else {
-        hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), grid, dim3(MB), 0, s, nt,
+        hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), grid, dim3(mb), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W,
                            (int64_t)round_up(c_le(P), 4), eps2, t.loc.as<double>());
         TFMM_LAUNCHED();
