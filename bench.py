@@ -67,30 +67,28 @@ def run_gpu(w, pos, mass, args):
         tree.rebuild(pd, md)
         tree.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision=precision, out=out)
 
-    def timed(variant, precision, steps, warmup):
+    def timed(variant, precision, steps, warmup, phases=None):
         for _ in range(warmup):
             step(variant, precision)
         torch.cuda.synchronize()
+        if phases is not None:
+            tree.set_timing(True)   # HIP events around every phase of the timed steps
         t0 = time.perf_counter()
         for _ in range(steps):
             step(variant, precision)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        dt = (time.perf_counter() - t0) / steps
+        if phases is not None:
+            phases.update(tree.phase_times())   # averages over the timed steps
+            tree.set_timing(False)
+        return dt
 
     res = {}
-    res["t_cons"] = timed("conserving", "mixed32", args.steps, args.warmup)
+    phases = {}
+    res["t_cons"] = timed("conserving", "mixed32", args.steps, args.warmup, phases)
+    res["phases_ms"] = phases
     res["t_std"] = timed("standard", "mixed32", max(3, args.steps // 2), 2)
     res["t_fp64"] = timed("conserving", "fp64", max(3, args.steps // 4), 1)
-
-    # per-phase device times of the timed configuration (events on the same stream)
-    tree.set_timing(True)
-    phases = []
-    for _ in range(max(3, args.steps // 2)):
-        step("conserving", "mixed32")
-        torch.cuda.synchronize()
-        phases.append(tree.phase_times())
-    tree.set_timing(False)
-    res["phases_ms"] = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
     res["info"] = tree.info()
     step("conserving", "mixed32")
     torch.cuda.synchronize()

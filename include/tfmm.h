@@ -202,12 +202,17 @@ int tfmm_tree_destroy(tfmm_tree *tree);
  * needs (for admission control).  Pure host computation. */
 size_t tfmm_footprint_bytes(int64_t n, int p, int n_leaf, int precision);
 
-/* Per-phase device times (milliseconds) of the last tfmm_evaluate_forces on
- * this tree, measured with HIP events on the stream each phase runs on when
- * timing is enabled (tfmm_tree_set_timing): out[0] M2L, [1] P2P, [2] L2L,
- * [3] L2P, [4] moments (moments, M2L and L2L run on the tree's second stream,
- * P2P and L2P on the caller's), [5] whole evaluation (including a walk if one
- * was needed).  Synchronising.  Errors: EINVAL, ESTATE. */
+/* Per-phase device times (milliseconds), averaged over the evaluations
+ * (tfmm_evaluate_forces) run on this tree since timing was last switched on
+ * or off with tfmm_tree_set_timing, which also clears the averages.  Measured
+ * with HIP events on the stream each phase runs on: out[0] M2L, [1] P2P,
+ * [2] L2L, [3] L2P, [4] moments (moments, M2L and L2L run on the tree's second
+ * stream beside P2P, which runs on the caller's; L2P runs on the caller's
+ * stream after the two join), [5] whole evaluation (including a walk if one
+ * was needed).  While timing is on, each evaluation records nine events and
+ * reads the previous evaluation's times (already complete when the tree was
+ * rebuilt in between).  tfmm_tree_phase_times synchronises with the last
+ * timed evaluation.  Errors: EINVAL, ESTATE (no timed evaluation), EDEVICE. */
 int tfmm_tree_set_timing(tfmm_tree *tree, int enable);
 int tfmm_tree_phase_times(tfmm_tree *tree, double *out);
 

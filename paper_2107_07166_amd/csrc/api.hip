@@ -140,6 +140,28 @@ void check_params(const tfmm_params* p) {
 //   s: sources -> frontier passes -> near-list chain -> [join a] -> P2P -> L2P
 // The latency-bound chains hide behind each other; P2P runs after the join,
 // alone on the device.
+// Adds the phase times of the last timed evaluation to the tree's sums.
+// Events: moments [0,1], M2L [7,2], L2L [2,3] on the tree's second stream;
+// P2P [6,4], L2P [8,5] on the caller's stream (8: after the streams join);
+// whole evaluation [0,5].
+void fold_times(Tree& t) {
+    if (!t.ev_pending) return;
+    TFMM_HIP(hipEventSynchronize(t.ev[5]));
+    auto el = [&](int i, int j) {
+        float ms = 0.f;
+        TFMM_HIP(hipEventElapsedTime(&ms, t.ev[i], t.ev[j]));
+        return (double)ms;
+    };
+    t.t_sum[0] += el(7, 2);  // M2L
+    t.t_sum[1] += el(6, 4);  // P2P
+    t.t_sum[2] += el(2, 3);  // L2L
+    t.t_sum[3] += el(8, 5);  // L2P
+    t.t_sum[4] += el(0, 1);  // moments
+    t.t_sum[5] += el(0, 5);  // whole evaluation after the tree build
+    t.t_count += 1;
+    t.ev_pending = false;
+}
+
 void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential, hipStream_t s) {
     const bool need_walk = !t.walk_valid || t.walk_theta != prm->theta;
     // The zeroth-order magnitude realignment (Eq. aaB0) is quadratic in the
@@ -153,6 +175,7 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
         for (auto& e : t.ev) TFMM_HIP(hipEventCreate(&e));
         t.ev_ready = true;
     }
+    if (t.timing) fold_times(t);
     aux_fork(t, s);
     const hipStream_t a = t.aux;
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[0], a));
@@ -173,6 +196,7 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
     run_p2p(t, prm->precision, eps2, potential != nullptr, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[4], s));
     aux_join(t, s);
+    if (t.timing) TFMM_HIP(hipEventRecord(t.ev[8], s));
     run_l2p(t, pe, ve, prm->G, force, s);
     if (potential) {
         // far-field potential from the standard expansion of order p (every
@@ -182,7 +206,7 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
     }
     if (t.timing) {
         TFMM_HIP(hipEventRecord(t.ev[5], s));
-        t.have_times = true;
+        t.ev_pending = true;
     }
 }
 
@@ -454,30 +478,23 @@ size_t tfmm_footprint_bytes(int64_t n, int p, int n_leaf, int precision) {
 
 int tfmm_tree_set_timing(tfmm_tree* tree, int enable) {
     if (!tree) return TFMM_EINVAL;
-    tree->timing = enable != 0;
-    tree->have_times = false;
-    return TFMM_OK;
+    return guarded(tree->ctx, [&] {
+        Tree& t = *tree;
+        if (t.ev_pending) TFMM_HIP(hipEventSynchronize(t.ev[5]));
+        t.timing = enable != 0;
+        t.ev_pending = false;
+        for (double& v : t.t_sum) v = 0.0;
+        t.t_count = 0;
+    });
 }
 
 int tfmm_tree_phase_times(tfmm_tree* tree, double* out) {
     if (!tree || !out) return TFMM_EINVAL;
     return guarded(tree->ctx, [&] {
         Tree& t = *tree;
-        if (!t.have_times) fail(TFMM_ESTATE, "no timed evaluation on this tree");
-        TFMM_HIP(hipEventSynchronize(t.ev[5]));
-        // events: moments [0,1], M2L [7,2], L2L [2,3] on the tree's second
-        // stream; P2P [6,4], L2P [4,5] on the caller's stream
-        auto el = [&](int i, int j) {
-            float ms = 0.f;
-            TFMM_HIP(hipEventElapsedTime(&ms, t.ev[i], t.ev[j]));
-            return (double)ms;
-        };
-        out[0] = el(7, 2);  // M2L
-        out[1] = el(6, 4);  // P2P
-        out[2] = el(2, 3);  // L2L
-        out[3] = el(4, 5);  // L2P
-        out[4] = el(0, 1);  // moments
-        out[5] = el(0, 5);  // whole evaluation after the tree build
+        fold_times(t);
+        if (t.t_count == 0) fail(TFMM_ESTATE, "no timed evaluation on this tree");
+        for (int k = 0; k < 6; ++k) out[k] = t.t_sum[k] / (double)t.t_count;
     });
 }
 

@@ -167,11 +167,15 @@ struct Tree {
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     DevBuf scratch_b, scratch2_b, w_tg_b, w_sr_b;  // the near-list chain's own scratch
 
-    // timing
+    // timing: events of the latest timed evaluation, and the phase times of
+    // the earlier ones added up (taken at the next timed evaluation, when its
+    // events are complete, or when read)
     bool timing = false;
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[9] = {};
     bool ev_ready = false;
-    bool have_times = false;
+    bool ev_pending = false;
+    double t_sum[6] = {};
+    int64_t t_count = 0;
 };
 
 // ---- scans (scan.hip) -----------------------------------------------------

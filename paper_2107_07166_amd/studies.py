@@ -150,15 +150,13 @@ def study_profile(steps: int, n_leaf: int, workload: str = "plummer1m", variant:
     tree = api.Tree(ctx, pd, md, n_leaf=n_leaf)
     f = torch.empty((w.n, 3), dtype=torch.float64, device=pd.device)
     tree.set_timing(True)
-    phases = []
     for _ in range(steps):
         tree.rebuild(pd, md)
         tree.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision="mixed32", out=f)
-        torch.cuda.synchronize()
-        phases.append(tree.phase_times())
+    torch.cuda.synchronize()
     out = {"study": "profile", "workload": workload, "variant": variant, "steps": steps, "n_leaf": n_leaf,
            "tree": tree.info(),
-           "phases_ms_last": phases[-1]}
+           "phases_ms_mean": tree.phase_times()}
     tree.close()
     ctx.close()
     return out

@@ -485,3 +485,30 @@ def test_split_near_lists(ctx, variant, prec, tol):
     gt.close()
     assert _erms(f, ref) <= tol
     assert _erms(f[in_split], ref[in_split]) <= tol
+
+
+def test_phase_timing(ctx):
+    """Phase times are averages over the timed evaluations; timing changes no
+    result, and switching it off clears the averages."""
+    from paper_2107_07166_amd import _lib, api
+    pos, m = plummer(20000, 210707167)
+    gt = _gpu_tree(ctx, pos, m, 16)
+    args = dict(p=4, theta=0.5, eps=1e-3, variant="conserving", precision="mixed32")
+    ref = gt.evaluate(**args).cpu().numpy()
+    with pytest.raises(api.TfmmError) as e:
+        gt.phase_times()
+    assert e.value.status == _lib.ESTATE
+    gt.set_timing(True)
+    for _ in range(3):
+        gt.rebuild(_dev(pos), _dev(m))
+        f = gt.evaluate(**args).cpu().numpy()
+        assert np.array_equal(f, ref)
+    ph = gt.phase_times()
+    assert set(ph) == {"m2l", "p2p", "l2l", "l2p", "moments", "total"}
+    assert all(v > 0 for v in ph.values())
+    assert ph["total"] >= ph["p2p"] and ph["total"] >= ph["m2l"] and ph["total"] >= ph["moments"]
+    gt.set_timing(False)
+    with pytest.raises(api.TfmmError) as e:
+        gt.phase_times()
+    assert e.value.status == _lib.ESTATE
+    gt.close()
