@@ -373,3 +373,42 @@ def test_input_permutation_leaves_forces_unchanged():
     t2 = oracle.Tree(pos[perm], m[perm], n_leaf=16, theta=0.6)
     f2 = t2.forces(4, 1e-3, "conserving")
     np.testing.assert_allclose(f2, f[perm], rtol=1e-13, atol=1e-15 * np.abs(f).max())
+
+
+def test_p2_standard_torque_matches_closed_form():
+    """Eq. total_torque at p = 2.  Two clusters in opposite octants of the
+    root cube are joined by a single far pair; the near forces inside each
+    cluster are exact central pair forces (no torque), and the truncated far
+    forces a_a = -M_B grad phi(R) - M_B Phi x_a (x_a about Z_A, Phi the second
+    derivatives of the softened kernel at R = Z_A - Z_B) leave the net torque
+    tau_i = -eps_ijk Phi_kl (M_B Q_A + M_A Q_B)_jl, with Q the raw second
+    moments about each cluster's centre of mass."""
+    rng = _rng(21)
+    A = rng.normal(size=(30, 3)) * 0.15 + np.array([-1.0, -1.0, -1.0])
+    B = rng.normal(size=(40, 3)) * 0.2 + np.array([1.0, 0.8, 1.1])
+    pos = np.vstack([A, B])
+    m = rng.uniform(0.5, 1.5, len(pos))
+    eps = 0.05
+    t = oracle.Tree(pos, m, n_leaf=64, theta=0.5)
+    far, near = t.lists()
+    assert len(far) == 1 and len(near) == 2
+    F = t.forces(2, eps, "standard")
+    tau = np.cross(pos, F).sum(0)
+    mA, mB = m[:30], m[30:]
+    MA, MB = mA.sum(), mB.sum()
+    ZA = (mA[:, None] * A).sum(0) / MA
+    ZB = (mB[:, None] * B).sum(0) / MB
+    QA = np.einsum("a,ai,aj->ij", mA, A - ZA, A - ZA)
+    QB = np.einsum("a,ai,aj->ij", mB, B - ZB, B - ZB)
+    R = ZA - ZB
+    s = R @ R + eps * eps
+    Phi = np.eye(3) * s ** -1.5 - 3.0 * np.outer(R, R) * s ** -2.5
+    lc = np.zeros((3, 3, 3))
+    lc[0, 1, 2] = lc[1, 2, 0] = lc[2, 0, 1] = 1.0
+    lc[0, 2, 1] = lc[2, 1, 0] = lc[1, 0, 2] = -1.0
+    closed = -np.einsum("ijk,kl,jl->i", lc, Phi, MB * QA + MA * QB)
+    assert np.linalg.norm(closed) > 1e-4
+    assert np.linalg.norm(tau - closed) <= 1e-9 * np.linalg.norm(closed)
+    # the realigned forces of the same tree carry no torque
+    tc = np.cross(pos, t.forces(2, eps, "conserving")).sum(0)
+    assert np.linalg.norm(tc) <= 1e-12 * np.linalg.norm(closed)
