@@ -9,7 +9,7 @@
 // shifts, in one pass):
 //   standard   : L_leaf = sum_A shift(L_A, d_A),  d_A = Z_leaf - Z_A;
 //   conserving : P_leaf = sum_A shift(P_A, d_A),
-//                Q'_e,leaf = sum_A [shift(Q'_e,A, d_A) - d_A,e shift(P_A, d_A)]
+//                Q'_e,leaf = sum_A shift(Q'_e,A - d_A,e P_A, d_A)
 // (the vector field -x_e P(x) + Q'_e(x) re-expanded about the new centre).
 // L2P then evaluates a_e = -sum_j L_{j+e} x^j / j!  or  -x_e P(x) + Q'_e(x)
 // at x = X_a - Z_leaf and writes F_a = G m_a (near + far) in the caller's
@@ -80,14 +80,12 @@ __global__ __launch_bounds__(LB) void l2l_cons_kernel(int64_t n_leaves, const in
             if (part == 0) {
                 E1::shift_std(la, d[0], d[1], d[2], acc);
             } else {
-                E1::shift_std(la + part * NC1, d[0], d[1], d[2], acc);
-                double sp[NC1];
-#pragma unroll
-                for (int k = 0; k < NC1; ++k) sp[k] = 0.0;
-                E1::shift_std(la, d[0], d[1], d[2], sp);
+                // the shift is linear: shift(Q'_e) - d_e shift(P) = shift(Q'_e - d_e P)
                 const double de = d[part - 1];
+                double v[NC1];
 #pragma unroll
-                for (int k = 0; k < NC1; ++k) acc[k] = fma(-de, sp[k], acc[k]);
+                for (int k = 0; k < NC1; ++k) v[k] = fma(-de, la[k], la[part * NC1 + k]);
+                E1::shift_std(v, d[0], d[1], d[2], acc);
             }
         }
     }
