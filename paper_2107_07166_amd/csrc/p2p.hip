@@ -5,7 +5,8 @@
 // One wavefront (= one workgroup) owns one target leaf.  A chunk of nt <= 64
 // target particles is laid out over the lanes as G groups of L lanes, each
 // lane holding R consecutive targets (L = ceil(nt / R), G = floor(64 / L));
-// group g takes every G-th staged source.  R in 1..4 is chosen per chunk to
+// group g takes every G-th staged source (the stage keeps each group's sources
+// contiguous, so its loop count is uniform).  R in 1..4 is chosen per chunk to
 // keep the most lanes busy (R = 1 with G replicas for small leaves, R > 1 for
 // leaves of 33..64 particles), and a staged source is reused for R targets.
 // Source leaves are staged into an LDS chunk already expressed in the target
@@ -80,25 +81,26 @@ __device__ __forceinline__ void chunk_layout(int nt, int& R, int& L, int& G) {
     }
 }
 
-// Interactions of one staged chunk for a lane's R targets: sources g, g + G, ...
+// Interactions of one staged chunk for a lane's R targets: the ng sources its
+// group owns, stored contiguously from src (the loop count is the same for
+// every lane, so the loop runs on scalar registers).
 template <typename T, bool SAFE, bool POT, int R>
-__device__ __forceinline__ void consume(const typename Vec4<T>::type* stage, int g, int G, int cp, const T* tx,
-                                        const T* ty, const T* tz, T eps2, T* sx, T* sy, T* sz, T* sp) {
+__device__ __forceinline__ void consume(const typename Vec4<T>::type* src, int ng, const T* tx, const T* ty,
+                                        const T* tz, T eps2, T* sx, T* sy, T* sz, T* sp) {
     constexpr int U = (R >= 4) ? 1 : 4 / R;
-    const int step = G * U;
-    const int cmain = cp / step * step;
-    int k = g;
-    for (; k < cmain; k += step) {
+    const int nmain = ng / U * U;
+    int i = 0;
+    for (; i < nmain; i += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const typename Vec4<T>::type v = stage[k + u * G];
+            const typename Vec4<T>::type v = src[i + u];
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 interact<T, SAFE, POT>(v, tx[r], ty[r], tz[r], eps2, sx[r], sy[r], sz[r], sp[r]);
         }
     }
-    for (; k < cp; k += G) {
-        const typename Vec4<T>::type v = stage[k];
+    for (; i < ng; ++i) {
+        const typename Vec4<T>::type v = src[i];
 #pragma unroll
         for (int r = 0; r < R; ++r) interact<T, SAFE, POT>(v, tx[r], ty[r], tz[r], eps2, sx[r], sy[r], sz[r], sp[r]);
     }
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                                                     double* __restrict__ near_pot) {
     using V4 = typename Vec4<T>::type;
     constexpr int SPL = CH / kWave;  // staged sources per lane per chunk
-    __shared__ V4 stage[CH + kWave];
+    __shared__ V4 stage[CH + 2 * kWave];
     __shared__ int e_start[kWave];
     __shared__ int e_first[kWave];
     __shared__ double e_off[3][kWave];
@@ -201,30 +203,41 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
 #pragma unroll
                 for (int k = 0; k < SPL; ++k)
                     if (lane + kWave * k < cnt) v[k] = P[idx[k]];
+                // the chunk padded to a multiple of G; group g owns sources
+                // g, g + G, ..., stored contiguously at g * gs (gs odd, so the
+                // groups' reads of one step fall in distinct LDS banks)
+                const int cp = (cnt + G - 1) / G * G;
+                const int ng = __builtin_amdgcn_readfirstlane(cp / G);  // the same on every lane
+                const int gs = ng | 1;
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
-                    if (lane + kWave * k < cnt) {
+                    const int c = lane + kWave * k;
+                    if (c < cnt) {
                         V4 w;
                         w.x = (T)((double)v[k].x + e_off[0][ent[k]]);
                         w.y = (T)((double)v[k].y + e_off[1][ent[k]]);
                         w.z = (T)((double)v[k].z + e_off[2][ent[k]]);
                         w.w = v[k].w;
-                        stage[lane + kWave * k] = w;
+                        const int q = c / G;
+                        stage[(c - q * G) * gs + q] = w;
                     }
                 }
-                // pad to a multiple of G, then run: group g takes g, g+G, ...
-                const int cp = (cnt + G - 1) / G * G;
-                if (cnt + lane < cp) stage[cnt + lane] = pad;
+                if (cnt + lane < cp) {
+                    const int c = cnt + lane;
+                    const int q = c / G;
+                    stage[(c - q * G) * gs + q] = pad;
+                }
                 __syncthreads();
                 T sx[RMAX], sy[RMAX], sz[RMAX], sp[RMAX];
 #pragma unroll
                 for (int r = 0; r < RMAX; ++r) sx[r] = sy[r] = sz[r] = sp[r] = T(0);
                 if (act) {
+                    const V4* src = stage + g * gs;
                     switch (R) {
-                        case 1: consume<T, SAFE, POT, 1>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz, sp); break;
-                        case 2: consume<T, SAFE, POT, 2>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz, sp); break;
-                        case 3: consume<T, SAFE, POT, 3>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz, sp); break;
-                        default: consume<T, SAFE, POT, 4>(stage, g, G, cp, tx, ty, tz, eps2, sx, sy, sz, sp); break;
+                        case 1: consume<T, SAFE, POT, 1>(src, ng, tx, ty, tz, eps2, sx, sy, sz, sp); break;
+                        case 2: consume<T, SAFE, POT, 2>(src, ng, tx, ty, tz, eps2, sx, sy, sz, sp); break;
+                        case 3: consume<T, SAFE, POT, 3>(src, ng, tx, ty, tz, eps2, sx, sy, sz, sp); break;
+                        default: consume<T, SAFE, POT, 4>(src, ng, tx, ty, tz, eps2, sx, sy, sz, sp); break;
                     }
                 }
 #pragma unroll
