@@ -25,6 +25,7 @@ namespace tfmm {
 namespace {
 
 constexpr int CH = 256;   // staged source particles per chunk
+static_assert(CH + kWave <= 1040, "the staging's multiply-shift division needs positions below 1040");
 constexpr int UNR = 4;    // inner-loop unroll
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -209,6 +210,9 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                 const int cp = (cnt + G - 1) / G * G;
                 const int ng = __builtin_amdgcn_readfirstlane(cp / G);  // the same on every lane
                 const int gs = ng | 1;
+                // c / G for c < CH + kWave as (c * gm) >> 16, gm = ceil(2^16 / G): exact
+                // while c * (gm G - 2^16) < 2^16, i.e. for every c below 1040
+                const uint32_t gm = (uint32_t)__builtin_amdgcn_readfirstlane((65536 + G - 1) / G);
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
                     const int c = lane + kWave * k;
@@ -218,13 +222,13 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                         w.y = (T)((double)v[k].y + e_off[1][ent[k]]);
                         w.z = (T)((double)v[k].z + e_off[2][ent[k]]);
                         w.w = v[k].w;
-                        const int q = c / G;
+                        const int q = (int)(((uint32_t)c * gm) >> 16);
                         stage[(c - q * G) * gs + q] = w;
                     }
                 }
                 if (cnt + lane < cp) {
                     const int c = cnt + lane;
-                    const int q = c / G;
+                    const int q = (int)(((uint32_t)c * gm) >> 16);
                     stage[(c - q * G) * gs + q] = pad;
                 }
                 __syncthreads();
