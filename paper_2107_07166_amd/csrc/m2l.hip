@@ -217,8 +217,11 @@ __global__ void zero_f64_kernel(double* __restrict__ p, int64_t n) {
 }
 
 // Orders from which the conserving locals are accumulated one polynomial per
-// launch (the fused kernel would spill its 4 NC1 accumulators).
-constexpr int kConsSplitP = 5;
+// launch.  The fused kernel holds 4 NC1 accumulators: at p = 5 (285 registers,
+// one wave per SIMD) it still beats four launches (2.7 against 3.0 ms on 2^20
+// Plummer particles); at p = 6 (486 registers) it loses (6.3 against 6.1 ms on
+// the 2^22-particle disk).
+constexpr int kConsSplitP = 6;
 
 template <int P, int VAR, typename T>
 void launch(Tree& t, double eps2, hipStream_t s) {

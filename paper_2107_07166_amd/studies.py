@@ -236,6 +236,39 @@ def study_zeroth(n_leaf: int, reps: int) -> dict:
     return {"study": "zeroth", "workload": w.name, "n_leaf": n_leaf, "theta": w.theta, "rows": rows}
 
 
+def study_orders(n_leaf: int, reps: int, orders=(2, 3, 4, 5, 6, 8)) -> dict:
+    """The benchmark workload (Plummer N = 2^20, theta = 0.5, mixed) at several
+    orders p, standard and conserving: time per evaluation (tree and walk
+    kept), the conserving variant's overhead, net torque, and the rms error
+    against the p = 8 conserving FP64 evaluation of the same tree."""
+    w = generators.WORKLOADS["plummer1m"]
+    pos, mass = w.make()
+    ctx = api.Context(0)
+    pd, md = _dev(pos), _dev(mass)
+    t = api.Tree(ctx, pd, md, n_leaf=n_leaf)
+    ref = t.evaluate(p=8, theta=w.theta, eps=w.eps, variant="conserving", precision="fp64").cpu().numpy()
+    out = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
+    rows = {}
+    for p in orders:
+        row = {}
+        for variant in ("standard", "conserving"):
+            t.evaluate(p=p, theta=w.theta, eps=w.eps, variant=variant, precision="mixed32", out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                t.evaluate(p=p, theta=w.theta, eps=w.eps, variant=variant, precision="mixed32", out=out)
+            torch.cuda.synchronize()
+            d = ctx.diagnostics(pd, md, out)
+            row[variant] = {"ms_per_eval": (time.perf_counter() - t0) / reps * 1e3,
+                            "err_vs_p8_fp64": _rel_rms(out.cpu().numpy() - ref, ref),
+                            "net_torque_rel": float(d[19])}
+        row["conserving_overhead"] = row["conserving"]["ms_per_eval"] / row["standard"]["ms_per_eval"] - 1.0
+        rows[str(p)] = row
+    t.close()
+    ctx.close()
+    return {"study": "orders", "workload": w.name, "n_leaf": n_leaf, "theta": w.theta, "rows": rows}
+
+
 def study_copy() -> dict:
     x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     y = torch.empty_like(x)
@@ -249,7 +282,7 @@ def study_copy() -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["binary", "disk", "serve", "profile", "copy", "shapes", "zeroth"])
+    ap.add_argument("study", choices=["binary", "disk", "serve", "profile", "copy", "shapes", "zeroth", "orders"])
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--dt", type=float, default=1e-3)
@@ -275,6 +308,8 @@ def main():
         r = study_shapes(a.n or 4000, (3.6, 4.0, 5.0, 6.0, 8.0, 12.0, 16.0), 210707170)
     elif a.study == "zeroth":
         r = study_zeroth(a.n_leaf, a.reps)
+    elif a.study == "orders":
+        r = study_orders(a.n_leaf, a.reps)
     else:
         r = study_serve(a.requests, a.sessions, a.rate, a.slots, a.budget_gb)
     print(json.dumps(r), flush=True)
