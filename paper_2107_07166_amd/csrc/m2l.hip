@@ -211,11 +211,6 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
     }
 }
 
-__global__ void zero_f64_kernel(double* __restrict__ p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = 0.0;
-}
-
 // Orders from which the conserving locals are accumulated one polynomial per
 // launch.  The fused kernel holds 4 NC1 accumulators: at p = 5 (285 registers,
 // one wave per SIMD) it still beats four launches (2.7 against 3.0 ms on 2^20
@@ -298,9 +293,9 @@ void dispatch_pot(Tree& t, int mom_p, int precision, double eps2, hipStream_t s)
 // moments on the device are of order mom_p >= p.
 void run_m2l_pot(Tree& t, int p, int mom_p, int precision, double eps2, hipStream_t s) {
     const int64_t tot = t.n_nodes * (int64_t)c_le(p);
+    // no clearing: a node's locals are written whole when its far list is not
+    // empty, and the downward pass reads only such nodes
     t.loc_pot.ensure(t.ctx, (size_t)tot * 8);
-    hipLaunchKernelGGL(zero_f64_kernel, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, t.loc_pot.as<double>(), tot);
-    TFMM_LAUNCHED();
     switch (p) {
         case 1: dispatch_pot<1>(t, mom_p, precision, eps2, s); break;
         case 2: dispatch_pot<2>(t, mom_p, precision, eps2, s); break;
@@ -317,9 +312,9 @@ void run_m2l_pot(Tree& t, int p, int mom_p, int precision, double eps2, hipStrea
 void run_m2l(Tree& t, int p, int variant, int precision, double eps2, hipStream_t s) {
     const int nloc = n_local(p, variant);
     const int64_t tot = t.n_nodes * (int64_t)nloc;
+    // no clearing: a node's locals are written whole when its far list is not
+    // empty, and the downward pass reads only such nodes
     t.loc.ensure(t.ctx, (size_t)tot * 8);
-    hipLaunchKernelGGL(zero_f64_kernel, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, t.loc.as<double>(), tot);
-    TFMM_LAUNCHED();
     switch (p) {
         case 1: dispatch_var<1>(t, variant, precision, eps2, s); break;
         case 2: dispatch_var<2>(t, variant, precision, eps2, s); break;
