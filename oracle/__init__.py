@@ -13,7 +13,7 @@ Contents (paper: Korobkin et al., arXiv:2107.07166):
 * ``pair_far`` / ``cluster_far`` -- truncated far-field pair accelerations,
                          standard (gradient of the truncated Eq. taylor) and
                          conserving (Eq. realign with the projection scalar
-                         truncated at degree p-1).
+                         truncated at degree p-1, or at a higher degree K).
 * ``Tree``            -- keys, stable order, octree, centres of mass, r_max
                          (Eq. mac_criterion), mutual walk, and FMM forces on any
                          subset of particles.
@@ -54,8 +54,8 @@ def _load():
     lib = ctypes.CDLL(str(_LIB_PATH))
     lib.orc_direct.argtypes = [_i64, _vp, _vp, _d, _d, _vp, _vp]
     lib.orc_series.argtypes = [_d, _d, _d, _d, _i32, _vp]
-    lib.orc_pair_far.argtypes = [_vp, _vp, _vp, _d, _i32, _d, _i32, _vp, _vp]
-    lib.orc_cluster_far.argtypes = [_i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _d, _i32, _vp, _vp]
+    lib.orc_pair_far.argtypes = [_vp, _vp, _vp, _d, _i32, _i32, _d, _i32, _vp, _vp]
+    lib.orc_cluster_far.argtypes = [_i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _d, _i32, _vp, _vp]
     lib.orc_tree_build.argtypes = [_i64, _vp, _vp, _i64, _d]
     lib.orc_tree_build.restype = _vp
     lib.orc_tree_free.argtypes = [_vp]
@@ -70,7 +70,7 @@ def _load():
     lib.orc_tree_nodes.restype = None
     lib.orc_tree_lists.argtypes = [_vp, _vp, _vp]
     lib.orc_tree_lists.restype = None
-    lib.orc_fmm_forces.argtypes = [_vp, _i32, _d, _d, _i32, _i64, _vp, _vp, _vp]
+    lib.orc_fmm_forces.argtypes = [_vp, _i32, _i32, _d, _d, _i32, _i64, _vp, _vp, _vp]
     lib.orc_diagnostics.argtypes = [_i64, _vp, _vp, _vp, _vp, _vp]
     lib.orc_set_threads.argtypes = [_i32]
     _lib = lib
@@ -115,19 +115,21 @@ def series(c0, c1, c2, alpha, nmax):
     return w
 
 
-def pair_far(R, x, y, mb, p, eps, variant="standard"):
-    """Truncated far-field acceleration (G=1) of a at Z_A+x due to b at Z_B+y."""
+def pair_far(R, x, y, mb, p, eps, variant="standard", scalar_degree=0):
+    """Truncated far-field acceleration (G=1) of a at Z_A+x due to b at Z_B+y.
+
+    scalar_degree: degree K of the conserving projection scalar (0 = p-1)."""
     R, x, y = _f64(R), _f64(x), _f64(y)
     acc = np.empty(3)
     pot = np.empty(1)
-    rc = _load().orc_pair_far(_ptr(R), _ptr(x), _ptr(y), float(mb), int(p), float(eps),
-                              VARIANTS[variant], _ptr(acc), _ptr(pot))
+    rc = _load().orc_pair_far(_ptr(R), _ptr(x), _ptr(y), float(mb), int(p), int(scalar_degree),
+                              float(eps), VARIANTS[variant], _ptr(acc), _ptr(pot))
     if rc:
         raise ValueError("orc_pair_far: bad arguments")
     return acc, float(pot[0])
 
 
-def cluster_far(Xt, ZA, Ys, ms, ZB, p, eps, variant="standard"):
+def cluster_far(Xt, ZA, Ys, ms, ZB, p, eps, variant="standard", scalar_degree=0):
     """Far-field accelerations (G=1) on targets Xt (node centre ZA) from sources Ys, ms (centre ZB)."""
     Xt = _f64(Xt, (-1, 3))
     Ys = _f64(Ys, (-1, 3))
@@ -136,7 +138,7 @@ def cluster_far(Xt, ZA, Ys, ms, ZB, p, eps, variant="standard"):
     acc = np.empty((len(Xt), 3))
     pot = np.empty(len(Xt))
     rc = _load().orc_cluster_far(len(Xt), _ptr(Xt), _ptr(ZA), len(Ys), _ptr(Ys), _ptr(ms),
-                                 _ptr(ZB), int(p), float(eps), VARIANTS[variant],
+                                 _ptr(ZB), int(p), int(scalar_degree), float(eps), VARIANTS[variant],
                                  _ptr(acc), _ptr(pot))
     if rc:
         raise ValueError("orc_cluster_far: bad arguments")
@@ -210,14 +212,17 @@ class Tree:
         _load().orc_tree_lists(self._h, _ptr(m), _ptr(p))
         return m, p
 
-    def forces(self, p, eps, variant="standard", G=1.0, targets=None, with_potential=False):
-        """FMM forces (and optionally potentials) on `targets` (original indices) or all."""
+    def forces(self, p, eps, variant="standard", G=1.0, targets=None, with_potential=False,
+               scalar_degree=0):
+        """FMM forces (and optionally potentials) on `targets` (original indices) or all.
+
+        scalar_degree: degree K of the conserving projection scalar (0 = p-1)."""
         lib = _load()
         tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
         nt = self.n if tg is None else len(tg)
         f = np.empty((nt, 3))
         pot = np.empty(nt) if with_potential else None
-        rc = lib.orc_fmm_forces(self._h, int(p), float(eps), float(G), VARIANTS[variant],
+        rc = lib.orc_fmm_forces(self._h, int(p), int(scalar_degree), float(eps), float(G), VARIANTS[variant],
                                 nt, _ptr(tg), _ptr(f), _ptr(pot))
         if rc:
             raise ValueError(f"orc_fmm_forces failed ({rc})")

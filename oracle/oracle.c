@@ -26,6 +26,14 @@
  *               degree p-1, the force's own degree; this is exactly
  *             = -m_b T_{p-1}[g](R; delta) (R + delta)
  *               which is central and antisymmetric, so pair torques vanish.
+ *   conserving with the scalar kept to a higher degree K > p-1 (Sec. 3.2
+ *               allows more terms of the expansion of the scalar): along
+ *               delta -> t delta the standard force a(t) and u(t) = R + t delta
+ *               are polynomials in t, 1/|u(t)|^2 a power series; the scalar's
+ *               series is their product, summed to t^K at t = 1:
+ *             = (sum_{n<=K} [t^n] (a(t).u(t)) / |u(t)|^2) (R + delta).
+ *               The standard force's own truncation error enters the scalar
+ *               from degree p on, so this is not the order K+1 force.
  *   conserving_r2 (zeroth order only, p = 1): the magnitude of the zeroth-
  *               order acceleration along n_ab (Eq. realign2), with n_ab
  *               expanded to first order in delta / |R| as in Eq.
@@ -156,11 +164,23 @@ int orc_series(double c0, double c1, double c2, double alpha, int nmax, double *
 }
 
 #define ORC_PMAX 8
+#define ORC_KMAX 12 /* largest degree of the conserving projection scalar */
+
+/* Degree of the conserving projection scalar: 0 selects the default p-1;
+ * otherwise p-1 <= K <= ORC_KMAX, conserving variant only.  Returns -1 if
+ * the combination is invalid. */
+static int scalar_degree(int p, int variant, int kdeg)
+{
+    if (kdeg == 0) return p - 1;
+    if (variant != ORC_CONSERVING || kdeg < p - 1 || kdeg > ORC_KMAX) return -1;
+    return kdeg;
+}
 
 /* Truncated far-field acceleration of particle a due to particle b (unit G),
- * R = Z_A - Z_B, d = delta = x_a - y_b.  Optionally the truncated potential
- * -m_b T_p[(.)^(-1/2)] (standard expansion of Eq. taylor). */
-static void pair_far(const double R[3], const double d[3], double mb, int p,
+ * R = Z_A - Z_B, d = delta = x_a - y_b; kdeg = degree of the conserving
+ * projection scalar (already validated, p-1 by default).  Optionally the
+ * truncated potential -m_b T_p[(.)^(-1/2)] (standard expansion of Eq. taylor). */
+static void pair_far(const double R[3], const double d[3], double mb, int p, int kdeg,
                      double eps2, int variant, double acc[3], double *pot)
 {
     double c0 = (R[0] * R[0] + R[1] * R[1] + R[2] * R[2]) + eps2;
@@ -178,6 +198,30 @@ static void pair_far(const double R[3], const double d[3], double mb, int p,
         double rr = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
         double rd = (R[0] * d[0] + R[1] * d[1]) + R[2] * d[2];
         double sc = gam[0] * (1.0 - rd / rr);
+        for (int k = 0; k < 3; ++k) acc[k] = -mb * ((R[k] + d[k]) * sc);
+    } else if (variant == ORC_CONSERVING && kdeg > p - 1) {
+        /* Eq. realign: project the standard pair force a onto u = X_a - Y_b,
+         * the scalar (a . u)/|u|^2 expanded along delta -> t delta (Eqs.
+         * nab-expansion, abnab-expansion) and kept to degree kdeg.
+         * -a(t)/m_b = R sum_{n<=p-1} gam_n t^n + delta sum_{n<=p-2} gam_n t^(n+1);
+         * num = coefficients of (-a(t)/m_b) . (R + t delta), degree <= p+1. */
+        double rr = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
+        double rd = (R[0] * d[0] + R[1] * d[1]) + R[2] * d[2];
+        double num[ORC_PMAX + 2] = {0.0};
+        for (int n = 0; n <= p - 1; ++n) {
+            num[n] += gam[n] * rr;
+            num[n + 1] += gam[n] * rd;
+        }
+        for (int n = 0; n <= p - 2; ++n) {
+            num[n + 1] += gam[n] * rd;
+            num[n + 2] += gam[n] * c2;
+        }
+        /* 1/|u(t)|^2 = (R.R + 2 R.delta t + delta.delta t^2)^(-1), no softening */
+        double h[ORC_KMAX + 1];
+        orc_series(rr, 2.0 * rd, c2, -1.0, kdeg, h);
+        double sc = 0.0;
+        for (int n = 0; n <= kdeg; ++n)
+            for (int j = 0; j <= n && j <= p + 1; ++j) sc += num[j] * h[n - j];
         for (int k = 0; k < 3; ++k) acc[k] = -mb * ((R[k] + d[k]) * sc);
     } else if (variant == ORC_CONSERVING) {
         for (int k = 0; k < 3; ++k) acc[k] = -mb * ((R[k] + d[k]) * t_hi);
@@ -212,11 +256,13 @@ static int pair_near(const double *Xa, const double *Xb, double mb, double eps2,
 
 /* Exported single-pair evaluation (for the pin tests). */
 int orc_pair_far(const double *R, const double *x, const double *y, double mb,
-                 int p, double eps, int variant, double *acc, double *pot)
+                 int p, int kdeg, double eps, int variant, double *acc, double *pot)
 {
     if (p < 1 || p > ORC_PMAX || !R || !x || !y || !acc) return -1;
+    int K = scalar_degree(p, variant, kdeg);
+    if (K < 0) return -1;
     double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
-    pair_far(R, d, mb, p, eps * eps, variant, acc, pot);
+    pair_far(R, d, mb, p, K, eps * eps, variant, acc, pot);
     return 0;
 }
 
@@ -224,10 +270,12 @@ int orc_pair_far(const double *R, const double *x, const double *y, double mb,
  * node with centre ZA, due to ns sources Ys (masses ms) in a node with centre
  * ZB: the sum over b of the truncated pair accelerations. */
 int orc_cluster_far(int64_t nt, const double *Xt, const double *ZA, int64_t ns,
-                    const double *Ys, const double *ms, const double *ZB, int p,
+                    const double *Ys, const double *ms, const double *ZB, int p, int kdeg,
                     double eps, int variant, double *acc, double *pot)
 {
     if (p < 1 || p > ORC_PMAX || nt < 0 || ns < 0) return -1;
+    int K = scalar_degree(p, variant, kdeg);
+    if (K < 0) return -1;
     double R[3] = {ZA[0] - ZB[0], ZA[1] - ZB[1], ZA[2] - ZB[2]};
     double eps2 = eps * eps;
     for (int64_t a = 0; a < nt; ++a) {
@@ -237,7 +285,7 @@ int orc_cluster_far(int64_t nt, const double *Xt, const double *ZA, int64_t ns,
             double y[3] = {Ys[3 * b] - ZB[0], Ys[3 * b + 1] - ZB[1], Ys[3 * b + 2] - ZB[2]};
             double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
             double f[3], ph = 0.0;
-            pair_far(R, d, ms[b], p, eps2, variant, f, pot ? &ph : NULL);
+            pair_far(R, d, ms[b], p, K, eps2, variant, f, pot ? &ph : NULL);
             for (int k = 0; k < 3; ++k) nsum_add(&s[k], f[k]);
             nsum_add(&sp, ph);
         }
@@ -611,12 +659,14 @@ static int build_adjacency(orc_tree *t)
  * gets G times the potential with the far part from the standard Taylor
  * expansion of Eq. taylor.
  */
-int orc_fmm_forces(orc_tree *t, int p, double eps, double G, int variant,
+int orc_fmm_forces(orc_tree *t, int p, int kdeg, double eps, double G, int variant,
                    int64_t n_targets, const int64_t *targets, double *force, double *pot)
 {
     if (!t || p < 1 || p > ORC_PMAX || !(eps >= 0.0) || !force) return -1;
     if (variant != ORC_STANDARD && variant != ORC_CONSERVING && variant != ORC_CONSERVING_R2) return -1;
     if (variant == ORC_CONSERVING_R2 && p != 1) return -1;
+    int K = scalar_degree(p, variant, kdeg);
+    if (K < 0) return -1;
     if (build_adjacency(t)) return -2;
     int64_t nt = targets ? n_targets : t->n;
     int64_t *pos_of = (int64_t *)malloc((size_t)t->n * sizeof(int64_t));
@@ -653,7 +703,7 @@ int orc_fmm_forces(orc_tree *t, int p, double eps, double G, int variant,
                     const double *Yb = &t->X[3 * sb];
                     double y[3] = {Yb[0] - ZB[0], Yb[1] - ZB[1], Yb[2] - ZB[2]};
                     double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
-                    pair_far(R, d, t->m[sb], p, eps2, variant, acc, pot ? &pp : NULL);
+                    pair_far(R, d, t->m[sb], p, K, eps2, variant, acc, pot ? &pp : NULL);
                     for (int dd = 0; dd < 3; ++dd) nsum_add(&f[dd], acc[dd]);
                     if (pot) nsum_add(&ph, pp);
                 }

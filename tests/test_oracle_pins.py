@@ -316,8 +316,14 @@ def test_error_falls_with_order_and_angle(ball2k):
 
 
 def test_realignment_keeps_the_accuracy_order(ball2k):
-    """Sec. 4: realignment leaves the accuracy essentially unaffected; here the
-    conserving/standard error ratio stays bounded at fixed p (p >= 2)."""
+    """On a tree workload the realigned force keeps the standard force's order
+    of accuracy but not its constant: the conserving/standard error ratio at
+    fixed p stays bounded (measured 2.8-5.6 here for p = 1..6).  The paper's
+    statement that accuracy is not affected (Sec. 4) is about its two-body
+    distance test, where the ratio is 0.7-1.1 (pinned in
+    test_oracle_outputs.py).  Its top-order term is a Taylor term of
+    g = |r|^-3, which is not harmonic, so its sum over a source cell lacks the
+    cancellation of the harmonic standard remainder."""
     pos, m, ref = ball2k
     t = oracle.Tree(pos, m, n_leaf=16, theta=0.5)
     for p in (2, 4, 6):
