@@ -207,6 +207,26 @@ def evaluate_forces(pos: torch.Tensor, mass: torch.Tensor, p: int = 4, theta: fl
         t.close()
 
 
+def evaluate_forces_oneshot(pos: torch.Tensor, mass: torch.Tensor, p: int = 4, theta: float = 0.5,
+                            eps: float = 1e-3, variant: str = "conserving", precision: str = "mixed32",
+                            n_leaf: int = 64, G: float = 1.0, ctx: Optional[Context] = None,
+                            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Build, evaluate and destroy a tree in one library call
+    (tfmm_evaluate_forces_oneshot; synchronising)."""
+    ctx = ctx or default_context(pos.device.index or 0)
+    n = int(mass.shape[0])
+    _check_vec(pos, "pos", (n, 3))
+    _check_vec(mass, "mass", (n,))
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    _check_vec(out, "out", (n, 3))
+    prm = Params(int(p), float(theta), float(eps), float(G), VARIANTS[variant], PRECISIONS[precision])
+    ctx.check(ctx.lib.tfmm_evaluate_forces_oneshot(ctx.handle, n, pos.data_ptr(), mass.data_ptr(), int(n_leaf),
+                                                   ctypes.byref(prm), out.data_ptr(),
+                                                   _stream_handle(pos.device)))
+    return out
+
+
 def momentum_diagnostics(pos, mass, force, vel=None, ctx: Optional[Context] = None) -> np.ndarray:
     ctx = ctx or default_context(pos.device.index or 0)
     return ctx.diagnostics(pos, mass, force, vel)
