@@ -1,22 +1,39 @@
 """Benchmark: particle force evaluations per second on one MI355X.
 
-Workload: Plummer sphere, N = 2^20 equal masses (total 1), scale radius 1,
-softening 1e-3, expansion order p = 4, theta = tan(theta_MAC) = 0.5, seeded
-synthetic input resident in HBM.  One step = one full force evaluation of the
-conserving (torque-free) variant in the mixed path: tree rebuild (keys, sort,
-octree, centres of mass, r_max), walk, moments, M2L, L2L, P2P, L2P.
+Headline workload: Plummer sphere, N = 2^20 equal masses (total 1), scale
+radius 1, softening 1e-3, expansion order p = 4, theta = tan(theta_MAC) = 0.5,
+seeded synthetic input resident in HBM.  One step = one full force
+evaluation of the conserving (torque-free) variant in the mixed path: tree
+rebuild (keys, sort, octree, centres of mass, r_max), walk, moments, M2L,
+L2L, P2P, L2P.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line.  Besides the headline value it reports the standard
-variant and the FP64 path at the same workload, per-phase device times
-(HIP events on the library's stream), the roofline of the dominant kernel
-(P2P), and the CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line.  Besides the headline value it reports:
+
+* the standard variant and the FP64 path at the same workload (every variant
+  timed the same way: K steps after W warm-up steps, with the per-phase HIP
+  events of the library on);
+* per-phase device times (rebuild, walk, moments, M2L, P2P, L2L, L2P, the
+  interaction pass where P2P and M2L run side by side);
+* the roofline of the dominant kernel (P2P) and the algorithmic FLOP rate of
+  the whole interaction pass (P2P + M2L);
+* the exponential disk (N = 2^22, p = 6, theta = 0.8): ms per step of both
+  variants and the conserving overhead;
+* a bounded serving run: Poisson-arriving solves of N log-uniform in
+  [1e3, 5e5], p in {2,4,6}, theta in {0.4,0.6,0.8}, plus resident leapfrog
+  sessions; FP32-batched server against FP64 one solve at a time on the same
+  trace: solves/s at capacity, p50/p99 latency at a fixed arrival rate;
+* the two-body setup of the paper's distance test: force error of orders 0
+  and 1 with and without realignment;
+* the CPU oracle timed on a bounded sample of the headline workload.
 """
 
 from __future__ import annotations
 
 import argparse
+import dataclasses
+import importlib.util
 import json
 import os
 import sys
@@ -47,11 +64,43 @@ def _p2p_traffic():
     return P2P_TRAFFIC_BYTES if sha == P2P_TRAFFIC_SOURCE_SHA else None
 
 
+def _m2l_pair_flops(p, variant):
+    """Algorithmic FLOPs per directed far pair, counted in the generated code."""
+    path = os.path.join(ROOT, "paper_2107_07166_amd", "csrc", "gen_expansions.py")
+    spec = importlib.util.spec_from_file_location("gen_expansions", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.pair_flops(p, variant)
+
+
 def _erms(f, ref):
     return float(np.sqrt(np.mean(((f - ref) ** 2).sum(1) / (ref ** 2).sum(1))))
 
 
-def run_gpu(w, pos, mass, args):
+def _timed_steps(tree, pd, md, out, w, variant, precision, steps, warmup):
+    """K timed steps (rebuild + evaluate) after W warm-up steps, with the
+    library's phase events on; returns (seconds per step, phase times)."""
+    import torch
+
+    def step():
+        tree.rebuild(pd, md)
+        tree.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision=precision, out=out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    tree.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ph = tree.phase_times()
+    tree.set_timing(False)
+    return dt, ph
+
+
+def run_headline(w, pos, mass, args):
     import torch
 
     from paper_2107_07166_amd import api
@@ -62,49 +111,110 @@ def run_gpu(w, pos, mass, args):
     ctx = api.Context(0)
     tree = api.Tree(ctx, pd, md, n_leaf=args.n_leaf)
     out = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
-
-    def step(variant, precision):
-        tree.rebuild(pd, md)
-        tree.evaluate(p=w.p, theta=w.theta, eps=w.eps, variant=variant, precision=precision, out=out)
-
-    def timed(variant, precision, steps, warmup, phases=None):
-        for _ in range(warmup):
-            step(variant, precision)
-        torch.cuda.synchronize()
-        if phases is not None:
-            tree.set_timing(True)   # HIP events around every phase of the timed steps
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step(variant, precision)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        if phases is not None:
-            phases.update(tree.phase_times())   # averages over the timed steps
-            tree.set_timing(False)
-        return dt
-
     res = {}
-    phases = {}
-    res["t_cons"] = timed("conserving", "mixed32", args.steps, args.warmup, phases)
-    res["phases_ms"] = phases
-    res["t_std"] = timed("standard", "mixed32", max(3, args.steps // 2), 2)
-    res["t_fp64"] = timed("conserving", "fp64", max(3, args.steps // 4), 1)
-    res["info"] = tree.info()
-    step("conserving", "mixed32")
-    torch.cuda.synchronize()
+    res["t_cons"], res["phases_cons"] = _timed_steps(tree, pd, md, out, w, "conserving", "mixed32",
+                                                     args.steps, args.warmup)
     res["force"] = out.cpu().numpy()
-    step("standard", "mixed32")
-    torch.cuda.synchronize()
+    res["t_std"], res["phases_std"] = _timed_steps(tree, pd, md, out, w, "standard", "mixed32",
+                                                   args.steps, args.warmup)
     res["force_std"] = out.cpu().numpy()
+    res["t_fp64"], res["phases_fp64"] = _timed_steps(tree, pd, md, out, w, "conserving", "fp64",
+                                                     max(3, args.steps // 4), 1)
+    res["info"] = tree.info()
     d = ctx.diagnostics(pd, md, torch.from_numpy(res["force"]).to(dev))
     ds = ctx.diagnostics(pd, md, torch.from_numpy(res["force_std"]).to(dev))
     res["torque_cons"] = float(d[19])
     res["torque_std"] = float(ds[19])
     res["netforce_cons"] = float(d[18])
+    res["netforce_std"] = float(ds[18])
     res["gpu_name"] = torch.cuda.get_device_name(0)
     tree.close()
     ctx.close()
     return res
+
+
+def run_disk(args):
+    """Exponential disk, N = 2^22, p = 6, theta = 0.8: both variants timed the
+    same way; the cost of realignment at a high order and a wide angle."""
+    import torch
+
+    from paper_2107_07166_amd import api
+    from paper_2107_07166_amd.generators import WORKLOADS
+
+    w = WORKLOADS["disk4m"]
+    pos, mass = w.make()
+    dev = torch.device("cuda:0")
+    pd = torch.from_numpy(pos).to(dev)
+    md = torch.from_numpy(mass).to(dev)
+    ctx = api.Context(0)
+    tree = api.Tree(ctx, pd, md, n_leaf=args.n_leaf)
+    out = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
+    res = {"workload": f"disk4m: exponential disk N={w.n}, scale length 1, sech^2 height 0.05, eps=1e-3, "
+                       f"p={w.p}, theta={w.theta}", "n": w.n}
+    for variant in ("standard", "conserving"):
+        dt, ph = _timed_steps(tree, pd, md, out, w, variant, "mixed32", args.disk_steps, 2)
+        d = ctx.diagnostics(pd, md, out)
+        res[variant] = {"ms_per_step": dt * 1e3, "evals_per_s": w.n / dt, "phases_ms": ph,
+                        "net_torque_rel": float(d[19]), "net_force_rel": float(d[18])}
+    res["conserving_overhead"] = res["conserving"]["ms_per_step"] / res["standard"]["ms_per_step"] - 1.0
+    res["conserving_overhead_evaluation"] = (res["conserving"]["phases_ms"]["total"]
+                                             / res["standard"]["phases_ms"]["total"] - 1.0)
+    res["tree"] = tree.info()
+    tree.close()
+    ctx.close()
+    return res
+
+
+def run_serving(args):
+    """A bounded serving run on one trace: capacity (every solve queued at
+    once) and latency at a fixed Poisson rate, FP32-batched against FP64 one
+    solve at a time; resident sessions step beside the solves."""
+    from paper_2107_07166_amd.serve import (Server, close_sessions, make_inputs, make_sessions, make_trace,
+                                            summarize)
+
+    trace = make_trace(args.serve_requests, rate=args.serve_rate)
+    inputs = {r.rid: make_inputs(r) for r in trace}
+    burst = [dataclasses.replace(r, arrival=0.0) for r in trace]
+    servers = (("fp64_one_at_a_time", "fp64", 1), ("mixed32_batched", "mixed32", args.serve_slots))
+    res = {"requests": len(trace), "sessions": args.serve_sessions, "rate_per_s": args.serve_rate,
+           "slots_batched": args.serve_slots,
+           "trace": "Poisson arrivals; N log-uniform in [1e3, 5e5]; ball/Plummer/disk; p in {2,4,6}; "
+                    "theta in {0.4,0.6,0.8}; standard/conserving; eps=1e-3"}
+    samples = {}
+    for name, prec, k in servers:
+        recs = Server(slots=k, precision=prec).run(burst, inputs=inputs)
+        cap = summarize(recs)
+        sessions = make_sessions(args.serve_sessions, precision=prec, n_max=5e4)
+        try:
+            recs = Server(slots=k, precision=prec).run(trace, sessions=sessions, inputs=inputs)
+        finally:
+            close_sessions(sessions)
+        s = summarize(recs)
+        res[name] = {"capacity_solves_per_s": cap["solves_per_s"], "solves_per_s": s["solves_per_s"],
+                     "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "session_steps": s["session_steps"],
+                     "step_p50_ms": s.get("step_p50_ms"), "step_p99_ms": s.get("step_p99_ms"),
+                     "errors": s["errors"]}
+        samples[name] = {r.rid: r.sample for r in recs if r.kind == "solve" and not r.error}
+    a, b = samples["mixed32_batched"], samples["fp64_one_at_a_time"]
+    errs = [_erms(a[i], b[i]) for i in a if i in b]
+    res["mixed_vs_fp64_rms_per_request"] = {"max": max(errs), "median": float(np.median(errs))}
+    res["capacity_ratio"] = (res["mixed32_batched"]["capacity_solves_per_s"]
+                             / res["fp64_one_at_a_time"]["capacity_solves_per_s"])
+    return res
+
+
+def run_distance_test():
+    """Two irregular bodies of 4000 particles at distances 3.6 / 8 / 16 (their
+    radius is 1), each one leaf, theta = 0.99 (one far pair), eps = 0, FP64:
+    rms relative error of the inter-body force for orders 0 and 1 with and
+    without realignment.  The exact force is the library's theta = 0
+    evaluation (exact pair sums; checked against the oracle's direct sum in
+    the GPU tests)."""
+    from paper_2107_07166_amd.studies import study_shapes
+    r = study_shapes(4000, (3.6, 8.0, 16.0), 5)
+    return {"rows": [{k: (v["err"] if isinstance(v, dict) else v) for k, v in row.items()} for row in r["rows"]],
+            "net_torque_rel_max": {lab: max(row[lab]["net_torque_rel"] for row in r["rows"])
+                                   for lab in r["rows"][0] if isinstance(r["rows"][0][lab], dict)}}
 
 
 def cpu_baseline(w, pos, mass, budget_s, n_leaf):
@@ -145,6 +255,12 @@ def main():
     ap.add_argument("--n-leaf", type=int, default=64)
     ap.add_argument("--cpu-budget", type=float, default=18.0, help="seconds of oracle force time")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--disk-steps", type=int, default=8)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-sessions", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-rate", type=float, default=100.0, help="Poisson arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
@@ -155,11 +271,19 @@ def main():
 
     w = WORKLOADS["plummer1m"]
     pos, mass = w.make()
-    g = run_gpu(w, pos, mass, args)
+    g = run_headline(w, pos, mass, args)
+    print(f"# headline done: {g['t_cons'] * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     t = g["t_cons"]
-    n_int = g["info"]["near_interactions"]
-    p2p_ms = g["phases_ms"]["p2p"]
+    info = g["info"]
+    n_int = info["near_interactions"]
+    ph = g["phases_cons"]
+    p2p_ms = ph["p2p"]
     achieved = P2P_FLOP_PER_PAIR * n_int / (p2p_ms * 1e-3) / 1e12
+    m2l_flop = _m2l_pair_flops(w.p, "conserving") * info["far_directed"]
+    inter_tflops = (P2P_FLOP_PER_PAIR * n_int + m2l_flop) / (ph["interaction"] * 1e-3) / 1e12
+    m2l_flop_std = _m2l_pair_flops(w.p, "standard") * info["far_directed"]
+    inter_tflops_std = ((P2P_FLOP_PER_PAIR * n_int + m2l_flop_std)
+                        / (g["phases_std"]["interaction"] * 1e-3) / 1e12)
     line = {
         "metric": "particle force evals/s at N=1M p=4 theta=0.5 (conserving variant, end to end)",
         "value": w.n / t,
@@ -180,15 +304,30 @@ def main():
                      "peak_without_packed_fp32": PEAK_FP32_NOPK_TFLOPS,
                      "flop_per_unit": P2P_FLOP_PER_PAIR, "units_per_launch": n_int,
                      "avg_launch_ms": p2p_ms, "traffic": _p2p_traffic()},
-        "standard_variant": {"value": w.n / g["t_std"], "ms_per_step": g["t_std"] * 1e3},
+        "interaction_pass": {"what": "P2P + M2L algorithmic FLOPs over the window from the first start to "
+                                     "the last end of the two (they run side by side)",
+                             "p2p_flop": P2P_FLOP_PER_PAIR * n_int,
+                             "m2l_flop_per_directed_pair": _m2l_pair_flops(w.p, "conserving"),
+                             "m2l_flop": m2l_flop, "window_ms": ph["interaction"],
+                             "achieved_tflops": inter_tflops, "frac_of_peak": inter_tflops / PEAK_FP32_TFLOPS,
+                             "standard_variant_tflops": inter_tflops_std},
+        "standard_variant": {"value": w.n / g["t_std"], "ms_per_step": g["t_std"] * 1e3,
+                             "phases_ms": g["phases_std"]},
         "conserving_overhead": g["t_cons"] / g["t_std"] - 1.0,
-        "fp64_path": {"value": w.n / g["t_fp64"], "ms_per_step": g["t_fp64"] * 1e3},
-        "phases_ms": g["phases_ms"],
-        "tree": g["info"],
+        "fp64_path": {"value": w.n / g["t_fp64"], "ms_per_step": g["t_fp64"] * 1e3,
+                      "phases_ms": g["phases_fp64"]},
+        "phases_ms": ph,
+        "tree": info,
         "net_torque_rel": {"conserving": g["torque_cons"], "standard": g["torque_std"]},
-        "net_force_rel_conserving": g["netforce_cons"],
+        "net_force_rel": {"conserving": g["netforce_cons"], "standard": g["netforce_std"]},
         "gpu": g["gpu_name"],
     }
+    if not args.no_extra:
+        line["disk"] = run_disk(args)
+        print(f"# disk done: overhead {line['disk']['conserving_overhead']:.3f}", file=sys.stderr, flush=True)
+        line["serving"] = run_serving(args)
+        print("# serving done", file=sys.stderr, flush=True)
+        line["distance_test"] = run_distance_test()
     if not args.no_cpu:
         cb, sample, f_cons, f_std = cpu_baseline(w, pos, mass, args.cpu_budget, args.n_leaf)
         line["cpu_baseline"] = cb

@@ -203,16 +203,23 @@ int tfmm_tree_destroy(tfmm_tree *tree);
 size_t tfmm_footprint_bytes(int64_t n, int p, int n_leaf, int precision);
 
 /* Per-phase device times (milliseconds), averaged over the evaluations
- * (tfmm_evaluate_forces) run on this tree since timing was last switched on
- * or off with tfmm_tree_set_timing, which also clears the averages.  Measured
- * with HIP events on the stream each phase runs on: out[0] M2L, [1] P2P,
- * [2] L2L, [3] L2P, [4] moments (moments, M2L and L2L run on the tree's second
- * stream beside P2P, which runs on the caller's; L2P runs on the caller's
- * stream after the two join), [5] whole evaluation (including a walk if one
- * was needed).  While timing is on, each evaluation records nine events and
- * reads the previous evaluation's times (already complete when the tree was
- * rebuilt in between).  tfmm_tree_phase_times synchronises with the last
- * timed evaluation.  Errors: EINVAL, ESTATE (no timed evaluation), EDEVICE. */
+ * (tfmm_evaluate_forces) and rebuilds (tfmm_tree_rebuild) run on this tree
+ * since timing was last switched on or off with tfmm_tree_set_timing, which
+ * also clears the averages.  Measured with HIP events on the stream each
+ * phase runs on.  out: host, 10 doubles: [0] M2L, [1] P2P, [2] L2L, [3] L2P,
+ * [4] moments (moments, M2L and L2L run on the tree's second stream beside
+ * P2P, which runs on the caller's; L2P runs on the caller's stream after the
+ * two join), [5] whole evaluation (including a walk if one was needed),
+ * [6] rebuild (keys, sort, octree, geometry; 0 if no timed rebuild),
+ * [7] walk (frontier passes and both list chains, averaged over the timed
+ * evaluations that walked; 0 if none), [8] the walk's frontier passes alone,
+ * [9] the interaction pass: from the first start to the last end of P2P and
+ * M2L, which run side by side.
+ * While timing is on, each evaluation records up to eleven events and each
+ * rebuild two; an evaluation reads the previous evaluation's times and a
+ * rebuild the previous rebuild's.  tfmm_tree_phase_times synchronises with
+ * the last timed evaluation and rebuild.  Errors: EINVAL, ESTATE (no timed
+ * evaluation), EDEVICE. */
 int tfmm_tree_set_timing(tfmm_tree *tree, int enable);
 int tfmm_tree_phase_times(tfmm_tree *tree, double *out);
 

@@ -167,9 +167,11 @@ class Tree:
         self.ctx.check(self.ctx.lib.tfmm_tree_set_timing(self.handle, int(bool(enable))))
 
     def phase_times(self) -> dict:
-        a = np.zeros(6)
+        """Average device times (ms) of the timed evaluations and rebuilds."""
+        a = np.zeros(10)
         self.ctx.check(self.ctx.lib.tfmm_tree_phase_times(self.handle, a.ctypes.data_as(ctypes.c_void_p)))
-        return dict(zip(("m2l", "p2p", "l2l", "l2p", "moments", "total"), a.tolist()))
+        return dict(zip(("m2l", "p2p", "l2l", "l2p", "moments", "total", "rebuild", "walk", "walk_passes",
+                         "interaction"), a.tolist()))
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None:

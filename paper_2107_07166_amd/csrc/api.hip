@@ -137,29 +137,59 @@ void check_params(const tfmm_params* p) {
 
 // Two streams: s (the caller's) and the tree's second stream a.
 //   a: moments (during the frontier passes) -> far-list chain -> M2L -> L2L
-//   s: sources -> frontier passes -> near-list chain -> [join a] -> P2P -> L2P
-// The latency-bound chains hide behind each other; P2P runs after the join,
-// alone on the device.
+//   s: sources -> frontier passes -> near-list chain -> P2P -> [join a] -> L2P
+// The latency-bound list chains hide behind each other, and P2P starts as
+// soon as the near lists exist, beside M2L and L2L on the second stream.
 // Adds the phase times of the last timed evaluation to the tree's sums.
 // Events: moments [0,1], M2L [7,2], L2L [2,3] on the tree's second stream;
 // P2P [6,4], L2P [8,5] on the caller's stream (8: after the streams join);
-// whole evaluation [0,5].
+// whole evaluation [0,5]; walk [11, later of 7 and 6], its frontier passes
+// [11,12] (only in evaluations that walked).
+double elapsed_ms(Tree& t, int i, int j) {
+    float ms = 0.f;
+    TFMM_HIP(hipEventElapsedTime(&ms, t.ev[i], t.ev[j]));
+    return (double)ms;
+}
+
 void fold_times(Tree& t) {
     if (!t.ev_pending) return;
     TFMM_HIP(hipEventSynchronize(t.ev[5]));
-    auto el = [&](int i, int j) {
-        float ms = 0.f;
-        TFMM_HIP(hipEventElapsedTime(&ms, t.ev[i], t.ev[j]));
-        return (double)ms;
-    };
-    t.t_sum[0] += el(7, 2);  // M2L
-    t.t_sum[1] += el(6, 4);  // P2P
-    t.t_sum[2] += el(2, 3);  // L2L
-    t.t_sum[3] += el(8, 5);  // L2P
-    t.t_sum[4] += el(0, 1);  // moments
-    t.t_sum[5] += el(0, 5);  // whole evaluation after the tree build
+    t.t_sum[0] += elapsed_ms(t, 7, 2);  // M2L
+    t.t_sum[1] += elapsed_ms(t, 6, 4);  // P2P
+    t.t_sum[2] += elapsed_ms(t, 2, 3);  // L2L
+    t.t_sum[3] += elapsed_ms(t, 8, 5);  // L2P
+    t.t_sum[4] += elapsed_ms(t, 0, 1);  // moments
+    t.t_sum[5] += elapsed_ms(t, 0, 5);  // whole evaluation after the tree build
+    {
+        // the interaction pass: from the first of P2P and M2L to start (6, 7)
+        // until the later of the two ends (4, 2)
+        const int first = elapsed_ms(t, 7, 6) >= 0.0 ? 7 : 6;
+        t.t_sum[9] += std::max(elapsed_ms(t, first, 4), elapsed_ms(t, first, 2));
+    }
+    if (t.ev_walked) {
+        // the far-list chain ends where M2L starts (7), the near-list chain where P2P starts (6)
+        t.t_sum[7] += std::max(elapsed_ms(t, 11, 7), elapsed_ms(t, 11, 6));
+        t.t_sum[8] += elapsed_ms(t, 11, 12);
+        t.t_walks += 1;
+    }
     t.t_count += 1;
     t.ev_pending = false;
+}
+
+// Adds the time of the last timed rebuild to the tree's sums.
+void fold_build(Tree& t) {
+    if (!t.build_pending) return;
+    TFMM_HIP(hipEventSynchronize(t.ev[10]));
+    t.t_sum[6] += elapsed_ms(t, 9, 10);
+    t.t_builds += 1;
+    t.build_pending = false;
+}
+
+void timing_events(Tree& t) {
+    if (t.timing && !t.ev_ready) {
+        for (auto& e : t.ev) TFMM_HIP(hipEventCreate(&e));
+        t.ev_ready = true;
+    }
 }
 
 void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential, hipStream_t s) {
@@ -171,10 +201,7 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
     const int pe = r2 ? 2 : prm->p;
     const int ve = r2 ? TFMM_CONSERVING : prm->variant;
     const double eps2 = prm->softening * prm->softening;
-    if (t.timing && !t.ev_ready) {
-        for (auto& e : t.ev) TFMM_HIP(hipEventCreate(&e));
-        t.ev_ready = true;
-    }
+    timing_events(t);
     if (t.timing) fold_times(t);
     aux_fork(t, s);
     const hipStream_t a = t.aux;
@@ -184,7 +211,8 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
     prepare_sources(t, prm->precision, s);
     if (need_walk) {
         t.walk_valid = false;
-        walk_lists_begin(t, prm->theta, s);
+        if (t.timing) TFMM_HIP(hipEventRecord(t.ev[11], s));
+        walk_lists_begin(t, prm->theta, s, t.timing ? t.ev[12] : nullptr);
     }
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[7], a));
     run_m2l(t, pe, prm->variant, prm->precision, eps2, a);
@@ -207,6 +235,7 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
     if (t.timing) {
         TFMM_HIP(hipEventRecord(t.ev[5], s));
         t.ev_pending = true;
+        t.ev_walked = need_walk;
     }
 }
 
@@ -299,8 +328,19 @@ int tfmm_tree_rebuild(tfmm_tree* tree, int64_t n, const double* pos, const doubl
         if (n < 1 || n > (int64_t)INT32_MAX / 2) fail(TFMM_EINVAL, "n must be in 1..2^30");
         if (!pos || !mass) fail(TFMM_EINVAL, "pos and mass must be device pointers");
         set_device(tree->ctx);
-        tree->n = n;
-        build_tree(*tree, pos, mass, (hipStream_t)stream);
+        Tree& t = *tree;
+        const hipStream_t s = (hipStream_t)stream;
+        timing_events(t);
+        if (t.timing) {
+            fold_build(t);
+            TFMM_HIP(hipEventRecord(t.ev[9], s));
+        }
+        t.n = n;
+        build_tree(t, pos, mass, s);
+        if (t.timing) {
+            TFMM_HIP(hipEventRecord(t.ev[10], s));
+            t.build_pending = true;
+        }
     });
 }
 
@@ -481,10 +521,12 @@ int tfmm_tree_set_timing(tfmm_tree* tree, int enable) {
     return guarded(tree->ctx, [&] {
         Tree& t = *tree;
         if (t.ev_pending) TFMM_HIP(hipEventSynchronize(t.ev[5]));
+        if (t.build_pending) TFMM_HIP(hipEventSynchronize(t.ev[10]));
         t.timing = enable != 0;
         t.ev_pending = false;
+        t.build_pending = false;
         for (double& v : t.t_sum) v = 0.0;
-        t.t_count = 0;
+        t.t_count = t.t_walks = t.t_builds = 0;
     });
 }
 
@@ -493,8 +535,13 @@ int tfmm_tree_phase_times(tfmm_tree* tree, double* out) {
     return guarded(tree->ctx, [&] {
         Tree& t = *tree;
         fold_times(t);
+        fold_build(t);
         if (t.t_count == 0) fail(TFMM_ESTATE, "no timed evaluation on this tree");
         for (int k = 0; k < 6; ++k) out[k] = t.t_sum[k] / (double)t.t_count;
+        out[6] = t.t_builds ? t.t_sum[6] / (double)t.t_builds : 0.0;
+        out[7] = t.t_walks ? t.t_sum[7] / (double)t.t_walks : 0.0;
+        out[8] = t.t_walks ? t.t_sum[8] / (double)t.t_walks : 0.0;
+        out[9] = t.t_sum[9] / (double)t.t_count;
     });
 }
 

@@ -169,13 +169,17 @@ struct Tree {
 
     // timing: events of the latest timed evaluation, and the phase times of
     // the earlier ones added up (taken at the next timed evaluation, when its
-    // events are complete, or when read)
+    // events are complete, or when read).  ev[9], ev[10]: the latest timed
+    // rebuild, folded at the next rebuild or when read; ev[11], ev[12]: the
+    // walk of the latest evaluation (start, end of the frontier passes).
     bool timing = false;
-    hipEvent_t ev[9] = {};
+    hipEvent_t ev[13] = {};
     bool ev_ready = false;
     bool ev_pending = false;
-    double t_sum[6] = {};
-    int64_t t_count = 0;
+    bool ev_walked = false;        // the pending evaluation ran a walk
+    bool build_pending = false;
+    double t_sum[10] = {};
+    int64_t t_count = 0, t_walks = 0, t_builds = 0;
 };
 
 // ---- scans (scan.hip) -----------------------------------------------------
@@ -231,7 +235,9 @@ V read_back_checked(Ctx* ctx, const V* dev, hipStream_t s) {
 // ---- phases ---------------------------------------------------------------
 void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s);
 void walk_tree(Tree& t, double theta, hipStream_t s);
-void walk_lists_begin(Tree& t, double theta, hipStream_t s);
+// passes_done: an event recorded on s once the frontier passes are queued
+// (before the list chains), or nullptr
+void walk_lists_begin(Tree& t, double theta, hipStream_t s, hipEvent_t passes_done = nullptr);
 void walk_lists_end(Tree& t, hipStream_t s);
 void aux_fork(Tree& t, hipStream_t s);
 void aux_join(Tree& t, hipStream_t s);

@@ -350,6 +350,41 @@ def gen_struct(P):
     return out
 
 
+def _count_flops(lines):
+    """Floating-point operations in straight-line generated code: an fma
+    counts 2, every binary +, - and * written with spaces around it counts 1
+    (unary minus and index arithmetic are not counted)."""
+    import re
+    n = 0
+    for ln in lines:
+        body = ln.split("=", 1)[1] if "=" in ln else ln
+        body = re.sub(r"\[[^\]]*\]", "", body)  # index expressions
+        n += 2 * body.count("fma(") + len(re.findall(r" [-+*] ", body))
+    return n
+
+
+def pair_flops(P, variant):
+    """Algorithmic FLOPs of one directed far pair in the M2L kernel at order P:
+    R, s = |R|^2 + eps^2 and one reciprocal square root (10), the radial
+    functions F_1..F_P (2 each), the derivative tensors (generated
+    recurrence) and the contraction with the source moments.  variant:
+    "standard" (phi derivatives, L_j for |j| >= 1) or "conserving" (g
+    derivatives, P and Q'_e)."""
+    body = gen_struct(P)
+    def fn(name):
+        start = next(i for i, l in enumerate(body) if f" {name}(" in l)
+        end = next(i for i in range(start + 1, len(body)) if body[i] == "  }")
+        return body[start + 1:end]
+    prologue = 10 + 2 * P
+    if variant == "standard":
+        lines = fn("phi_derivs") + fn("m2l_std")
+        # the potential term L_0 is not part of the force pass
+        lines = [l for l in lines if "if (WITH_POT)" not in l and not l.strip().startswith("L[0] =")]
+    else:
+        lines = fn("g_derivs") + fn("m2l_cons")
+    return prologue + _count_flops(lines)
+
+
 def main(path=None):
     here = os.path.dirname(os.path.abspath(__file__))
     path = path or os.path.join(here, "expansions_gen.h")

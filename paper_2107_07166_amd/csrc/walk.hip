@@ -910,7 +910,7 @@ void aux_join(Tree& t, hipStream_t s) {
 // The frontier passes on s, then the far-list chain on the tree's second
 // stream (after the passes) and the near-list chain on s.  walk_lists_end
 // reads the totals back once the near chain is done.
-void walk_lists_begin(Tree& t, double theta, hipStream_t s) {
+void walk_lists_begin(Tree& t, double theta, hipStream_t s, hipEvent_t passes_done) {
     Ctx* ctx = t.ctx;
     const int64_t nn = t.n_nodes;
     t.w_geo.ensure(ctx, (size_t)std::max<int64_t>(nn, 1) * sizeof(double4));
@@ -926,6 +926,7 @@ void walk_lists_begin(Tree& t, double theta, hipStream_t s) {
     t.walk_hint_far = t.n_m2l;
     t.walk_hint_near = t.n_p2p;
     const int64_t n_far = t.n_m2l, n_near = t.n_p2p;
+    if (passes_done) TFMM_HIP(hipEventRecord(passes_done, s));
 
     t.w_res.ensure(ctx, sizeof(WalkTotals));
     WalkTotals* res = t.w_res.as<WalkTotals>();

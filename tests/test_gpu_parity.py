@@ -511,9 +511,12 @@ def test_phase_timing(ctx):
         f = gt.evaluate(**args).cpu().numpy()
         assert np.array_equal(f, ref)
     ph = gt.phase_times()
-    assert set(ph) == {"m2l", "p2p", "l2l", "l2p", "moments", "total"}
+    assert set(ph) == {"m2l", "p2p", "l2l", "l2p", "moments", "total", "rebuild", "walk", "walk_passes",
+                       "interaction"}
     assert all(v > 0 for v in ph.values())
+    assert ph["interaction"] >= max(ph["p2p"], ph["m2l"])
     assert ph["total"] >= ph["p2p"] and ph["total"] >= ph["m2l"] and ph["total"] >= ph["moments"]
+    assert ph["total"] >= ph["walk"] >= ph["walk_passes"]
     gt.set_timing(False)
     with pytest.raises(api.TfmmError) as e:
         gt.phase_times()
