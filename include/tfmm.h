@@ -98,6 +98,16 @@ const char *tfmm_last_error(const tfmm_ctx *ctx);
  * context is destroyed); they are not included here. */
 size_t tfmm_ctx_bytes_in_use(const tfmm_ctx *ctx);
 
+/* All device memory the context holds: the buffers counted by
+ * tfmm_ctx_bytes_in_use plus the released blocks it keeps for reuse (the
+ * amount charged against hbm_budget_bytes).  0 for NULL. */
+size_t tfmm_ctx_bytes_held(const tfmm_ctx *ctx);
+
+/* Give every released block the context keeps for reuse back to the device
+ * (tfmm_ctx_bytes_held then equals tfmm_ctx_bytes_in_use).  Synchronises the
+ * device.  Errors: EINVAL (NULL). */
+int tfmm_ctx_trim(tfmm_ctx *ctx);
+
 /* Build the tree for n particles.  pos: device, n x 3 FP64 row-major (x, y, z
  * of particle a at pos[3a..3a+2]); mass: device, n FP64 (> 0).  n_leaf: a
  * node with more than n_leaf particles is split (1..4096).  Keys: 21 bits per

@@ -61,6 +61,14 @@ class Context:
     def bytes_in_use(self) -> int:
         return int(self.lib.tfmm_ctx_bytes_in_use(self.handle))
 
+    def bytes_held(self) -> int:
+        """Device bytes held, including released blocks kept for reuse."""
+        return int(self.lib.tfmm_ctx_bytes_held(self.handle))
+
+    def trim(self) -> None:
+        """Give the released blocks kept for reuse back to the device."""
+        self.check(self.lib.tfmm_ctx_trim(self.handle))
+
     def close(self) -> None:
         if getattr(self, "handle", None) is not None:
             for t in list(self._trees):

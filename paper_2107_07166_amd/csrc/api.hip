@@ -290,6 +290,16 @@ const char* tfmm_last_error(const tfmm_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 size_t tfmm_ctx_bytes_in_use(const tfmm_ctx* ctx) { return ctx ? ctx->used - ctx->cached : 0; }
 
+size_t tfmm_ctx_bytes_held(const tfmm_ctx* ctx) { return ctx ? ctx->used : 0; }
+
+int tfmm_ctx_trim(tfmm_ctx* ctx) {
+    if (!ctx) return TFMM_EINVAL;
+    return guarded(ctx, [&] {
+        set_device(ctx);
+        ctx->trim_cache();
+    });
+}
+
 int tfmm_build_tree(tfmm_ctx* ctx, int64_t n, const double* pos, const double* mass, int n_leaf, void* stream,
                     tfmm_tree** out) {
     if (!ctx) return TFMM_EINVAL;
