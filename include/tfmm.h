@@ -178,6 +178,20 @@ int tfmm_leapfrog(tfmm_tree *tree, const tfmm_params *params, double *pos, doubl
 int tfmm_momentum_diagnostics(tfmm_ctx *ctx, int64_t n, const double *pos, const double *vel,
                               const double *mass, const double *force, void *stream, double *out);
 
+/* tfmm_momentum_diagnostics without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops): the
+ * same kernels and the same 20 values, written asynchronously to out (device,
+ * 20 FP64, caller-owned) on `stream`; no synchronisation, no hipMalloc, no
+ * memset.  The partial sums live in a fixed static device array of 82 KiB per
+ * GPU (set up when the first context is created on that GPU, held until the
+ * process ends) that every call on that GPU shares: calls that overlap on one
+ * GPU (different streams, or different host threads) race and must be
+ * serialised by the caller.  Nothing in it has to start at zero.  Limit:
+ * 1 <= n <= 2^30.  Errors: EINVAL (n out of range, NULL pos, mass, force or
+ * out), EDEVICE. */
+int tfmm_momentum_diagnostics_noalloc(tfmm_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                                      const double *mass, const double *force, double *out, void *stream);
+
 /* Sizes of a tree: out[0] n, [1] nodes, [2] leaves, [3] deepest level,
  * [4] far (M2L) unordered pairs, [5] near (P2P) unordered pairs, [6] directed
  * near particle interactions (sum over directed leaf pairs of n_target *

@@ -46,6 +46,7 @@ SIGNATURES = {
     "tfmm_evaluate_forces_oneshot": (_int, [_vp, _i64, _vp, _vp, _int, ctypes.POINTER(Params), _vp, _vp]),
     "tfmm_leapfrog": (_int, [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _d, _int, _int, _vp]),
     "tfmm_momentum_diagnostics": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tfmm_momentum_diagnostics_noalloc": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tfmm_tree_info": (_int, [_vp, _vp]),
     "tfmm_tree_export": (_int, [_vp] + [_vp] * 12),
     "tfmm_lists_export": (_int, [_vp, _vp, _vp]),

@@ -258,6 +258,7 @@ int tfmm_ctx_create(int device, size_t hbm_budget_bytes, tfmm_ctx** out) {
     c->budget = hbm_budget_bytes;
     const int rc = guarded(c, [&] {
         set_device(c);
+        diag_scratch_init(device);
         c->pinned_bytes = 1 << 16;
         TFMM_HIP(hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault));
         TFMM_HIP(hipMalloc(reinterpret_cast<void**>(&c->dev_err), 256));
@@ -421,6 +422,18 @@ int tfmm_momentum_diagnostics(tfmm_ctx* ctx, int64_t n, const double* pos, const
         if (n < 1 || !pos || !mass || !force || !out) fail(TFMM_EINVAL, "bad diagnostics arguments");
         set_device(ctx);
         run_diagnostics(n, pos, vel, mass, force, out, ctx, (hipStream_t)stream);
+    });
+}
+
+int tfmm_momentum_diagnostics_noalloc(tfmm_ctx* ctx, int64_t n, const double* pos, const double* vel,
+                                      const double* mass, const double* force, double* out, void* stream) {
+    if (!ctx) return TFMM_EINVAL;
+    return guarded(ctx, [&] {
+        if (n < 1 || n > kNoAllocMaxN)
+            fail(TFMM_EINVAL, "n must be in 1..2^30 (the allocation-free diagnostics' limit)");
+        if (!pos || !mass || !force || !out) fail(TFMM_EINVAL, "bad diagnostics arguments");
+        set_device(ctx);
+        run_diagnostics_noalloc(n, pos, vel, mass, force, out, ctx->device, (hipStream_t)stream);
     });
 }
 

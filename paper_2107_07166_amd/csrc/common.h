@@ -252,6 +252,11 @@ void run_l2l(Tree& t, int p, int variant, hipStream_t s);
 void run_l2p(Tree& t, int p, int variant, double G, double* force, hipStream_t s);
 void run_diagnostics(int64_t n, const double* pos, const double* vel, const double* mass,
                      const double* force, double* out_host, Ctx* ctx, hipStream_t s);
+void diag_scratch_init(int device);  // with the device current
+void run_diagnostics_noalloc(int64_t n, const double* pos, const double* vel, const double* mass,
+                             const double* force, double* out_dev, int device, hipStream_t s);
+// largest n of the allocation-free diagnostics (the library's particle limit)
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 30;
 void run_kick(int64_t n, double* vel, const double* force, const double* mass, double h, hipStream_t s);
 void run_drift(int64_t n, double* pos, const double* vel, double dt, hipStream_t s);
 

@@ -2,6 +2,8 @@
 // torque of Eq. total_torque summed over every particle, taken about the
 // system's centre of mass, plus linear and angular momentum.  Fixed grid,
 // fixed per-thread strides and fixed tree reductions: bitwise reproducible.
+#include <mutex>
+
 #include "common.h"
 
 namespace tfmm {
@@ -11,6 +13,20 @@ constexpr int DB = 256;
 constexpr int DG = 512;
 constexpr int N1 = 4;   // m, m x, m y, m z
 constexpr int N2 = 16;  // F(3) |F| rxF(3) |r||F| P(3) L(3)
+// Scratch of one evaluation: per-block partial sums of both passes, the two
+// pass totals, then the 20 output values.
+constexpr int kScratchDoubles = DG * (N1 + N2) + N1 + N2;
+constexpr int kOut = 20;
+
+// Scratch of the allocation-free entry point (tfmm_momentum_diagnostics_noalloc),
+// one copy per GPU, held until the process ends.  Host code never uses this
+// name as an address: the device address of each GPU's copy is looked up once
+// per device with hipGetSymbolAddress (diag_scratch_init) and used instead.
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
 
 template <int NV>
 __device__ void block_reduce(double (&v)[NV], double* sh) {
@@ -86,13 +102,33 @@ __global__ __launch_bounds__(DB) void diag_pass2(int64_t n, const double* __rest
     if (threadIdx.x < N2) part[blockIdx.x * N2 + threadIdx.x] = sh[threadIdx.x * DB];
 }
 
-}  // namespace
+// The 20 output values from the two pass totals (layout of
+// tfmm_momentum_diagnostics).  One thread.
+__global__ void diag_finish(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double M = a[0];  // a: m, mx, my, mz; b: pass 2
+    for (int d = 0; d < 3; ++d) {
+        out[d] = b[d];
+        out[4 + d] = b[4 + d];
+        out[8 + d] = b[8 + d];
+        out[11 + d] = b[11 + d];
+        out[15 + d] = a[1 + d] / M;
+    }
+    out[3] = b[3];
+    out[7] = b[7];
+    out[14] = M;
+    const double fs = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    const double ts = sqrt(b[4] * b[4] + b[5] * b[5] + b[6] * b[6]);
+    out[18] = b[3] > 0 ? fs / b[3] : 0.0;
+    out[19] = b[7] > 0 ? ts / b[7] : 0.0;
+}
 
-void run_diagnostics(int64_t n, const double* pos, const double* vel, const double* mass, const double* force,
-                     double* out, Ctx* ctx, hipStream_t s) {
-    DevBuf buf;
-    buf.ensure(ctx, (size_t)(DG * (N1 + N2) + N1 + N2) * 8);
-    double* p1 = buf.as<double>();
+// Every kernel writes each scratch value it later reads (fixed grid of DG
+// blocks), so nothing has to start at zero.  buf: kScratchDoubles doubles;
+// out: 20 doubles (device).
+void launch_diagnostics(int64_t n, const double* pos, const double* vel, const double* mass, const double* force,
+                        double* buf, double* out, hipStream_t s) {
+    double* p1 = buf;
     double* p2 = p1 + DG * N1;
     double* t1 = p2 + DG * N2;
     double* t2 = t1 + N1;
@@ -104,27 +140,47 @@ void run_diagnostics(int64_t n, const double* pos, const double* vel, const doub
     TFMM_LAUNCHED();
     hipLaunchKernelGGL(diag_final<N2>, dim3(1), dim3(DB), 0, s, (const double*)p2, t2);
     TFMM_LAUNCHED();
-    double h[N1 + N2];
-    TFMM_HIP(hipMemcpyAsync(ctx->pinned, t1, sizeof(h), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(diag_finish, dim3(1), dim3(kWave), 0, s, (const double*)t1, (const double*)t2, out);
+    TFMM_LAUNCHED();
+}
+
+}  // namespace
+
+void run_diagnostics(int64_t n, const double* pos, const double* vel, const double* mass, const double* force,
+                     double* out, Ctx* ctx, hipStream_t s) {
+    DevBuf buf;
+    buf.ensure(ctx, (size_t)(kScratchDoubles + kOut) * 8);
+    double* dev_out = buf.as<double>() + kScratchDoubles;
+    launch_diagnostics(n, pos, vel, mass, force, buf.as<double>(), dev_out, s);
+    TFMM_HIP(hipMemcpyAsync(ctx->pinned, dev_out, kOut * sizeof(double), hipMemcpyDeviceToHost, s));
     TFMM_HIP(hipStreamSynchronize(s));
-    std::memcpy(h, ctx->pinned, sizeof(h));
-    const double* a = h;       // m, mx, my, mz
-    const double* b = h + N1;  // pass 2
-    const double M = a[0];
-    for (int d = 0; d < 3; ++d) {
-        out[d] = b[d];
-        out[4 + d] = b[4 + d];
-        out[8 + d] = b[8 + d];
-        out[11 + d] = b[11 + d];
-        out[15 + d] = a[1 + d] / M;
+    std::memcpy(out, ctx->pinned, kOut * sizeof(double));
+}
+
+// Looks up the device address of this GPU's copy of `scratch` (the device
+// must be current); once per device, at context creation.
+void diag_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) fail(TFMM_EINVAL, "device index beyond the supported 64");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return;
+    void* ptr = nullptr;
+    TFMM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(TFMM_EDEVICE, "hipGetSymbolAddress returned no address for the diagnostics scratch");
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+}
+
+// Allocation-free diagnostics: the same kernels as run_diagnostics on the
+// device's static scratch, results written to out (device, 20 doubles); no
+// synchronisation, no allocation, no memset.
+void run_diagnostics_noalloc(int64_t n, const double* pos, const double* vel, const double* mass,
+                             const double* force, double* out, int device, hipStream_t s) {
+    double* buf = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (device >= 0 && device < kMaxDevices) buf = g_scratch_ptr[device];
     }
-    out[3] = b[3];
-    out[7] = b[7];
-    out[14] = M;
-    const double fs = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-    const double ts = std::sqrt(b[4] * b[4] + b[5] * b[5] + b[6] * b[6]);
-    out[18] = b[3] > 0 ? fs / b[3] : 0.0;
-    out[19] = b[7] > 0 ? ts / b[7] : 0.0;
+    if (!buf) fail(TFMM_ESTATE, "the diagnostics scratch of this device was not set up (no context created on it)");
+    launch_diagnostics(n, pos, vel, mass, force, buf, out, s);
 }
 
 }  // namespace tfmm
