@@ -151,7 +151,8 @@ struct Tree {
     int mom_p = -1;
     DevBuf W32, W64;              // (-1)^|k| M_k / k!, NCP per node (FP32 / FP64 copies)
     DevBuf loc;                   // FP64 M2L locals per node (NLOC per node)
-    DevBuf loc_leaf;              // FP64 gathered locals per leaf
+    DevBuf loc_leaf;              // FP64 gathered locals per leaf (per node when built level by level)
+    DevBuf loc_has;               // uint8 per node: its gathered locals exist (level-by-level pass)
     DevBuf near3;                 // FP64 near-field acceleration (3 per sorted particle)
     DevBuf near_pot, partial_pot; // FP64 near-field potential (per sorted particle / per partial row)
     DevBuf loc_pot, loc_pot_leaf; // FP64 standard locals with L_0 (potential output only)

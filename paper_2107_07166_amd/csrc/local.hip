@@ -3,10 +3,11 @@
 // Taylor expansion from each node's centre of mass to the particle positions.
 //
 // A local expansion is a polynomial about its node's centre, so moving it to
-// a descendant's centre is an exact re-expansion.  Each leaf gathers the M2L
-// results of itself and of all its ancestors, each shifted directly from the
-// ancestor's centre to the leaf's (the composition of the level-by-level
-// shifts, in one pass):
+// a descendant's centre is an exact re-expansion.  Up to p = 4 each leaf
+// gathers the M2L results of itself and of all its ancestors, each shifted
+// directly from the ancestor's centre to the leaf's (the composition of the
+// level-by-level shifts, in one pass); from p = 5 the shifts run level by
+// level (below):
 //   standard   : L_leaf = sum_A shift(L_A, d_A),  d_A = Z_leaf - Z_A;
 //   conserving : P_leaf = sum_A shift(P_A, d_A),
 //                Q'_e,leaf = sum_A shift(Q'_e,A - d_A,e P_A, d_A)
@@ -14,6 +15,8 @@
 // L2P then evaluates a_e = -sum_j L_{j+e} x^j / j!  or  -x_e P(x) + Q'_e(x)
 // at x = X_a - Z_leaf and writes F_a = G m_a (near + far) in the caller's
 // particle order.
+#include <algorithm>
+
 #include "common.h"
 #include "expansions_gen.h"
 
@@ -21,6 +24,15 @@ namespace tfmm {
 namespace {
 
 constexpr int LB = 128;
+
+// Orders whose downward pass runs level by level (each node shifted once, one
+// launch per level) instead of by direct ancestor-to-leaf shifts (one launch,
+// every ancestor shifted once per leaf).  On the 2^22-particle disk at p = 6
+// the level-by-level pass takes 0.19 / 0.43 ms (standard / conserving)
+// against 0.24 / 0.76 ms; on 2^20 Plummer particles at p = 4 it is slower
+// (0.086 / 0.073 against 0.026 / 0.065 ms), the launches outweighing the
+// cheaper shifts.
+constexpr int kL2LByLevelP = 5;
 
 template <int P>
 __global__ __launch_bounds__(LB) void l2l_std_kernel(int64_t n_leaves, const int32_t* __restrict__ leaves,
@@ -92,6 +104,135 @@ __global__ __launch_bounds__(LB) void l2l_cons_kernel(int64_t n_leaves, const in
     double* out = loc_leaf + (int64_t)leaf * NLOC + part * NC1;
 #pragma unroll
     for (int k = 0; k < NC1; ++k) out[k] = acc[k];
+}
+
+// Level-by-level downward pass: a node's local expansion is its own M2L
+// result plus its parent's expansion shifted to its centre, one launch per
+// level (the top levels, at most kTopNodes nodes, in one block).  has[i] is 1
+// when node i or one of its ancestors has a non-empty far list; only such
+// nodes' expansions are written, and every leaf's (zeros if none).  Each node
+// is shifted once, instead of every ancestor once per leaf.
+//   standard   : L_i = L_own + shift(L_parent, d),  d = Z_i - Z_parent;
+//   conserving : P_i = P_own + shift(P_parent, d),
+//                Q'_e,i = Q'_e,own + shift(Q'_e,parent - d_e P_parent, d).
+// Thread (node, part): part 0 only for the standard variant; parts 0..3
+// (P, Q'_x, Q'_y, Q'_z) for the conserving one.
+template <int P, int VAR>
+__device__ __forceinline__ void l2l_node(int32_t i, int part, const int32_t* __restrict__ parent,
+                                         const int32_t* __restrict__ nchild, const double4* __restrict__ Z,
+                                         const uint32_t* __restrict__ m2l_off, const double* __restrict__ loc,
+                                         double* __restrict__ acc_out, uint8_t* __restrict__ has) {
+    constexpr bool CONS = VAR == TFMM_CONSERVING;
+    constexpr int NP = CONS ? Expansion<P>::NC1 : Expansion<P>::NC;  // coefficients per part
+    constexpr int NLOC = CONS ? 4 * NP : NP;
+    const bool own = m2l_off[i + 1] > m2l_off[i];
+    const int32_t par = parent[i];
+    const bool inherit = par >= 0 && has[par] != 0;
+    double* out = acc_out + (int64_t)i * NLOC + part * NP;
+    if (!own && !inherit) {
+        if (part == 0) has[i] = 0;
+        if (nchild[i] == 0) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) out[k] = 0.0;
+        }
+        return;
+    }
+    double acc[NP];
+    if (own) {
+        const double* lo = loc + (int64_t)i * NLOC + part * NP;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) acc[k] = lo[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+    }
+    if (inherit) {
+        const double4 zi = Z[i], zp = Z[par];
+        const double d[3] = {zi.x - zp.x, zi.y - zp.y, zi.z - zp.z};
+        const double* la = acc_out + (int64_t)par * NLOC;
+        if constexpr (!CONS) {
+            Expansion<P>::shift_std(la, d[0], d[1], d[2], acc);
+        } else if constexpr (P == 1) {
+            if (part == 0) acc[0] += la[0];
+            else acc[0] += la[part] - d[part - 1] * la[0];
+        } else {
+            using E1 = Expansion<P - 1>;
+            if (part == 0) {
+                E1::shift_std(la, d[0], d[1], d[2], acc);
+            } else {
+                const double de = d[part - 1];
+                double v[NP];
+#pragma unroll
+                for (int k = 0; k < NP; ++k) v[k] = fma(-de, la[k], la[part * NP + k]);
+                E1::shift_std(v, d[0], d[1], d[2], acc);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) out[k] = acc[k];
+    if (part == 0) has[i] = 1;
+}
+
+template <int P, int VAR>
+__global__ __launch_bounds__(LB) void l2l_level_kernel(int32_t b, int32_t e, const int32_t* __restrict__ parent,
+                                                       const int32_t* __restrict__ nchild,
+                                                       const double4* __restrict__ Z,
+                                                       const uint32_t* __restrict__ m2l_off,
+                                                       const double* __restrict__ loc, double* __restrict__ acc_out,
+                                                       uint8_t* __restrict__ has) {
+    constexpr int PARTS = VAR == TFMM_CONSERVING ? 4 : 1;
+    const int64_t t = (int64_t)blockIdx.x * LB + threadIdx.x;
+    const int64_t i = b + t / PARTS;
+    if (i >= e) return;
+    l2l_node<P, VAR>((int32_t)i, (int)(t % PARTS), parent, nchild, Z, m2l_off, loc, acc_out, has);
+}
+
+struct LevelRange {
+    int32_t b[kLevels + 2];
+};
+
+// The top levels in one block, level after level.
+template <int P, int VAR>
+__global__ __launch_bounds__(LB) void l2l_top_kernel(LevelRange lv, int top, const int32_t* __restrict__ parent,
+                                                     const int32_t* __restrict__ nchild,
+                                                     const double4* __restrict__ Z,
+                                                     const uint32_t* __restrict__ m2l_off,
+                                                     const double* __restrict__ loc, double* __restrict__ acc_out,
+                                                     uint8_t* __restrict__ has) {
+    constexpr int PARTS = VAR == TFMM_CONSERVING ? 4 : 1;
+    for (int L = 0; L <= top; ++L) {
+        const int64_t cnt = (int64_t)(lv.b[L + 1] - lv.b[L]) * PARTS;
+        for (int64_t t = threadIdx.x; t < cnt; t += LB)
+            l2l_node<P, VAR>(lv.b[L] + (int32_t)(t / PARTS), (int)(t % PARTS), parent, nchild, Z, m2l_off, loc,
+                             acc_out, has);
+        __syncthreads();
+    }
+}
+
+template <int P, int VAR>
+void l2l_levels(Tree& t, hipStream_t s) {
+    constexpr int PARTS = VAR == TFMM_CONSERVING ? 4 : 1;
+    constexpr int64_t kTopNodes = LB;
+    t.loc_has.ensure(t.ctx, (size_t)std::max<int64_t>(t.n_nodes, 1));
+    int top = -1;
+    while (top + 1 <= t.max_level && t.level_begin[(size_t)top + 2] <= kTopNodes) ++top;
+    if (top >= 0) {
+        LevelRange lv{};
+        for (int L = 0; L <= top + 1; ++L) lv.b[L] = (int32_t)t.level_begin[L];
+        hipLaunchKernelGGL((l2l_top_kernel<P, VAR>), dim3(1), dim3(LB), 0, s, lv, top, t.nd_parent.as<int32_t>(),
+                           t.nd_nchild.as<int32_t>(), t.nd_Z.as<double4>(), t.m2l_off.as<uint32_t>(),
+                           t.loc.as<double>(), t.loc_leaf.as<double>(), t.loc_has.as<uint8_t>());
+        TFMM_LAUNCHED();
+    }
+    for (int L = top + 1; L <= t.max_level; ++L) {
+        const int32_t b = (int32_t)t.level_begin[L], e = (int32_t)t.level_begin[L + 1];
+        if (e <= b) continue;
+        hipLaunchKernelGGL((l2l_level_kernel<P, VAR>), dim3((unsigned)cdiv((int64_t)(e - b) * PARTS, LB)), dim3(LB),
+                           0, s, b, e, t.nd_parent.as<int32_t>(), t.nd_nchild.as<int32_t>(), t.nd_Z.as<double4>(),
+                           t.m2l_off.as<uint32_t>(), t.loc.as<double>(), t.loc_leaf.as<double>(),
+                           t.loc_has.as<uint8_t>());
+        TFMM_LAUNCHED();
+    }
 }
 
 template <int P, int VAR>
@@ -172,6 +313,11 @@ void potential_down(Tree& t, int precision, double eps2, double G, double* pot, 
 template <int P>
 void l2l_dispatch(Tree& t, int variant, hipStream_t s) {
     const int64_t nl = t.n_leaves;
+    if constexpr (P >= kL2LByLevelP) {
+        if (variant == TFMM_CONSERVING) l2l_levels<P, TFMM_CONSERVING>(t, s);
+        else l2l_levels<P, TFMM_STANDARD>(t, s);
+        return;
+    }
     if (variant == TFMM_CONSERVING)
         hipLaunchKernelGGL(l2l_cons_kernel<P>, dim3((unsigned)cdiv(nl * 4, LB)), dim3(LB), 0, s, nl,
                            t.leaves.as<int32_t>(), t.nd_parent.as<int32_t>(), t.nd_Z.as<double4>(),

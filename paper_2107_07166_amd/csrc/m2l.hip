@@ -148,11 +148,12 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
     }
 }
 
-// Conserving M2L one output polynomial per launch (POLY 0: P, 1..3: Q'_x,y,z)
-// for orders whose four accumulator sets do not fit the registers together:
-// each launch recomputes the g-derivatives of every pair and accumulates one
-// set of NC1 locals, written into its slice of the node's 4 NC1 block.
-template <int P, int POLY, typename T>
+// Conserving M2L for a subset of the output polynomials per launch (bit 0:
+// P, bits 1..3: Q'_x,y,z), for orders whose four accumulator sets do not fit
+// the registers together: every launch recomputes the g-derivatives of its
+// pairs and accumulates popcount(MASK) sets of NC1 locals, each written into
+// its slice of the node's 4 NC1 block.
+template <int P, int MASK, typename T>
 __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
                                                            const uint32_t* __restrict__ off,
                                                            const uint32_t* __restrict__ src, uint32_t src_mask,
@@ -162,6 +163,7 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
     constexpr int NC = E::NC;
     constexpr int NC1 = E::NC1;
     constexpr int NCP = (NC + 3) / 4 * 4;
+    constexpr int NPOLY = (MASK & 1) + ((MASK >> 1) & 1) + ((MASK >> 2) & 1) + ((MASK >> 3) & 1);
     const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     if (wave * TPW >= n_targets) return;
@@ -170,9 +172,9 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
     const bool has = ti < n_targets;
     const int32_t A = (int32_t)(has ? ti : wave * TPW);
     const double4 za = Z[A];
-    T acc[NC1];
+    T acc[NPOLY * NC1];
 #pragma unroll
-    for (int k = 0; k < NC1; ++k) acc[k] = T(0);
+    for (int k = 0; k < NPOLY * NC1; ++k) acc[k] = T(0);
     const uint32_t q0 = has ? off[A] : 0u, q1 = has ? off[A + 1] : 0u;
     for (uint32_t q = q0 + sl; q < q1; q += LPT) {
         const int32_t B = (int32_t)(src[q] & src_mask);
@@ -197,25 +199,36 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
         }
         T G[NC1];
         E::g_derivs(Rx, Ry, Rz, F, G);
-        if constexpr (POLY == 0) E::cons_p(G, w, acc);
-        else if constexpr (POLY == 1) E::cons_qx(G, w, Rx, acc);
-        else if constexpr (POLY == 2) E::cons_qy(G, w, Ry, acc);
-        else E::cons_qz(G, w, Rz, acc);
+        int slot = 0;
+        if constexpr (MASK & 1) E::cons_p(G, w, acc + NC1 * slot++);
+        if constexpr (MASK & 2) E::cons_qx(G, w, Rx, acc + NC1 * slot++);
+        if constexpr (MASK & 4) E::cons_qy(G, w, Ry, acc + NC1 * slot++);
+        if constexpr (MASK & 8) E::cons_qz(G, w, Rz, acc + NC1 * slot++);
     }
 #pragma unroll
-    for (int k = 0; k < NC1; ++k) acc[k] = half_wave_sum_last(acc[k]);
+    for (int k = 0; k < NPOLY * NC1; ++k) acc[k] = half_wave_sum_last(acc[k]);
     if (has && q1 > q0 && sl == LPT - 1) {
-        double* out = loc + (int64_t)A * (4 * NC1) + POLY * NC1;
+        double* out = loc + (int64_t)A * (4 * NC1);
+        int slot = 0;
 #pragma unroll
-        for (int k = 0; k < NC1; ++k) out[k] = (double)acc[k];
+        for (int poly = 0; poly < 4; ++poly) {
+            if (!((MASK >> poly) & 1)) continue;
+#pragma unroll
+            for (int k = 0; k < NC1; ++k) out[poly * NC1 + k] = (double)acc[slot * NC1 + k];
+            ++slot;
+        }
     }
 }
 
-// Orders from which the conserving locals are accumulated one polynomial per
-// launch.  The fused kernel holds 4 NC1 accumulators: at p = 5 (285 registers,
-// one wave per SIMD) it still beats four launches (2.7 against 3.0 ms on 2^20
-// Plummer particles); at p = 6 (486 registers) it loses (6.3 against 6.1 ms on
-// the 2^22-particle disk).
+// From p = 6 the conserving locals are accumulated one polynomial per launch:
+// the four accumulator sets together take 486 registers at p = 6 (one wave
+// per SIMD), one set 129-190 (two to three waves).  On the 2^22-particle disk
+// (p = 6, theta = 0.8) the far field took 4.54 ms in four launches against
+// 4.81 ms in two (P with Q'_x, Q'_y with Q'_z; 264 registers) and 4.97 ms in
+// one; reading the moments where the contraction uses them instead of into
+// registers first was slower in every split.  At p = 5 the fused kernel (285
+// registers) beats four launches (2.7 against 3.0 ms on 2^20 Plummer
+// particles).
 constexpr int kConsSplitP = 6;
 
 template <int P, int VAR, typename T>
@@ -226,22 +239,16 @@ void launch(Tree& t, double eps2, hipStream_t s) {
     const int mb = VAR == TFMM_STANDARD ? TFMM_M2L_STD_MB : TFMM_M2L_CONS_MB;
     const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, mb));
     if constexpr (VAR == TFMM_CONSERVING && P >= kConsSplitP) {
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 0, T>), grid, dim3(mb), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
-                           t.loc.as<double>());
-        TFMM_LAUNCHED();
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 1, T>), grid, dim3(mb), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
-                           t.loc.as<double>());
-        TFMM_LAUNCHED();
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 2, T>), grid, dim3(mb), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
-                           t.loc.as<double>());
-        TFMM_LAUNCHED();
-        hipLaunchKernelGGL((m2l_cons_pass_kernel<P, 3, T>), grid, dim3(mb), 0, s, nt,
-                           t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W, eps2,
-                           t.loc.as<double>());
-        TFMM_LAUNCHED();
+        auto pass = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(mb), 0, s, nt, t.m2l_off.template as<uint32_t>(),
+                               t.m2l_src.template as<uint32_t>(), t.m2l_src_mask, t.nd_Z.template as<double4>(), W,
+                               eps2, t.loc.template as<double>());
+            TFMM_LAUNCHED();
+        };
+        pass(m2l_cons_pass_kernel<P, 0x1, T>);
+        pass(m2l_cons_pass_kernel<P, 0x2, T>);
+        pass(m2l_cons_pass_kernel<P, 0x4, T>);
+        pass(m2l_cons_pass_kernel<P, 0x8, T>);
     } else {
         hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), grid, dim3(mb), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W,
