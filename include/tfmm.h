@@ -76,6 +76,14 @@ typedef struct {
     double G;         /* gravitational constant */
     int variant;      /* tfmm_variant */
     int precision;    /* tfmm_precision */
+    int scalar_degree; /* TFMM_CONSERVING only: degree K of the projection
+                          scalar (a.u)/|u|^2 of Eq. abnab-expansion, which
+                          Sec. 3.2 allows to keep more terms; 0 = the default
+                          p-1; otherwise p-1 <= K <= min(p+1, 6).  The order-p
+                          standard force is realigned (Eq. realign) with the
+                          scalar's Taylor polynomial of degree K in
+                          x_a - y_b: still central, no net torque, closer to
+                          the direct sum; moments and locals of order K+1. */
 } tfmm_params;
 
 /* Create a context on HIP device `device` that may hold at most
@@ -144,8 +152,8 @@ int tfmm_tree_walk(tfmm_tree *tree, double theta, void *stream);
  * and joined back into it before the forces are written, so the call is
  * ordered on `stream` like a single kernel.
  * Errors: EINVAL (p outside 1..8, theta outside [0,1), eps < 0, bad variant
- * or precision, TFMM_CONSERVING_R2 with p != 1, NULL force), ENOMEM,
- * EDEVICE. */
+ * or precision, TFMM_CONSERVING_R2 with p != 1, scalar_degree set for another
+ * variant or outside its range, NULL force), ENOMEM, EDEVICE. */
 int tfmm_evaluate_forces(tfmm_tree *tree, const tfmm_params *params, double *force,
                          double *potential, void *stream);
 

@@ -29,7 +29,8 @@ _sz = ctypes.c_size_t
 
 class Params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("theta", ctypes.c_double), ("softening", ctypes.c_double),
-                ("G", ctypes.c_double), ("variant", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("G", ctypes.c_double), ("variant", ctypes.c_int), ("precision", ctypes.c_int),
+                ("scalar_degree", ctypes.c_int)]
 
 
 SIGNATURES = {

@@ -127,9 +127,11 @@ class Tree:
 
     def evaluate(self, p: int = 4, theta: float = 0.5, eps: float = 1e-3, variant: str = "conserving",
                  precision: str = "mixed32", G: float = 1.0,
-                 out: Optional[torch.Tensor] = None, pot: Optional[torch.Tensor] = None) -> torch.Tensor:
+                 out: Optional[torch.Tensor] = None, pot: Optional[torch.Tensor] = None,
+                 scalar_degree: int = 0) -> torch.Tensor:
         """Forces into `out` (n x 3); if `pot` (n) is given, also G times the
-        potential at every particle (standard expansion for the far field)."""
+        potential at every particle (standard expansion for the far field).
+        scalar_degree: degree of the conserving projection scalar (0 = p - 1)."""
         if out is None:
             out = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
         _check_vec(out, "out", (self.n, 3))
@@ -137,7 +139,8 @@ class Tree:
         if pot is not None:
             _check_vec(pot, "pot", (self.n,))
             pot_ptr = pot.data_ptr()
-        prm = Params(int(p), float(theta), float(eps), float(G), VARIANTS[variant], PRECISIONS[precision])
+        prm = Params(int(p), float(theta), float(eps), float(G), VARIANTS[variant], PRECISIONS[precision],
+                     int(scalar_degree))
         self.ctx.check(self.ctx.lib.tfmm_evaluate_forces(self.handle, ctypes.byref(prm), out.data_ptr(), pot_ptr,
                                                          _stream_handle(self.device)))
         return out

@@ -133,6 +133,17 @@ void check_params(const tfmm_params* p) {
     if (p->variant == TFMM_CONSERVING_R2 && p->p != 1)
         fail(TFMM_EINVAL, "the conserving_r2 variant is zeroth order: p must be 1");
     if (p->precision != TFMM_FP64 && p->precision != TFMM_MIXED32) fail(TFMM_EINVAL, "unknown precision");
+    if (p->scalar_degree != 0) {
+        if (p->variant != TFMM_CONSERVING)
+            fail(TFMM_EINVAL, "scalar_degree applies to the conserving variant only");
+        if (p->scalar_degree < p->p - 1 || p->scalar_degree > std::min(p->p + 1, kKnobMaxK))
+            fail(TFMM_EINVAL, "scalar_degree must satisfy p-1 <= K <= min(p+1, 6)");
+    }
+}
+
+// Degree of the conserving projection scalar (p - 1 unless raised).
+int scalar_degree(const tfmm_params* p) {
+    return p->scalar_degree == 0 ? p->p - 1 : p->scalar_degree;
 }
 
 // Two streams: s (the caller's) and the tree's second stream a.
@@ -198,7 +209,11 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
     // target offset and needs the node quadrupoles: it runs through the
     // conserving locals (P, Q') of order 2, with its own M2L.
     const bool r2 = prm->variant == TFMM_CONSERVING_R2;
-    const int pe = r2 ? 2 : prm->p;
+    // A conserving projection scalar kept to degree K > p - 1 needs moments and
+    // locals of order K + 1.
+    const int kdeg = scalar_degree(prm);
+    const bool knob = prm->variant == TFMM_CONSERVING && kdeg > prm->p - 1;
+    const int pe = r2 ? 2 : (knob ? kdeg + 1 : prm->p);
     const int ve = r2 ? TFMM_CONSERVING : prm->variant;
     const double eps2 = prm->softening * prm->softening;
     timing_events(t);
@@ -215,7 +230,7 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
         walk_lists_begin(t, prm->theta, s, t.timing ? t.ev[12] : nullptr);
     }
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[7], a));
-    run_m2l(t, pe, prm->variant, prm->precision, eps2, a);
+    run_m2l(t, knob ? prm->p : pe, prm->variant, prm->precision, eps2, a, knob ? kdeg : -1);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[2], a));
     run_l2l(t, pe, ve, a);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[3], a));

@@ -350,6 +350,76 @@ def gen_struct(P):
     return out
 
 
+KNOB_MAX_K = 6  # largest scalar degree K on the GPU (moments to order K + 1 <= 7)
+
+
+def knob_pairs():
+    """(p, K) pairs of the scalar-degree knob built for the GPU: p - 1 < K <= p + 1, K <= KNOB_MAX_K."""
+    return [(ps, k) for ps in range(1, PMAX + 1) for k in range(ps, ps + 2) if k <= KNOB_MAX_K]
+
+
+def gen_knob(PS, K):
+    """The projection scalar of the conserving force kept to degree K > PS - 1
+    (order-PS standard force realigned, Eq. realign, scalar expanded as in
+    Eq. abnab-expansion), as a derivative tensor S_k, |k| <= K, for the
+    conserving M2L contraction of order K + 1:
+        S(delta) = T_{PS-1}[g](delta) - G_{PS-1}(delta) W_{K-PS+1}(delta),
+    with G_{PS-1} the degree-(PS-1) part of g(R + delta) and W_m the Taylor
+    polynomial of degree m of w(delta) = (u.delta)/|u|^2 = 1 - (R.u)/|u|^2,
+    u = R + delta (no softening in the projection).  So S_k = G_k for
+    |k| <= PS - 1, and for PS <= |k| <= K
+        S_k = -k! sum_{a + b = k, |a| = PS - 1, |b| >= 1} (G_a / a!) (w_b / b!),
+    w_b = -(R.R h_b + sum_d b_d R_d h_{b - e_d}), h_b the derivatives of
+    h(u) = 1/|u|^2 at R (radial recurrence with F'_0 = 1/R.R,
+    F'_{n+1} = -2 (n+1) F'_n / R.R)."""
+    m = K - PS + 1
+    out = [f"template <> struct Knob<{PS}, {K}> {{",
+           f"  static constexpr int NS = {c_le(K)};",
+           "  template <typename T>",
+           "  __device__ __forceinline__ static void scalar(T Rx, T Ry, T Rz, const T* G, T* S) {",
+           "    const T rr = Rx * Rx + Ry * Ry + Rz * Rz;",
+           "    const T irr = T(1) / rr;",
+           f"    T H[{m + 1}];",
+           "    H[0] = irr;"]
+    for n in range(1, m + 1):
+        out.append(f"    H[{n}] = {fmt(-2 * n)} * H[{n - 1}] * irr;")
+    lines, name = gen_layers(m, 0)
+    out += ["    " + l.replace("F[", "H[") for l in lines]
+    for k in all_upto(PS - 1):
+        out.append(f"    S[{idx(k)}] = G[{idx(k)}];")
+    # w_b, 1 <= |b| <= m
+    wname = {}
+    for b in all_upto(m):
+        if sum(b) == 0:
+            continue
+        terms = [f"rr * {name[(0, b)]}"]
+        for d in range(3):
+            if b[d] > 0:
+                bm = list(b)
+                bm[d] -= 1
+                c = f"{fmt(b[d])} * " if b[d] > 1 else ""
+                terms.append(f"{c}R{AX[d]} * {name[(0, tuple(bm))]}")
+        v = f"w_{idx(b)}"
+        wname[b] = v
+        out.append(f"    const T {v} = -({' + '.join(terms)});")
+    import math
+    def fact(k):
+        return math.factorial(k[0]) * math.factorial(k[1]) * math.factorial(k[2])
+    for n in range(PS, K + 1):
+        for k in multi(n):
+            terms = []
+            for a in multi(PS - 1):
+                b = (k[0] - a[0], k[1] - a[1], k[2] - a[2])
+                if min(b) < 0 or sum(b) < 1:
+                    continue
+                c = -fact(k) / (fact(a) * fact(b))
+                terms.append(f"{fmt(c)} * (G[{idx(a)}] * {wname[b]})")
+            out.append(f"    S[{idx(k)}] = {' + '.join(terms)};")
+    out.append("  }")
+    out.append("};")
+    return out
+
+
 def _count_flops(lines):
     """Floating-point operations in straight-line generated code: an fma
     counts 2, every binary +, - and * written with spaces around it counts 1
@@ -398,6 +468,12 @@ def main(path=None):
              ""]
     for P in range(1, PMAX + 1):
         lines += gen_struct(P)
+        lines.append("")
+    lines.append("// The conserving projection scalar kept to degree K above the default")
+    lines.append("// (see gen_knob in the generator).")
+    lines.append("template <int PS, int K> struct Knob;")
+    for ps, k in knob_pairs():
+        lines += gen_knob(ps, k)
         lines.append("")
     lines.append("}  // namespace tfmm")
     text = "\n".join(lines) + "\n"

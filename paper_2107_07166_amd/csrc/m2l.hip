@@ -153,7 +153,10 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
 // the registers together: every launch recomputes the g-derivatives of its
 // pairs and accumulates popcount(MASK) sets of NC1 locals, each written into
 // its slice of the node's 4 NC1 block.
-template <int P, int MASK, typename T>
+// PS: order of the realigned standard force.  PS == P is the conserving
+// variant of order P; PS < P keeps its projection scalar to degree P - 1
+// (Knob<PS, P - 1>), with moments and locals of order P.
+template <int P, int PS, int MASK, typename T>
 __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
                                                            const uint32_t* __restrict__ off,
                                                            const uint32_t* __restrict__ src, uint32_t src_mask,
@@ -198,7 +201,13 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
             w[4 * k + 3] = v.w;
         }
         T G[NC1];
-        E::g_derivs(Rx, Ry, Rz, F, G);
+        if constexpr (PS == P) {
+            E::g_derivs(Rx, Ry, Rz, F, G);
+        } else {
+            T G0[Expansion<PS>::NC1];
+            Expansion<PS>::g_derivs(Rx, Ry, Rz, F, G0);
+            Knob<PS, P - 1>::scalar(Rx, Ry, Rz, G0, G);
+        }
         int slot = 0;
         if constexpr (MASK & 1) E::cons_p(G, w, acc + NC1 * slot++);
         if constexpr (MASK & 2) E::cons_qx(G, w, Rx, acc + NC1 * slot++);
@@ -245,16 +254,49 @@ void launch(Tree& t, double eps2, hipStream_t s) {
                                eps2, t.loc.template as<double>());
             TFMM_LAUNCHED();
         };
-        pass(m2l_cons_pass_kernel<P, 0x1, T>);
-        pass(m2l_cons_pass_kernel<P, 0x2, T>);
-        pass(m2l_cons_pass_kernel<P, 0x4, T>);
-        pass(m2l_cons_pass_kernel<P, 0x8, T>);
+        pass(m2l_cons_pass_kernel<P, P, 0x1, T>);
+        pass(m2l_cons_pass_kernel<P, P, 0x2, T>);
+        pass(m2l_cons_pass_kernel<P, P, 0x4, T>);
+        pass(m2l_cons_pass_kernel<P, P, 0x8, T>);
     } else {
         hipLaunchKernelGGL((m2l_kernel<P, VAR, T>), grid, dim3(mb), 0, s, nt,
                            t.m2l_off.as<uint32_t>(), t.m2l_src.as<uint32_t>(), t.m2l_src_mask, t.nd_Z.as<double4>(), W,
                            (int64_t)round_up(c_le(P), 4), eps2, t.loc.as<double>());
         TFMM_LAUNCHED();
     }
+}
+
+// The conserving far field of force order PS with the projection scalar kept
+// to degree K > PS - 1: locals of order K + 1 (split by polynomial from order
+// kConsSplitP, like the conserving variant).
+template <int PS, int K, typename T>
+void launch_knob(Tree& t, double eps2, hipStream_t s) {
+    constexpr int P = K + 1;
+    const int64_t nt = t.n_nodes;
+    if (nt <= 0) return;
+    const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
+    const int mb = TFMM_M2L_CONS_MB;
+    const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, mb));
+    auto pass = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(mb), 0, s, nt, t.m2l_off.template as<uint32_t>(),
+                           t.m2l_src.template as<uint32_t>(), t.m2l_src_mask, t.nd_Z.template as<double4>(), W, eps2,
+                           t.loc.template as<double>());
+        TFMM_LAUNCHED();
+    };
+    if constexpr (P >= kConsSplitP) {
+        pass(m2l_cons_pass_kernel<P, PS, 0x1, T>);
+        pass(m2l_cons_pass_kernel<P, PS, 0x2, T>);
+        pass(m2l_cons_pass_kernel<P, PS, 0x4, T>);
+        pass(m2l_cons_pass_kernel<P, PS, 0x8, T>);
+    } else {
+        pass(m2l_cons_pass_kernel<P, PS, 0xF, T>);
+    }
+}
+
+template <int PS, int K>
+void dispatch_knob(Tree& t, int precision, double eps2, hipStream_t s) {
+    if (precision == TFMM_MIXED32) launch_knob<PS, K, float>(t, eps2, s);
+    else launch_knob<PS, K, double>(t, eps2, s);
 }
 
 template <int P>
@@ -316,12 +358,30 @@ void run_m2l_pot(Tree& t, int p, int mom_p, int precision, double eps2, hipStrea
     }
 }
 
-void run_m2l(Tree& t, int p, int variant, int precision, double eps2, hipStream_t s) {
-    const int nloc = n_local(p, variant);
+void run_m2l(Tree& t, int p, int variant, int precision, double eps2, hipStream_t s, int kdeg) {
+    const bool knob = variant == TFMM_CONSERVING && kdeg > p - 1;
+    const int nloc = knob ? n_local(kdeg + 1, variant) : n_local(p, variant);
     const int64_t tot = t.n_nodes * (int64_t)nloc;
     // no clearing: a node's locals are written whole when its far list is not
     // empty, and the downward pass reads only such nodes
     t.loc.ensure(t.ctx, (size_t)tot * 8);
+    if (knob) {
+        switch (p * 16 + kdeg) {
+            case 1 * 16 + 1: dispatch_knob<1, 1>(t, precision, eps2, s); break;
+            case 1 * 16 + 2: dispatch_knob<1, 2>(t, precision, eps2, s); break;
+            case 2 * 16 + 2: dispatch_knob<2, 2>(t, precision, eps2, s); break;
+            case 2 * 16 + 3: dispatch_knob<2, 3>(t, precision, eps2, s); break;
+            case 3 * 16 + 3: dispatch_knob<3, 3>(t, precision, eps2, s); break;
+            case 3 * 16 + 4: dispatch_knob<3, 4>(t, precision, eps2, s); break;
+            case 4 * 16 + 4: dispatch_knob<4, 4>(t, precision, eps2, s); break;
+            case 4 * 16 + 5: dispatch_knob<4, 5>(t, precision, eps2, s); break;
+            case 5 * 16 + 5: dispatch_knob<5, 5>(t, precision, eps2, s); break;
+            case 5 * 16 + 6: dispatch_knob<5, 6>(t, precision, eps2, s); break;
+            case 6 * 16 + 6: dispatch_knob<6, 6>(t, precision, eps2, s); break;
+            default: fail(TFMM_EINVAL, "scalar_degree must satisfy p-1 <= K <= min(p+1, 6)");
+        }
+        return;
+    }
     switch (p) {
         case 1: dispatch_var<1>(t, variant, precision, eps2, s); break;
         case 2: dispatch_var<2>(t, variant, precision, eps2, s); break;

@@ -26,6 +26,10 @@
         their radius), each body one leaf, theta = 0.99: error of the inter-body
         force for orders 0 and 1 with and without realignment (both
         realignments at order 0), net force and torque (FP64, eps = 0).
+    python -m paper_2107_07166_amd.studies knob [--n-leaf 64] [--reps 5]
+        The benchmark workload with the conserving projection scalar kept to
+        degree K = p-1, p, p+1 (p = 2, 4, 5): time per evaluation, error
+        against the p = 8 standard FP64 evaluation, net torque.
     python -m paper_2107_07166_amd.studies zeroth [--n-leaf 64] [--reps 5]
         The benchmark workload at orders 0 and 1 with and without
         realignment: time per evaluation, net torque, error against p = 4.
@@ -269,6 +273,38 @@ def study_orders(n_leaf: int, reps: int, orders=(2, 3, 4, 5, 6, 8)) -> dict:
     return {"study": "orders", "workload": w.name, "n_leaf": n_leaf, "theta": w.theta, "rows": rows}
 
 
+def study_knob(n_leaf: int, reps: int) -> dict:
+    """The benchmark workload (Plummer N = 2^20, theta = 0.5, mixed) with the
+    conserving projection scalar kept to degree K = p - 1, p, p + 1 for
+    p = 2, 4, 5: time per evaluation (tree and walk kept), rms error against
+    the p = 8 standard FP64 evaluation, net torque; the standard variant of
+    the same p beside it."""
+    w = generators.WORKLOADS["plummer1m"]
+    pos, mass = w.make()
+    pd, md = _dev(pos), _dev(mass)
+    ctx = api.Context(0)
+    tree = api.Tree(ctx, pd, md, n_leaf=n_leaf)
+    ref = tree.evaluate(p=8, theta=w.theta, eps=w.eps, variant="standard", precision="fp64").cpu().numpy()
+    rows = []
+    for p in (2, 4, 5):
+        cases = [("standard", 0)] + [("conserving", k) for k in range(p - 1, min(p + 1, 6) + 1)]
+        for variant, k in cases:
+            kw = dict(p=p, theta=w.theta, eps=w.eps, variant=variant, precision="mixed32", scalar_degree=k)
+            f = tree.evaluate(**kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                tree.evaluate(out=f, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            d = ctx.diagnostics(pd, md, f)
+            rows.append({"p": p, "variant": variant, "K": k if variant == "conserving" else None, "ms": ms,
+                         "err_vs_p8": _rel_rms(f.cpu().numpy() - ref, ref), "net_torque_rel": float(d[19])})
+    tree.close()
+    ctx.close()
+    return {"study": "knob", "workload": "plummer1m", "n_leaf": n_leaf, "rows": rows}
+
+
 def study_copy() -> dict:
     x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     y = torch.empty_like(x)
@@ -282,7 +318,8 @@ def study_copy() -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["binary", "disk", "serve", "profile", "copy", "shapes", "zeroth", "orders"])
+    ap.add_argument("study", choices=["binary", "disk", "serve", "profile", "copy", "shapes", "zeroth", "orders",
+                                      "knob"])
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--dt", type=float, default=1e-3)
@@ -310,6 +347,8 @@ def main():
         r = study_zeroth(a.n_leaf, a.reps)
     elif a.study == "orders":
         r = study_orders(a.n_leaf, a.reps)
+    elif a.study == "knob":
+        r = study_knob(a.n_leaf, a.reps)
     else:
         r = study_serve(a.requests, a.sessions, a.rate, a.slots, a.budget_gb)
     print(json.dumps(r), flush=True)
