@@ -111,6 +111,13 @@ size_t tfmm_ctx_bytes_in_use(const tfmm_ctx *ctx);
  * amount charged against hbm_budget_bytes).  0 for NULL. */
 size_t tfmm_ctx_bytes_held(const tfmm_ctx *ctx);
 
+/* Change the context's device-memory budget (0 = no limit) for later
+ * allocations; released blocks kept for reuse are given back first if the
+ * context holds more than the new budget.  Memory already in use by trees is
+ * not touched (later growth beyond the budget fails with ENOMEM).  Errors:
+ * EINVAL (NULL), EDEVICE. */
+int tfmm_ctx_set_budget(tfmm_ctx *ctx, size_t hbm_budget_bytes);
+
 /* Give every released block the context keeps for reuse back to the device
  * (tfmm_ctx_bytes_held then equals tfmm_ctx_bytes_in_use).  Synchronises the
  * device.  Errors: EINVAL (NULL). */

@@ -40,6 +40,7 @@ SIGNATURES = {
     "tfmm_ctx_bytes_in_use": (_sz, [_vp]),
     "tfmm_ctx_bytes_held": (_sz, [_vp]),
     "tfmm_ctx_trim": (_int, [_vp]),
+    "tfmm_ctx_set_budget": (_int, [_vp, _sz]),
     "tfmm_build_tree": (_int, [_vp, _i64, _vp, _vp, _int, _vp, ctypes.POINTER(_vp)]),
     "tfmm_tree_rebuild": (_int, [_vp, _i64, _vp, _vp, _vp]),
     "tfmm_tree_walk": (_int, [_vp, _d, _vp]),

@@ -65,6 +65,10 @@ class Context:
         """Device bytes held, including released blocks kept for reuse."""
         return int(self.lib.tfmm_ctx_bytes_held(self.handle))
 
+    def set_budget(self, budget_bytes: int) -> None:
+        """Device-memory budget for later allocations (0 = no limit)."""
+        self.check(self.lib.tfmm_ctx_set_budget(self.handle, int(budget_bytes)))
+
     def trim(self) -> None:
         """Give the released blocks kept for reuse back to the device."""
         self.check(self.lib.tfmm_ctx_trim(self.handle))

@@ -308,6 +308,15 @@ size_t tfmm_ctx_bytes_in_use(const tfmm_ctx* ctx) { return ctx ? ctx->used - ctx
 
 size_t tfmm_ctx_bytes_held(const tfmm_ctx* ctx) { return ctx ? ctx->used : 0; }
 
+int tfmm_ctx_set_budget(tfmm_ctx* ctx, size_t hbm_budget_bytes) {
+    if (!ctx) return TFMM_EINVAL;
+    return guarded(ctx, [&] {
+        set_device(ctx);
+        ctx->budget = hbm_budget_bytes;
+        if (hbm_budget_bytes && ctx->used > hbm_budget_bytes) ctx->trim_cache();
+    });
+}
+
 int tfmm_ctx_trim(tfmm_ctx* ctx) {
     if (!ctx) return TFMM_EINVAL;
     return guarded(ctx, [&] {

@@ -4,8 +4,14 @@ Requests arrive over time (a Poisson trace); each asks for the forces on one
 particle set (N, p, theta, variant) or for the next leapfrog step of one of
 the persistent sessions.  The server keeps `slots` workers busy: as soon as a
 worker is free and the solve at the head of the queue fits in the device
-memory budget (tfmm_footprint_bytes), it is admitted, so requests that arrive
-while others run start as slots and memory free up.  Solves go first; a
+memory budget, it is admitted, so requests that arrive while others run start
+as slots and memory free up.  The budget counts what the slots really hold:
+a slot keeps its grow-only tree, its context's reusable blocks and its
+request buffers between solves, and a running solve reserves the larger of
+that and its footprint (tfmm_footprint_bytes plus the request buffers); the
+library part of the reservation is the slot context's budget, so a solve
+cannot outgrow it.  When the head solve does not fit, idle slots give their
+memory back, the largest first.  Solves go first; a
 session step takes a free worker only while no admissible solve is waiting,
 and session steps hold at most `step_slots` workers at once (default half),
 so an arriving solve finds a worker ready.  Every worker owns a
@@ -98,7 +104,14 @@ def make_inputs(req: Request):
     return hp, hm
 
 
+# Device bytes per particle of a worker's request buffers (pos, mass, force).
+STATE_BYTES = 56
+
+
 class _Worker:
+    """One slot: a libtfmm context, a stream, a reusable tree and request
+    buffers.  Everything it keeps between requests counts as held memory."""
+
     def __init__(self, wid: int, device: int, n_leaf: int):
         self.wid = wid
         self.ctx = api.Context(device)
@@ -110,8 +123,25 @@ class _Worker:
         self.mass = None
         self.force = None
 
+    def tensor_bytes(self) -> int:
+        return 0 if self.pos is None else STATE_BYTES * int(self.pos.shape[0])
+
+    def held(self) -> int:
+        """Device bytes this slot keeps: the context's (trees, scratch, blocks
+        kept for reuse) plus the request buffers."""
+        return self.ctx.bytes_held() + self.tensor_bytes()
+
+    def shrink(self) -> None:
+        """Give everything back (idle slots only)."""
+        if self.tree is not None:
+            self.tree.close()
+            self.tree = None
+        self.pos = self.mass = self.force = None
+        self.ctx.trim()
+
     def _buffers(self, n: int):
         if self.pos is None or self.pos.shape[0] < n:
+            self.pos = self.mass = self.force = None
             cap = max(n, 1024)
             self.pos = torch.empty((cap, 3), dtype=torch.float64, device=self.dev)
             self.mass = torch.empty((cap,), dtype=torch.float64, device=self.dev)
@@ -153,7 +183,9 @@ class Server:
         self.keep_full = bool(keep_full)
 
     def footprint(self, req: Request) -> int:
-        return api.footprint_bytes(req.n, req.p, self.n_leaf, self.precision) + 48 * req.n
+        """Device bytes a solve may need: the library's estimate for its tree
+        plus its request buffers."""
+        return api.footprint_bytes(req.n, req.p, self.n_leaf, self.precision) + STATE_BYTES * max(req.n, 1024)
 
     def run(self, requests: List[Request], sessions: Optional[List[Session]] = None,
             session_dt: float = 1e-3, inputs=None) -> List[Record]:
@@ -167,12 +199,25 @@ class Server:
         pending = collections.deque()      # solves, FIFO
         steps_q = collections.deque()      # session steps, FIFO
         records: List[Record] = []
-        state = {"used": sum(session_footprint(s.n, s.params["p"], s.n_leaf, s.params["precision"])
-                             for s in sessions),
-                 "free_workers": list(range(self.slots)), "solves_left": len(requests), "next_step_id": 10**9,
+        # Memory: the sessions' footprints, plus per slot either the bytes
+        # reserved for the solve it runs (the larger of what it held and the
+        # solve's footprint, the library part enforced through the slot
+        # context's budget) or, while it runs no solve, what it holds.
+        sess_bytes = sum(session_footprint(s.n, s.params["p"], s.n_leaf, s.params["precision"]) for s in sessions)
+        reserved = {}                      # slot -> bytes reserved for its running solve
+        state = {"free_workers": list(range(self.slots)), "solves_left": len(requests), "next_step_id": 10**9,
                  "stop": False, "error": None}
-        if state["used"] > self.budget:
+        self.peak_reserved = sess_bytes
+        self.over_reservation = 0
+        if sess_bytes > self.budget:
             raise MemoryError("the resident sessions alone exceed the memory budget")
+
+        def total_bytes(exclude: int = -1) -> int:
+            tot = sess_bytes
+            for v, w in enumerate(workers):
+                if v != exclude:
+                    tot += reserved[v] if v in reserved else w.held()
+            return tot
         t0 = time.perf_counter()
         for k, s in enumerate(sessions):  # every session starts with one queued step
             steps_q.append(Request(rid=state["next_step_id"] + k, arrival=0.0, kind="step", n=s.n, session=k,
@@ -201,7 +246,9 @@ class Server:
             with lock:
                 records.append(rec)
                 if req.kind == "solve":
-                    state["used"] -= fp
+                    held = workers[wid].held()
+                    if held > reserved.pop(wid):
+                        self.over_reservation += 1
                     state["solves_left"] -= 1
                 else:
                     busy_sessions.discard(req.session)
@@ -225,17 +272,42 @@ class Server:
                 while pending and state["free_workers"]:
                     req = pending[0]
                     fp = self.footprint(req)
-                    if fp > self.budget:
+                    if fp > self.budget - sess_bytes:
                         pending.popleft()
                         records.append(Record(req.rid, req.kind, req.n, req.p, req.theta, req.variant, req.arrival,
                                               error="footprint exceeds the budget"))
                         state["solves_left"] -= 1
                         continue
-                    if state["used"] + fp > self.budget:
-                        break
+                    lib_fp = api.footprint_bytes(req.n, req.p, self.n_leaf, self.precision)
+                    free = state["free_workers"]
+
+                    def need_of(v):
+                        # bytes slot v reserves for this solve: the larger of what it
+                        # holds and the footprint, for the library and the buffers
+                        lib_need = max(workers[v].ctx.bytes_held(), lib_fp)
+                        return lib_need, lib_need + max(workers[v].tensor_bytes(), fp - lib_fp)
+
+                    # the free slot that grows least (ties: the one holding most)
+                    wid = min(free, key=lambda v: (need_of(v)[1] - workers[v].held(), -workers[v].held()))
+                    w = workers[wid]
+                    lib_need, need = need_of(wid)
+                    total = total_bytes(exclude=wid) + need
+                    if total > self.budget:
+                        # give back what idle slots keep, the largest first, then the chosen
+                        # slot's own leftovers (its buffers may exceed what this solve needs)
+                        for v in sorted((v for v in free if v != wid), key=lambda v: -workers[v].held()) + [wid]:
+                            workers[v].shrink()
+                            lib_need, need = need_of(wid)
+                            total = total_bytes(exclude=wid) + need
+                            if total <= self.budget:
+                                break
+                    if total > self.budget:
+                        break  # wait for running solves: alone, the solve fits (checked above)
                     pending.popleft()
-                    state["used"] += fp
-                    wid = state["free_workers"].pop()
+                    reserved[wid] = need
+                    w.ctx.set_budget(lib_need)
+                    self.peak_reserved = max(self.peak_reserved, total)
+                    free.remove(wid)
                     th = threading.Thread(target=execute, args=(wid, req, now, fp), daemon=True)
                     threads.append(th)
                     th.start()

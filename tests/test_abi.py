@@ -49,3 +49,4 @@ def test_host_only_entry_points(lib):
     assert lib.tfmm_ctx_destroy(None) == _lib.OK
     assert lib.tfmm_ctx_bytes_held(None) == 0
     assert lib.tfmm_ctx_trim(None) == _lib.EINVAL
+    assert lib.tfmm_ctx_set_budget(None, 0) == _lib.EINVAL

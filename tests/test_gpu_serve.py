@@ -63,3 +63,28 @@ def test_memory_budget_queues_and_rejects(gpu):
     bad = [r for r in recs if r.error]
     assert len(bad) == 1 and "budget" in bad[0].error
     assert sum(1 for r in recs if not r.error) == len(reqs) - 1
+
+
+def test_memory_budget_counts_what_slots_hold(gpu):
+    """Slots keep their trees, reusable blocks and request buffers between
+    solves; the admission counts them, so under a budget of about two of the
+    larger footprints the reservations never exceed the budget, and no slot
+    ever holds more than it reserved (the library part is capped by the slot
+    context's budget)."""
+    from paper_2107_07166_amd.serve import Server, make_trace
+    reqs = _reqs() + make_trace(16, rate=300.0, seed=13, n_min=2e3, n_max=6e4)
+    for k, r in enumerate(reqs):
+        r.rid = k
+    probe = Server(slots=4)
+    fps = sorted(probe.footprint(r) for r in reqs)
+    budget = fps[-1] + fps[-2]
+    srv = Server(slots=4, budget_bytes=budget, keep_full=True)
+    recs = srv.run(reqs)
+    assert all(not r.error for r in recs), [r.error for r in recs if r.error]
+    assert len(recs) == len(reqs)
+    assert srv.over_reservation == 0
+    assert srv.peak_reserved <= budget
+    # the same solves with an unlimited budget give the same forces
+    free = {r.rid: r.full for r in Server(slots=4, keep_full=True).run(reqs)}
+    for r in recs:
+        assert np.array_equal(r.full, free[r.rid]), r.rid
