@@ -27,12 +27,8 @@ constexpr int MB = 256;         // largest block (4 waves); launches may use few
 // of the compute units.  The conserving far field is the heavier one and
 // finishes with the near field only with one-wave blocks; the standard one
 // already does with four-wave blocks and would only slow the near field.
-#ifndef TFMM_M2L_CONS_MB
-#define TFMM_M2L_CONS_MB 64
-#endif
-#ifndef TFMM_M2L_STD_MB
-#define TFMM_M2L_STD_MB 256
-#endif
+constexpr int kConsBlock = 64;
+constexpr int kStdBlock = 256;
 constexpr int LPT = 32;         // lanes per target node
 constexpr int TPW = kWave / LPT;  // target nodes per wavefront
 
@@ -245,7 +241,7 @@ void launch(Tree& t, double eps2, hipStream_t s) {
     const int64_t nt = t.n_nodes;  // every node; nodes with an empty far list write nothing
     if (nt <= 0) return;
     const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
-    const int mb = VAR == TFMM_STANDARD ? TFMM_M2L_STD_MB : TFMM_M2L_CONS_MB;
+    const int mb = VAR == TFMM_STANDARD ? kStdBlock : kConsBlock;
     const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, mb));
     if constexpr (VAR == TFMM_CONSERVING && P >= kConsSplitP) {
         auto pass = [&](auto kern) {
@@ -275,7 +271,7 @@ void launch_knob(Tree& t, double eps2, hipStream_t s) {
     const int64_t nt = t.n_nodes;
     if (nt <= 0) return;
     const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
-    const int mb = TFMM_M2L_CONS_MB;
+    const int mb = kConsBlock;
     const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, mb));
     auto pass = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, dim3(mb), 0, s, nt, t.m2l_off.template as<uint32_t>(),

@@ -30,38 +30,20 @@
 namespace tfmm {
 namespace {
 
-#ifndef TFMM_SORT_LOOK
-#define TFMM_SORT_LOOK 8  // earlier tiles read per look-back step
-#endif
-#ifndef TFMM_SORT_RI64
-#define TFMM_SORT_RI64 16
-#endif
-#ifndef TFMM_SORT_RI32
-#define TFMM_SORT_RI32 16
-#endif
+constexpr int kLookBack = 8;      // earlier tiles read per look-back step
 constexpr int RB = 256;           // threads per block (one digit per thread)
 constexpr int RW = RB / kWave;    // waves per block
-#ifndef TFMM_SORT_RI32K
-#define TFMM_SORT_RI32K 16
-#endif
-// keys per lane: 64-bit keys stage twice the bytes in LDS; keys without
-// values stage half
-template <typename K, bool HV> constexpr int keys_per_lane() {
-    return sizeof(K) == 8 ? TFMM_SORT_RI64 : (HV ? TFMM_SORT_RI32 : TFMM_SORT_RI32K);
-}
+// keys per lane (16 for every key type: measured against 8 and 32)
+template <typename K, bool HV> constexpr int keys_per_lane() { return 16; }
 template <typename K, bool HV> constexpr int tile_keys() { return RB * keys_per_lane<K, HV>(); }
 constexpr int RADIX = 256;
 constexpr int MAXP = 8;          // passes of a 64-bit key
 constexpr int kHistBlocks = 1024;
-// Sorts of at least this many tiles run reduce-then-scan passes.
-#ifndef TFMM_RTS_MIN_TILES
-#define TFMM_RTS_MIN_TILES 1024
-#endif
-constexpr int kRtsMinTiles = TFMM_RTS_MIN_TILES;
-#ifndef TFMM_HIST_KPT
-#define TFMM_HIST_KPT 16
-#endif
-constexpr int kHistKeysPerThread = TFMM_HIST_KPT;  // fewer blocks, fewer global atomics
+// Sorts of at least this many tiles run reduce-then-scan passes (count, scan,
+// scatter), so that no tile waits on another (decoupled look-back over
+// thousands of tiles costs more than the extra launches).
+constexpr int kRtsMinTiles = 1024;
+constexpr int kHistKeysPerThread = 16;  // fewer blocks, fewer global atomics
 constexpr uint32_t kSpinLimit = 1u << 20;
 
 // Tile status word: bits 62..63 flag (0 none, 1 own count, 2 running total
@@ -251,7 +233,7 @@ __global__ __launch_bounds__(RB) void radix_pass_kernel(Src src, K* __restrict__
     } else {
         __hip_atomic_store(&st[d], kFlagOwn | (unsigned long long)real, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // earlier tiles' words for this digit, kLook at a time (independent loads)
-        constexpr int kLook = TFMM_SORT_LOOK;
+        constexpr int kLook = kLookBack;
         uint32_t spins = 0;
         int64_t j = tile - 1;
         bool done = false;

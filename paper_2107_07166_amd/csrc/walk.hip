@@ -348,10 +348,7 @@ constexpr int kPassGrid = 2048;                // blocks of a fused pass (at mos
 // Passes expected to hold at most this many pairs run fused.  Look-back over
 // many tiles costs more than the second launch saves, so larger passes keep
 // the two-kernel form.
-#ifndef TFMM_FUSE_MAX_PAIRS
-#define TFMM_FUSE_MAX_PAIRS 4096
-#endif
-constexpr int64_t kFuseMaxPairs = TFMM_FUSE_MAX_PAIRS;
+constexpr int64_t kFuseMaxPairs = 4096;
 
 __device__ __forceinline__ unsigned long long pst_word(uint32_t epoch, unsigned long long flag,
                                                        unsigned long long v) {
