@@ -592,8 +592,8 @@ void orc_tree_nodes(const orc_tree *t, int32_t *level, uint64_t *prefix, int64_t
 /* canonical unordered pairs (lower node index first), in walk order */
 void orc_tree_lists(const orc_tree *t, int64_t *m2l, int64_t *p2p)
 {
-    if (m2l) memcpy(m2l, t->m2l, (size_t)t->n_m2l * 2 * sizeof(int64_t));
-    if (p2p) memcpy(p2p, t->p2p, (size_t)t->n_p2p * 2 * sizeof(int64_t));
+    if (m2l && t->n_m2l > 0) memcpy(m2l, t->m2l, (size_t)t->n_m2l * 2 * sizeof(int64_t));
+    if (p2p && t->n_p2p > 0) memcpy(p2p, t->p2p, (size_t)t->n_p2p * 2 * sizeof(int64_t));
 }
 
 static int cmp_i64(const void *a, const void *b)
