@@ -52,8 +52,8 @@ P2P_FLOP_PER_PAIR = 20        # per directed particle interaction (convention)
 # factor a plain copy of known size reads) and WRITE_SIZE (x1); see
 # profiles/p2p_plummer1m_counters.md.  Valid only for the kernel source the
 # counters were taken with (first 16 hex digits of its sha256).
-P2P_TRAFFIC_BYTES = (2 * 225760 + 32009) * 1024
-P2P_TRAFFIC_SOURCE_SHA = "9b57e608a2569034"
+P2P_TRAFFIC_BYTES = (2 * 225455 + 32009) * 1024
+P2P_TRAFFIC_SOURCE_SHA = "d8db2db14a6c4d73"
 
 
 def _p2p_traffic():

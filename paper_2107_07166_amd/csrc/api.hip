@@ -153,7 +153,8 @@ int scalar_degree(const tfmm_params* p) {
 // soon as the near lists exist, beside M2L and L2L on the second stream.
 // Adds the phase times of the last timed evaluation to the tree's sums.
 // Events: moments [0,1], M2L [7,2], L2L [2,3] on the tree's second stream;
-// P2P [6,4], L2P [8,5] on the caller's stream (8: after the streams join);
+// P2P [6,4] (the near-field kernel; the partial-sum reduction follows it),
+// L2P [8,5] on the caller's stream (8: after the streams join);
 // whole evaluation [0,5]; walk [11, later of 7 and 6], its frontier passes
 // [11,12] (only in evaluations that walked).
 double elapsed_ms(Tree& t, int i, int j) {
@@ -238,6 +239,7 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[6], s));
     run_p2p(t, prm->precision, eps2, potential != nullptr, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[4], s));
+    run_p2p_reduce(t, potential != nullptr, s);
     aux_join(t, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[8], s));
     run_l2p(t, pe, ve, prm->G, force, s);

@@ -250,6 +250,7 @@ void prepare_sources(Tree& t, int precision, hipStream_t s);
 void run_m2l(Tree& t, int p, int variant, int precision, double eps2, hipStream_t s, int kdeg);
 constexpr int kKnobMaxK = 6;  // largest scalar degree built for the GPU
 void run_p2p(Tree& t, int precision, double eps2, bool with_pot, hipStream_t s);
+void run_p2p_reduce(Tree& t, bool with_pot, hipStream_t s);
 void run_m2l_pot(Tree& t, int p, int mom_p, int precision, double eps2, hipStream_t s);
 void run_potential_down(Tree& t, int p, int precision, double eps2, double G, double* pot, hipStream_t s);
 void run_l2l(Tree& t, int p, int variant, hipStream_t s);

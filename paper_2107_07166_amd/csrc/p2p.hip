@@ -345,6 +345,14 @@ void launch(Tree& t, double eps2, hipStream_t s) {
                            t.nd_Z.as<double4>(), t.src4.as<V4>(), (T)eps2, t.leaf_nitems.as<int32_t>(),
                            t.partial.as<double>(), t.near3.as<double>(), ppot, npot);
     TFMM_LAUNCHED();
+}
+
+template <bool POT>
+void launch_reduce(Tree& t, hipStream_t s) {
+    const int64_t ni = t.n_items;
+    if (ni <= 0) return;
+    double* ppot = POT ? t.partial_pot.as<double>() : nullptr;
+    double* npot = POT ? t.near_pot.as<double>() : nullptr;
     // every leaf has at least one item, so at most n_items - n_leaves leaves have several
     const int64_t nmulti = ni - t.n_leaves;
     if (nmulti > 0) {
@@ -358,6 +366,13 @@ void launch(Tree& t, double eps2, hipStream_t s) {
 }
 
 }  // namespace
+
+// The partial sums of leaves whose near list was cut into several items
+// (after run_p2p on the same stream).
+void run_p2p_reduce(Tree& t, bool with_pot, hipStream_t s) {
+    if (with_pot) launch_reduce<true>(t, s);
+    else launch_reduce<false>(t, s);
+}
 
 void run_p2p(Tree& t, int precision, double eps2, bool with_pot, hipStream_t s) {
     t.near3.ensure(t.ctx, (size_t)t.n * 24);
