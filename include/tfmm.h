@@ -164,6 +164,40 @@ int tfmm_tree_walk(tfmm_tree *tree, double theta, void *stream);
 int tfmm_evaluate_forces(tfmm_tree *tree, const tfmm_params *params, double *force,
                          double *potential, void *stream);
 
+/* Forests: several independent particle sets solved by one set of launches
+ * (for serving many small requests at once).  Set k is particles
+ * offsets[k] .. offsets[k+1]-1 of pos and mass (device, laid out as in
+ * tfmm_build_tree); offsets is a host array of n_sets + 1 ascending values
+ * with offsets[0] = 0 and every set non-empty (1 <= n_sets <= 4096, at most
+ * 2^30 particles in all).  Every set gets what tfmm_build_tree would build
+ * for it alone -- its own bounding cube, keys, octree under its own root
+ * (node k is the root of set k; nodes are numbered level by level across the
+ * sets, in set order inside a level), moments and r_max (Eq.
+ * mac_criterion) -- and the walk starts from the pair (root k, root k) of
+ * every set, so nodes of different sets never interact: the forces of a set
+ * are bit for bit those of the set solved alone with the same parameters.
+ * Synchronising.  Errors: EINVAL (bad offsets or n_leaf, NULL pointers),
+ * ENOMEM, EDEVICE. */
+int tfmm_build_forest(tfmm_ctx *ctx, int n_sets, const int64_t *offsets, const double *pos,
+                      const double *mass, int n_leaf, void *stream, tfmm_tree **out);
+
+/* Rebuild any tree in place as a forest of n_sets sets (arguments as in
+ * tfmm_build_forest; n_sets = 1 is tfmm_tree_rebuild, and tfmm_tree_rebuild
+ * turns a forest back into one set).  Synchronising.  Errors: as
+ * tfmm_build_forest. */
+int tfmm_forest_rebuild(tfmm_tree *tree, int n_sets, const int64_t *offsets, const double *pos,
+                        const double *mass, void *stream);
+
+/* tfmm_evaluate_forces on a forest with one MAC parameter per set: theta is
+ * a host array of n_sets values in [0, 1) (Eq. mac_criterion for the pairs of
+ * set k uses theta[k]), or NULL for params->theta everywhere.  p, softening,
+ * G, variant, precision and scalar_degree are shared by all sets.  force and
+ * potential are laid out like pos (set after set, input order inside a set).
+ * tfmm_evaluate_forces on a forest equals this call with theta = NULL.
+ * Errors: as tfmm_evaluate_forces, and EINVAL for a theta outside [0, 1). */
+int tfmm_evaluate_forest(tfmm_tree *tree, const tfmm_params *params, const double *theta,
+                         double *force, double *potential, void *stream);
+
 /* Build + evaluate in one call (tree is built, used and destroyed).
  * Synchronising.  Errors: as tfmm_build_tree and tfmm_evaluate_forces. */
 int tfmm_evaluate_forces_oneshot(tfmm_ctx *ctx, int64_t n, const double *pos, const double *mass,
@@ -176,7 +210,8 @@ int tfmm_evaluate_forces_oneshot(tfmm_ctx *ctx, int64_t n, const double *pos, co
  * the masses the tree was built with.  force must hold the forces at pos on
  * entry when force_valid != 0, otherwise they are evaluated first; on return
  * it holds the forces at the final positions.  The tree must have been built
- * for n particles.  Synchronising (each rebuild reads sizes).
+ * for n particles, as one set (not a forest).  Synchronising (each rebuild
+ * reads sizes).
  * Errors: EINVAL (bad pointers, nsteps < 0, non-finite dt, bad params),
  * ENOMEM, EDEVICE. */
 int tfmm_leapfrog(tfmm_tree *tree, const tfmm_params *params, double *pos, double *vel,
@@ -237,8 +272,12 @@ int tfmm_lists_export(tfmm_tree *tree, int32_t *m2l_pairs, int32_t *p2p_pairs);
  * NULL is ignored. */
 int tfmm_tree_destroy(tfmm_tree *tree);
 
-/* Conservative estimate of the device bytes a tree of n particles at order p
- * needs (for admission control).  Pure host computation. */
+/* Estimate of the device bytes a tree of n particles at order p needs (for
+ * admission control; a forest: n = all its particles).  The interaction
+ * lists grow as theta falls: on the serving workloads (theta >= 0.4, Plummer,
+ * ball and disk sets) a fresh tree holds at most 0.9 of it.  A tree reused
+ * for another particle set keeps its grow-only buffers, so it can hold more.
+ * Pure host computation. */
 size_t tfmm_footprint_bytes(int64_t n, int p, int n_leaf, int precision);
 
 /* Per-phase device times (milliseconds), averaged over the evaluations

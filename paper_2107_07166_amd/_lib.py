@@ -43,6 +43,9 @@ SIGNATURES = {
     "tfmm_ctx_set_budget": (_int, [_vp, _sz]),
     "tfmm_build_tree": (_int, [_vp, _i64, _vp, _vp, _int, _vp, ctypes.POINTER(_vp)]),
     "tfmm_tree_rebuild": (_int, [_vp, _i64, _vp, _vp, _vp]),
+    "tfmm_build_forest": (_int, [_vp, _int, _vp, _vp, _vp, _int, _vp, ctypes.POINTER(_vp)]),
+    "tfmm_forest_rebuild": (_int, [_vp, _int, _vp, _vp, _vp, _vp]),
+    "tfmm_evaluate_forest": (_int, [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp]),
     "tfmm_tree_walk": (_int, [_vp, _d, _vp]),
     "tfmm_evaluate_forces": (_int, [_vp, ctypes.POINTER(Params), _vp, _vp, _vp]),
     "tfmm_evaluate_forces_oneshot": (_int, [_vp, _i64, _vp, _vp, _int, ctypes.POINTER(Params), _vp, _vp]),

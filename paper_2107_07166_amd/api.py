@@ -100,10 +100,20 @@ class Context:
         return out
 
 
-class Tree:
-    """Octree of one particle set, with its walk and expansions cached."""
+def _offsets(offsets, n: int) -> np.ndarray:
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or off.size < 2 or off[-1] != n:
+        raise ValueError("offsets must be 1-D, n_sets + 1 values ending at the particle count")
+    return off
 
-    def __init__(self, ctx: Context, pos: torch.Tensor, mass: torch.Tensor, n_leaf: int = 64):
+
+class Tree:
+    """Octree of one particle set (or a forest of independent sets), with its
+    walk and expansions cached."""
+
+    def __init__(self, ctx: Context, pos: torch.Tensor, mass: torch.Tensor, n_leaf: int = 64, offsets=None):
+        """offsets: None for one particle set, else the n_sets + 1 boundaries
+        of a forest (set k is particles offsets[k] .. offsets[k+1]-1)."""
         n = int(mass.shape[0])
         _check_vec(pos, "pos", (n, 3))
         _check_vec(mass, "mass", (n,))
@@ -112,18 +122,35 @@ class Tree:
         self.n_leaf = int(n_leaf)
         self.device = pos.device
         h = ctypes.c_void_p()
-        ctx.check(ctx.lib.tfmm_build_tree(ctx.handle, n, pos.data_ptr(), mass.data_ptr(), self.n_leaf,
-                                          _stream_handle(pos.device), ctypes.byref(h)))
+        if offsets is None:
+            self.n_sets = 1
+            ctx.check(ctx.lib.tfmm_build_tree(ctx.handle, n, pos.data_ptr(), mass.data_ptr(), self.n_leaf,
+                                              _stream_handle(pos.device), ctypes.byref(h)))
+        else:
+            off = _offsets(offsets, n)
+            self.n_sets = int(off.size - 1)
+            ctx.check(ctx.lib.tfmm_build_forest(ctx.handle, self.n_sets, off.ctypes.data_as(ctypes.c_void_p),
+                                                pos.data_ptr(), mass.data_ptr(), self.n_leaf,
+                                                _stream_handle(pos.device), ctypes.byref(h)))
         self.handle = h
         ctx._trees.add(self)
 
-    def rebuild(self, pos: torch.Tensor, mass: torch.Tensor) -> None:
-        """Rebuild for new positions; the particle count may change (buffers are grow-only)."""
+    def rebuild(self, pos: torch.Tensor, mass: torch.Tensor, offsets=None) -> None:
+        """Rebuild for new positions; the particle count may change (buffers
+        are grow-only).  offsets: as in the constructor (None: one set)."""
         n = int(mass.shape[0])
         _check_vec(pos, "pos", (n, 3))
         _check_vec(mass, "mass", (n,))
-        self.ctx.check(self.ctx.lib.tfmm_tree_rebuild(self.handle, n, pos.data_ptr(), mass.data_ptr(),
-                                                      _stream_handle(pos.device)))
+        if offsets is None:
+            self.ctx.check(self.ctx.lib.tfmm_tree_rebuild(self.handle, n, pos.data_ptr(), mass.data_ptr(),
+                                                          _stream_handle(pos.device)))
+            self.n_sets = 1
+        else:
+            off = _offsets(offsets, n)
+            self.ctx.check(self.ctx.lib.tfmm_forest_rebuild(self.handle, int(off.size - 1),
+                                                            off.ctypes.data_as(ctypes.c_void_p), pos.data_ptr(),
+                                                            mass.data_ptr(), _stream_handle(pos.device)))
+            self.n_sets = int(off.size - 1)
         self.n = n
 
     def walk(self, theta: float) -> None:
@@ -147,6 +174,27 @@ class Tree:
                      int(scalar_degree))
         self.ctx.check(self.ctx.lib.tfmm_evaluate_forces(self.handle, ctypes.byref(prm), out.data_ptr(), pot_ptr,
                                                          _stream_handle(self.device)))
+        return out
+
+    def evaluate_forest(self, thetas, p: int = 4, eps: float = 1e-3, variant: str = "conserving",
+                        precision: str = "mixed32", G: float = 1.0, out: Optional[torch.Tensor] = None,
+                        pot: Optional[torch.Tensor] = None, scalar_degree: int = 0) -> torch.Tensor:
+        """evaluate() with one theta per set of the forest (tfmm_evaluate_forest)."""
+        th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64))
+        if th.shape != (self.n_sets,):
+            raise ValueError(f"thetas must hold one value per set ({self.n_sets})")
+        if out is None:
+            out = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        _check_vec(out, "out", (self.n, 3))
+        pot_ptr = None
+        if pot is not None:
+            _check_vec(pot, "pot", (self.n,))
+            pot_ptr = pot.data_ptr()
+        prm = Params(int(p), float(th[0]), float(eps), float(G), VARIANTS[variant], PRECISIONS[precision],
+                     int(scalar_degree))
+        self.ctx.check(self.ctx.lib.tfmm_evaluate_forest(self.handle, ctypes.byref(prm),
+                                                         th.ctypes.data_as(ctypes.c_void_p), out.data_ptr(),
+                                                         pot_ptr, _stream_handle(self.device)))
         return out
 
     def info(self) -> dict:

@@ -141,6 +141,24 @@ void check_params(const tfmm_params* p) {
     }
 }
 
+// Particle sets of a forest: offsets (host) ascending from 0, every set
+// non-empty; returns the particle count.
+int64_t check_sets(int n_sets, const int64_t* offsets) {
+    if (n_sets < 1 || n_sets > kMaxSets) fail(TFMM_EINVAL, "n_sets must be in 1..4096");
+    if (!offsets) fail(TFMM_EINVAL, "offsets is NULL");
+    if (offsets[0] != 0) fail(TFMM_EINVAL, "offsets[0] must be 0");
+    for (int k = 0; k < n_sets; ++k)
+        if (offsets[k + 1] <= offsets[k]) fail(TFMM_EINVAL, "every set must hold at least one particle");
+    const int64_t n = offsets[n_sets];
+    if (n > (int64_t)INT32_MAX / 2) fail(TFMM_EINVAL, "n must be in 1..2^30");
+    return n;
+}
+
+void set_sets(Tree& t, int n_sets, const int64_t* offsets, hipStream_t s) {
+    t.n_sets = n_sets;
+    if (n_sets > 1) upload(t, t.set_off, offsets, (size_t)(n_sets + 1) * sizeof(int64_t), 0, s);
+}
+
 // Degree of the conserving projection scalar (p - 1 unless raised).
 int scalar_degree(const tfmm_params* p) {
     return p->scalar_degree == 0 ? p->p - 1 : p->scalar_degree;
@@ -204,8 +222,13 @@ void timing_events(Tree& t) {
     }
 }
 
-void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential, hipStream_t s) {
-    const bool need_walk = !t.walk_valid || t.walk_theta != prm->theta;
+// theta_sets: one theta per set of a forest (host), or nullptr for
+// params->theta everywhere.
+void evaluate(Tree& t, const tfmm_params* prm, const double* theta_sets, double* force, double* potential,
+              hipStream_t s) {
+    const std::vector<double> theta =
+        theta_sets ? std::vector<double>(theta_sets, theta_sets + t.n_sets) : std::vector<double>{prm->theta};
+    const bool need_walk = !t.walk_valid || t.walk_theta != theta;
     // The zeroth-order magnitude realignment (Eq. aaB0) is quadratic in the
     // target offset and needs the node quadrupoles: it runs through the
     // conserving locals (P, Q') of order 2, with its own M2L.
@@ -228,7 +251,7 @@ void evaluate(Tree& t, const tfmm_params* prm, double* force, double* potential,
     if (need_walk) {
         t.walk_valid = false;
         if (t.timing) TFMM_HIP(hipEventRecord(t.ev[11], s));
-        walk_lists_begin(t, prm->theta, s, t.timing ? t.ev[12] : nullptr);
+        walk_lists_begin(t, theta, s, t.timing ? t.ev[12] : nullptr);
     }
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[7], a));
     run_m2l(t, knob ? prm->p : pe, prm->variant, prm->precision, eps2, a, knob ? kdeg : -1);
@@ -373,6 +396,7 @@ int tfmm_tree_rebuild(tfmm_tree* tree, int64_t n, const double* pos, const doubl
             TFMM_HIP(hipEventRecord(t.ev[9], s));
         }
         t.n = n;
+        t.n_sets = 1;
         build_tree(t, pos, mass, s);
         if (t.timing) {
             TFMM_HIP(hipEventRecord(t.ev[10], s));
@@ -381,12 +405,83 @@ int tfmm_tree_rebuild(tfmm_tree* tree, int64_t n, const double* pos, const doubl
     });
 }
 
+int tfmm_build_forest(tfmm_ctx* ctx, int n_sets, const int64_t* offsets, const double* pos, const double* mass,
+                      int n_leaf, void* stream, tfmm_tree** out) {
+    if (!ctx) return TFMM_EINVAL;
+    if (!out) {
+        ctx->err = "out is NULL";
+        return TFMM_EINVAL;
+    }
+    *out = nullptr;
+    tfmm_tree* t = nullptr;
+    const int rc = guarded(ctx, [&] {
+        const int64_t n = check_sets(n_sets, offsets);
+        if (!pos || !mass) fail(TFMM_EINVAL, "pos and mass must be device pointers");
+        if (n_leaf < 1 || n_leaf > 4096) fail(TFMM_EINVAL, "n_leaf must be in 1..4096");
+        set_device(ctx);
+        t = new tfmm_tree();
+        t->ctx = ctx;
+        t->n = n;
+        t->n_leaf = n_leaf;
+        ctx->live_trees++;
+        set_sets(*t, n_sets, offsets, (hipStream_t)stream);
+        build_tree(*t, pos, mass, (hipStream_t)stream);
+    });
+    if (rc != TFMM_OK) {
+        if (t) {
+            tfmm_tree_destroy(t);
+        }
+        return rc;
+    }
+    *out = t;
+    return TFMM_OK;
+}
+
+int tfmm_forest_rebuild(tfmm_tree* tree, int n_sets, const int64_t* offsets, const double* pos,
+                        const double* mass, void* stream) {
+    if (!tree) return TFMM_EINVAL;
+    return guarded(tree->ctx, [&] {
+        const int64_t n = check_sets(n_sets, offsets);
+        if (!pos || !mass) fail(TFMM_EINVAL, "pos and mass must be device pointers");
+        set_device(tree->ctx);
+        Tree& t = *tree;
+        const hipStream_t s = (hipStream_t)stream;
+        timing_events(t);
+        if (t.timing) {
+            fold_build(t);
+            TFMM_HIP(hipEventRecord(t.ev[9], s));
+        }
+        t.n = n;
+        set_sets(t, n_sets, offsets, s);
+        build_tree(t, pos, mass, s);
+        if (t.timing) {
+            TFMM_HIP(hipEventRecord(t.ev[10], s));
+            t.build_pending = true;
+        }
+    });
+}
+
+int tfmm_evaluate_forest(tfmm_tree* tree, const tfmm_params* params, const double* theta, double* force,
+                         double* potential, void* stream) {
+    if (!tree) return TFMM_EINVAL;
+    return guarded(tree->ctx, [&] {
+        check_params(params);
+        if (!force) fail(TFMM_EINVAL, "force must be a device pointer");
+        if (theta)
+            for (int k = 0; k < tree->n_sets; ++k)
+                if (!(theta[k] >= 0.0) || !(theta[k] < 1.0))
+                    fail(TFMM_EINVAL, "theta must satisfy 0 <= theta < 1 for every set");
+        set_device(tree->ctx);
+        evaluate(*tree, params, theta, force, potential, (hipStream_t)stream);
+    });
+}
+
 int tfmm_tree_walk(tfmm_tree* tree, double theta, void* stream) {
     if (!tree) return TFMM_EINVAL;
     return guarded(tree->ctx, [&] {
         if (!(theta >= 0.0) || !(theta < 1.0)) fail(TFMM_EINVAL, "theta must satisfy 0 <= theta < 1");
         set_device(tree->ctx);
-        walk_tree(*tree, theta, (hipStream_t)stream);
+        walk_tree(*tree, std::vector<double>{theta}, (hipStream_t)stream);
     });
 }
 
@@ -397,7 +492,7 @@ int tfmm_evaluate_forces(tfmm_tree* tree, const tfmm_params* params, double* for
         check_params(params);
         if (!force) fail(TFMM_EINVAL, "force must be a device pointer");
         set_device(tree->ctx);
-        evaluate(*tree, params, force, potential, (hipStream_t)stream);
+        evaluate(*tree, params, nullptr, force, potential, (hipStream_t)stream);
     });
 }
 
@@ -424,18 +519,19 @@ int tfmm_leapfrog(tfmm_tree* tree, const tfmm_params* params, double* pos, doubl
         check_params(params);
         if (!pos || !vel || !mass || !force) fail(TFMM_EINVAL, "pos, vel, mass and force must be device pointers");
         if (nsteps < 0 || !std::isfinite(dt)) fail(TFMM_EINVAL, "nsteps must be >= 0 and dt finite");
+        if (tree->n_sets != 1) fail(TFMM_EINVAL, "leapfrog needs a tree of one particle set");
         set_device(tree->ctx);
         Tree& t = *tree;
         const hipStream_t s = (hipStream_t)stream;
         if (!force_valid) {
             build_tree(t, pos, mass, s);
-            evaluate(t, params, force, nullptr, s);
+            evaluate(t, params, nullptr, force, nullptr, s);
         }
         for (int k = 0; k < nsteps; ++k) {
             run_kick(t.n, vel, force, mass, 0.5 * dt, s);
             run_drift(t.n, pos, vel, dt, s);
             build_tree(t, pos, mass, s);
-            evaluate(t, params, force, nullptr, s);
+            evaluate(t, params, nullptr, force, nullptr, s);
             run_kick(t.n, vel, force, mass, 0.5 * dt, s);
         }
     });
@@ -544,6 +640,10 @@ int tfmm_tree_destroy(tfmm_tree* tree) {
         (void)hipEventDestroy(tree->join_ev);
         (void)hipStreamDestroy(tree->aux);
     }
+    if (tree->stage) {
+        (void)hipEventDestroy(tree->stage_ev);
+        (void)hipHostFree(tree->stage);
+    }
     // the device is idle: the tree's buffers go to the context's cache directly
     ctx->idle_release = true;
     delete tree;
@@ -562,7 +662,7 @@ size_t tfmm_footprint_bytes(int64_t n, int p, int n_leaf, int precision) {
     b += nn * (nc * 8 + ncp * 12 + 2 * nloc * 8);
     b += nn * (400.0 * 8 * 2 + 80.0 * 8 * 2);  // pair lists, directed lists, frontiers
     b += (double)n * 16;                       // scratch
-    return (size_t)(b * 1.25) + (64u << 20);
+    return (size_t)(b * 1.5) + (64u << 20);
 }
 
 int tfmm_tree_set_timing(tfmm_tree* tree, int enable) {

@@ -92,10 +92,37 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 
+// Largest number of particle sets in one tree (a forest of independent sets).
+constexpr int kMaxSets = 4096;
+
+// The set k of sorted position (or input index) j: off[k] <= j < off[k + 1]
+// (off: n_sets + 1 ascending offsets; never read for a single set).
+__device__ __forceinline__ int set_of(const int64_t* __restrict__ off, int n_sets, int64_t j) {
+    if (n_sets <= 1) return 0;
+    int lo = 0, hi = n_sets - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= j) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 struct Tree {
     Ctx* ctx = nullptr;
     int64_t n = 0;
     int n_leaf = 0;
+    // Independent particle sets sharing this tree object (a forest): set k
+    // is input particles [off[k], off[k + 1]), and after the sort the same
+    // range of sorted positions.  Each set has its own key cube and root
+    // (node k); the walk never pairs nodes of different sets.  One set for
+    // an ordinary tree.
+    int n_sets = 1;
+    DevBuf set_off;            // int64, n_sets + 1 (device)
+    DevBuf set_theta;          // FP64 theta of every set for the walk (device)
+    DevBuf set_sort;           // forest sort scratch: set keys and positions
+    void* stage = nullptr;     // pinned host staging of the set tables
+    hipEvent_t stage_ev = nullptr;  // the last upload from it
     // tree sizes (host copies)
     int64_t n_nodes = 0, n_leaves = 0;
     int max_level = 0;
@@ -123,7 +150,7 @@ struct Tree {
 
     // walk and per-target interaction lists
     bool walk_valid = false;
-    double walk_theta = -1.0;
+    std::vector<double> walk_theta;  // theta of the last walk: one value, or one per set
     int64_t n_m2l = -1, n_p2p = -1, n_near_int = -1;
     DevBuf m2l_pairs, p2p_pairs;  // int2, lower node id first
     DevBuf m2l_off, m2l_src;      // per-target CSR, directed: source = m2l_src[q] & m2l_src_mask
@@ -235,10 +262,15 @@ V read_back_checked(Ctx* ctx, const V* dev, hipStream_t s) {
 
 // ---- phases ---------------------------------------------------------------
 void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s);
-void walk_tree(Tree& t, double theta, hipStream_t s);
+// Copies bytes from host memory to dst (device) on s through the tree's
+// pinned staging area (slot 0 or 1, kStageSlot bytes each).
+constexpr size_t kStageSlot = 48 << 10;
+void upload(Tree& t, DevBuf& dst, const void* src, size_t bytes, int slot, hipStream_t s);
+// theta: one value for every set, or one per set (n_sets values)
+void walk_tree(Tree& t, const std::vector<double>& theta, hipStream_t s);
 // passes_done: an event recorded on s once the frontier passes are queued
 // (before the list chains), or nullptr
-void walk_lists_begin(Tree& t, double theta, hipStream_t s, hipEvent_t passes_done = nullptr);
+void walk_lists_begin(Tree& t, const std::vector<double>& theta, hipStream_t s, hipEvent_t passes_done = nullptr);
 void walk_lists_end(Tree& t, hipStream_t s);
 void aux_fork(Tree& t, hipStream_t s);
 void aux_join(Tree& t, hipStream_t s);

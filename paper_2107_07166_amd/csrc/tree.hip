@@ -68,6 +68,21 @@ __global__ __launch_bounds__(TB) void bbox_partial_kernel(const double* __restri
 // The cube of the keys: out[0..2] lo, [3..5] hi, [6] ext = the largest
 // extent (1 if all extents are 0), [7] scale = 2^21 / ext, [8] 1 if any
 // coordinate is not finite.  Exact FP64 operations, no contraction.
+__device__ void write_cube(const double* lo, const double* hi, bool bad, double* __restrict__ out) {
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        out[d] = lo[d];
+        out[3 + d] = hi[d];
+        const double e = hi[d] - lo[d];
+        if (e > ext) ext = e;
+    }
+    if (ext == 0.0) ext = 1.0;
+    const double scale = 2097152.0 / ext;
+    out[6] = ext;
+    out[7] = scale;
+    out[8] = (bad || !isfinite(ext) || !isfinite(scale)) ? 1.0 : 0.0;
+}
+
 __global__ __launch_bounds__(TB) void bbox_final_kernel(const double* __restrict__ part, int nb,
                                                         double* __restrict__ out) {
     __shared__ double sh[6][TB];
@@ -98,18 +113,53 @@ __global__ __launch_bounds__(TB) void bbox_final_kernel(const double* __restrict
         }
         __syncthreads();
     }
-    if (threadIdx.x < 6) out[threadIdx.x] = sh[threadIdx.x][0];
     if (threadIdx.x == 0) {
-        double ext = 0.0;
+        const double lo[3] = {sh[0][0], sh[1][0], sh[2][0]}, hi[3] = {sh[3][0], sh[4][0], sh[5][0]};
+        write_cube(lo, hi, s_bad != 0, out);
+    }
+}
+
+// The cubes of the sets of a forest, one block per set (cube k at out + 16 k).
+__global__ __launch_bounds__(TB) void bbox_sets_kernel(const double* __restrict__ pos,
+                                                       const int64_t* __restrict__ off,
+                                                       double* __restrict__ out) {
+    const int64_t a0 = off[blockIdx.x], a1 = off[blockIdx.x + 1];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int64_t a = a0 + threadIdx.x; a < a1; a += TB) {
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const double e = sh[3 + d][0] - sh[d][0];
-            if (e > ext) ext = e;
+            const double v = pos[3 * a + d];
+            bad |= !isfinite(v);
+            lo[d] = v < lo[d] ? v : lo[d];
+            hi[d] = v > hi[d] ? v : hi[d];
         }
-        if (ext == 0.0) ext = 1.0;
-        const double scale = 2097152.0 / ext;
-        out[6] = ext;
-        out[7] = scale;
-        out[8] = (s_bad || !isfinite(ext) || !isfinite(scale)) ? 1.0 : 0.0;
+    }
+    __shared__ double sh[6][TB];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    if (bad) s_bad = 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        sh[d][threadIdx.x] = lo[d];
+        sh[3 + d][threadIdx.x] = hi[d];
+    }
+    __syncthreads();
+    for (int st = TB / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double x = sh[d][threadIdx.x + st], y = sh[3 + d][threadIdx.x + st];
+                if (x < sh[d][threadIdx.x]) sh[d][threadIdx.x] = x;
+                if (y > sh[3 + d][threadIdx.x]) sh[3 + d][threadIdx.x] = y;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double l[3] = {sh[0][0], sh[1][0], sh[2][0]}, h[3] = {sh[3][0], sh[4][0], sh[5][0]};
+        write_cube(l, h, s_bad != 0, out + 16 * (int64_t)blockIdx.x);
     }
 }
 
@@ -124,10 +174,12 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
 }
 
 __global__ __launch_bounds__(TB) void morton_kernel(const double* __restrict__ pos, int64_t n,
-                                                    const double* __restrict__ cube, uint64_t* __restrict__ keys,
-                                                    int32_t* __restrict__ idx) {
+                                                    const double* __restrict__ cubes,
+                                                    const int64_t* __restrict__ set_off, int n_sets,
+                                                    uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
     const int64_t a = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (a >= n) return;
+    const double* cube = cubes + 16 * (int64_t)set_of(set_off, n_sets, a);
     const double lo[3] = {cube[0], cube[1], cube[2]};
     const double scale = cube[7];
     uint32_t q[3];
@@ -140,19 +192,44 @@ __global__ __launch_bounds__(TB) void morton_kernel(const double* __restrict__ p
     idx[a] = (int32_t)a;
 }
 
+// Forest: after the sort by key, a stable sort by set puts every set's
+// particles in its own range in key order.  skey = set of each sorted
+// particle, spos = its position; then the keys and the order follow spos.
+__global__ __launch_bounds__(TB) void set_keys_kernel(const int32_t* __restrict__ perm, int64_t n,
+                                                      const int64_t* __restrict__ set_off, int n_sets,
+                                                      uint32_t* __restrict__ skey, int32_t* __restrict__ spos) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= n) return;
+    skey[j] = (uint32_t)set_of(set_off, n_sets, perm[j]);
+    spos[j] = (int32_t)j;
+}
+
+__global__ __launch_bounds__(TB) void set_apply_kernel(const int32_t* __restrict__ spos, int64_t n,
+                                                       const uint64_t* __restrict__ keys,
+                                                       const int32_t* __restrict__ perm,
+                                                       uint64_t* __restrict__ keys_out, int32_t* __restrict__ perm_out) {
+    const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (j >= n) return;
+    const int32_t q = spos[j];
+    keys_out[j] = keys[q];
+    perm_out[j] = perm[q];
+}
+
 // Sorted FP64 particles and the level at which a key boundary appears in front
-// of each sorted position (22 = equal keys, never a boundary).
+// of each sorted position (22 = equal keys, never a boundary; 0 = the first
+// particle of a set, where its root starts).
 __global__ __launch_bounds__(TB) void gather_kernel(const double* __restrict__ pos,
                                                     const double* __restrict__ mass,
                                                     const uint64_t* __restrict__ keys,
                                                     const int32_t* __restrict__ perm, int64_t n,
+                                                    const int64_t* __restrict__ set_off, int n_sets,
                                                     double4* __restrict__ Xm, uint8_t* __restrict__ lvlb) {
     const int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (j >= n) return;
     const int64_t a = perm[j];
     Xm[j] = make_double4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], mass[a]);
     uint8_t lb = 0;
-    if (j > 0) {
+    if (j > 0 && (n_sets <= 1 || set_off[set_of(set_off, n_sets, j)] != j)) {
         const uint64_t x = keys[j - 1] ^ keys[j];
         lb = (x == 0) ? (uint8_t)(kLevels + 1) : (uint8_t)(kLevels - (63 - __clzll((long long)x)) / 3);
     }
@@ -172,21 +249,29 @@ struct NodeArrays {
 // ---- octree from the sorted keys, all levels at once -------------------------
 // With the split rule "count > n_leaf and level < 21", a particle's leaf level
 // lambda(j) is one more than the deepest level at which its cell holds more
-// than n_leaf particles (capped at 21), and that happens exactly when some
-// window of n_leaf + 1 consecutive sorted keys around j shares the prefix of
-// that level.  Position j then starts a node at every level l with
-// lvlb[j] <= l <= lambda(j) (l >= 1; the root is node 0).  Node ids are level
-// major and in position order inside a level, so an id is the level's first
-// id plus the number of node starts at that level before j: per-level counts
-// per block, scanned over blocks, plus wave ballots inside the block.
+// than n_leaf particles (capped at 21; 0 when its whole set fits one leaf),
+// and that happens exactly when some window of n_leaf + 1 consecutive sorted
+// keys of its set around j shares the prefix of that level.  Position j then
+// starts a node at every level l with lvlb[j] <= l <= lambda(j); the roots
+// (level 0) start at the first particle of every set, so root k is node k.
+// Node ids are level major and in position order inside a level, so an id is
+// the level's first id plus the number of node starts at that level before j:
+// per-level counts per block, scanned over blocks, plus wave ballots inside
+// the block.
 constexpr int NSLOT = kLevels + 2;  // levels 0..21 and a slot for the leaf count
 constexpr int kMaxLeafWindow = 4096;
 
-// cl[i] = deepest level shared by keys[i] and keys[i + n_leaf] (21 if equal).
+// cl[i] = deepest level shared by keys[i] and keys[i + n_leaf] (21 if equal,
+// -1 if the two belong to different sets).
 __global__ __launch_bounds__(TB) void window_level_kernel(const uint64_t* __restrict__ keys, int64_t nw, int n_leaf,
+                                                          const int64_t* __restrict__ set_off, int n_sets,
                                                           int8_t* __restrict__ cl) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i >= nw) return;
+    if (n_sets > 1 && set_off[set_of(set_off, n_sets, i) + 1] <= i + n_leaf) {
+        cl[i] = (int8_t)-1;
+        return;
+    }
     const uint64_t x = keys[i] ^ keys[i + n_leaf];
     cl[i] = (x == 0) ? (int8_t)kLevels : (int8_t)(kLevels - (63 - __clzll((long long)x)) / 3 - 1);
 }
@@ -239,17 +324,14 @@ __global__ __launch_bounds__(TB) void leaf_level_kernel(const int8_t* __restrict
         const int bd = x > y ? x : y;
         b = bd < 0 ? 0 : (bd + 1 < kLevels ? bd + 1 : kLevels);
         lam[j] = (uint8_t)b;
-        a = lvlb[j] > 1 ? lvlb[j] : 1;
+        a = lvlb[j];
     }
-    for (int l = 1; l <= kLevels; ++l) {
+    for (int l = 0; l <= kLevels; ++l) {
         const unsigned long long bl = __ballot(a <= l && l <= b);
         if (lane == 0) wc[wv][l] = (uint32_t)__popcll(bl);
     }
     const unsigned long long leaf = __ballot(a <= b);
-    if (lane == 0) {
-        wc[wv][0] = 0u;
-        wc[wv][NSLOT - 1] = (uint32_t)__popcll(leaf);
-    }
+    if (lane == 0) wc[wv][NSLOT - 1] = (uint32_t)__popcll(leaf);
     __syncthreads();
     if (tid < NSLOT) {
         uint32_t c = 0;
@@ -291,20 +373,21 @@ struct TreeHeader {
     int64_t nonfinite;        // a coordinate was not finite
 };
 
-__global__ void tree_header_kernel(const uint32_t* __restrict__ tot, const double* __restrict__ cube,
+__global__ void tree_header_kernel(const uint32_t* __restrict__ tot, const double* __restrict__ cubes, int n_sets,
                                    TreeHeader* __restrict__ h) {
     if (threadIdx.x != 0) return;
-    h->nonfinite = cube[8] != 0.0 ? 1 : 0;
+    int64_t bad = 0;
+    for (int k = 0; k < n_sets; ++k) bad |= cubes[16 * k + 8] != 0.0 ? 1 : 0;
+    h->nonfinite = bad;
     h->LB[0] = 0;
-    h->LB[1] = 1;
     int64_t ml = 0;
-    for (int l = 1; l <= kLevels; ++l) {
+    for (int l = 0; l <= kLevels; ++l) {
         h->LB[l + 1] = h->LB[l] + tot[l];
         if (tot[l] > 0) ml = l;
     }
     h->max_level = ml;
     h->n_nodes = h->LB[kLevels + 1];
-    h->n_leaves = (int64_t)tot[NSLOT - 1] + (ml == 0 ? 1 : 0);
+    h->n_leaves = (int64_t)tot[NSLOT - 1];
 }
 
 __global__ __launch_bounds__(TB) void node_create_kernel(NodeArrays nd, int64_t n, const uint64_t* __restrict__ keys,
@@ -320,16 +403,16 @@ __global__ __launch_bounds__(TB) void node_create_kernel(NodeArrays nd, int64_t 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int64_t j = (int64_t)blockIdx.x * TB + tid;
     const bool valid = j < n;
-    const int a = valid ? (lvlb[j] > 1 ? (int)lvlb[j] : 1) : 99;
+    const int a = valid ? (int)lvlb[j] : 99;
     const int b = valid ? (int)lam[j] : 0;
-    for (int l = 1; l <= kLevels; ++l) {
+    for (int l = 0; l <= kLevels; ++l) {
         const unsigned long long bl = __ballot(a <= l && l <= b);
         if (lane == 0) bal[wv][l] = bl;
     }
     if (tid < kLevels + 2) sLB[tid] = h->LB[tid];
-    if (tid >= 1 && tid <= kLevels) sboff[tid] = boff[(int64_t)tid * nblk + blockIdx.x];
+    if (tid <= kLevels) sboff[tid] = boff[(int64_t)tid * nblk + blockIdx.x];
     __syncthreads();
-    if (tid >= 1 && tid <= kLevels) {
+    if (tid <= kLevels) {
         uint32_t run = 0;
 #pragma unroll
         for (int q = 0; q < TB / kWave; ++q) {
@@ -343,20 +426,8 @@ __global__ __launch_bounds__(TB) void node_create_kernel(NodeArrays nd, int64_t 
     auto rank = [&](int l) -> int64_t {
         return (int64_t)sboff[l] + woff[wv][l] + (uint32_t)__popcll(bal[wv][l] & lt);
     };
-    auto incl = [&](int l) -> int64_t {
-        if (l == 0) return 1;
-        return rank(l) + ((a <= l && l <= b) ? 1 : 0);
-    };
-    leaf_of[j] = (b == 0) ? 0 : (int32_t)(sLB[b] + incl(b) - 1);
-    if (j == 0) {
-        nd.level[0] = 0;
-        nd.prefix[0] = 0;
-        nd.first[0] = 0;
-        nd.count[0] = (int32_t)n;
-        nd.parent[0] = -1;
-        nd.nchild[0] = 0;
-        nd.child_first[0] = (b >= 1) ? (int32_t)(sLB[1] + rank(1)) : -1;
-    }
+    auto incl = [&](int l) -> int64_t { return rank(l) + ((a <= l && l <= b) ? 1 : 0); };
+    leaf_of[j] = (int32_t)(sLB[b] + incl(b) - 1);
     for (int l = a; l <= b; ++l) {
         const int64_t id = sLB[l] + rank(l);
         nd.level[id] = l;
@@ -364,22 +435,23 @@ __global__ __launch_bounds__(TB) void node_create_kernel(NodeArrays nd, int64_t 
         nd.first[id] = (int32_t)j;
         nd.count[id] = 0;
         nd.nchild[id] = 0;
-        nd.parent[id] = (l == 1) ? 0 : (int32_t)(sLB[l - 1] + incl(l - 1) - 1);
+        nd.parent[id] = (l == 0) ? -1 : (int32_t)(sLB[l - 1] + incl(l - 1) - 1);
         nd.child_first[id] = (l + 1 <= b) ? (int32_t)(sLB[l + 1] + rank(l + 1)) : -1;
     }
 }
 
 // Particle counts (a node ends where the next node of its level starts if
-// that node has the same parent, else where its parent ends) and child counts
-// (written by the last child).
+// that node has the same parent, else where its parent ends; the roots,
+// parent -1, end where the next root starts) and child counts (written by the
+// last child).
 __global__ __launch_bounds__(TB) void node_finish_kernel(NodeArrays nd, int64_t nn, int64_t n,
                                                          const TreeHeader* __restrict__ h) {
-    const int64_t c = 1 + (int64_t)blockIdx.x * TB + threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (c >= nn) return;
     const int l = nd.level[c];
     const int32_t P = nd.parent[c];
     int64_t x = c, end = n;
-    for (int lx = l; lx >= 1; --lx) {
+    for (int lx = l; lx >= 0; --lx) {
         const int64_t nx = x + 1;
         if (nx < h->LB[lx + 1] && nd.parent[nx] == nd.parent[x]) {
             end = nd.first[nx];
@@ -388,7 +460,8 @@ __global__ __launch_bounds__(TB) void node_finish_kernel(NodeArrays nd, int64_t 
         x = nd.parent[x];
     }
     nd.count[c] = (int32_t)(end - nd.first[c]);
-    if (c + 1 >= h->LB[l + 1] || nd.parent[c + 1] != P) nd.nchild[P] = (int32_t)(c - nd.child_first[P] + 1);
+    if (P >= 0 && (c + 1 >= h->LB[l + 1] || nd.parent[c + 1] != P))
+        nd.nchild[P] = (int32_t)(c - nd.child_first[P] + 1);
 }
 
 __global__ __launch_bounds__(TB) void leaf_flag_kernel(const int32_t* __restrict__ nchild, int64_t nn,
@@ -583,33 +656,77 @@ V read_back(Ctx* ctx, const V* dev, hipStream_t s) {
 
 }  // namespace
 
+void upload(Tree& t, DevBuf& dst, const void* src, size_t bytes, int slot, hipStream_t s) {
+    if (bytes > kStageSlot) fail(TFMM_EINVAL, "set table too large");
+    if (!t.stage) {
+        TFMM_HIP(hipHostMalloc(&t.stage, 2 * kStageSlot, hipHostMallocDefault));
+        TFMM_HIP(hipEventCreateWithFlags(&t.stage_ev, hipEventDisableTiming));
+    } else {
+        // the previous copy out of the staging area has finished reading it
+        TFMM_HIP(hipEventSynchronize(t.stage_ev));
+    }
+    char* h = static_cast<char*>(t.stage) + (size_t)slot * kStageSlot;
+    std::memcpy(h, src, bytes);
+    dst.ensure(t.ctx, bytes);
+    TFMM_HIP(hipMemcpyAsync(dst.p, h, bytes, hipMemcpyHostToDevice, s));
+    TFMM_HIP(hipEventRecord(t.stage_ev, s));
+}
+
 void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     Ctx* ctx = t.ctx;
     const int64_t n = t.n;
     const size_t un = (size_t)n;
 
-    // bounding cube and key scale, on the device (no read-back)
+    // bounding cube and key scale of every set, on the device (no read-back)
+    const int ns = t.n_sets;
+    const int64_t* soff = ns > 1 ? t.set_off.as<int64_t>() : nullptr;
     const int nbb = (int)std::min<int64_t>(1024, cdiv(n, TB));
     t.scratch.ensure(ctx, std::max<size_t>({(size_t)nbb * 7 * 8 + 64, sort_scratch_bytes(n, 3 * kLevels) + 256,
                                             scan_scratch_bytes(n) + 256}));
-    t.cube.ensure(ctx, 16 * sizeof(double));
+    t.cube.ensure(ctx, (size_t)ns * 16 * sizeof(double));
     double* part = t.scratch.as<double>();
     double* cube = t.cube.as<double>();
-    hipLaunchKernelGGL(bbox_partial_kernel, dim3(nbb), dim3(TB), 0, s, pos, n, part);
-    TFMM_LAUNCHED();
-    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(TB), 0, s, (const double*)part, nbb, cube);
-    TFMM_LAUNCHED();
+    if (ns > 1) {
+        hipLaunchKernelGGL(bbox_sets_kernel, dim3((unsigned)ns), dim3(TB), 0, s, pos, soff, cube);
+        TFMM_LAUNCHED();
+    } else {
+        hipLaunchKernelGGL(bbox_partial_kernel, dim3(nbb), dim3(TB), 0, s, pos, n, part);
+        TFMM_LAUNCHED();
+        hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(TB), 0, s, (const double*)part, nbb, cube);
+        TFMM_LAUNCHED();
+    }
 
-    // keys and stable order
+    // keys and stable order (by set, then by key)
     t.keys.ensure(ctx, un * 8);
     t.keys2.ensure(ctx, un * 8);
     t.perm.ensure(ctx, un * 4);
     t.perm2.ensure(ctx, un * 4);
-    hipLaunchKernelGGL(morton_kernel, dim3(grid(n)), dim3(TB), 0, s, pos, n, (const double*)cube,
+    hipLaunchKernelGGL(morton_kernel, dim3(grid(n)), dim3(TB), 0, s, pos, n, (const double*)cube, soff, ns,
                        t.keys.as<uint64_t>(), t.perm.as<int32_t>());
     TFMM_LAUNCHED();
     radix_sort_u64(t.keys.as<uint64_t>(), t.perm.as<int32_t>(), t.keys2.as<uint64_t>(), t.perm2.as<int32_t>(),
                    n, 3 * kLevels, t.scratch.p, ctx->dev_err, s);
+    if (ns > 1) {
+        int bits = 1;
+        while ((1 << bits) < ns) ++bits;
+        t.set_sort.ensure(ctx, un * 16);
+        uint32_t* skey = t.set_sort.as<uint32_t>();
+        int32_t* spos = reinterpret_cast<int32_t*>(skey + n);
+        uint32_t* skey2 = skey + 2 * n;
+        int32_t* spos2 = reinterpret_cast<int32_t*>(skey + 3 * n);
+        hipLaunchKernelGGL(set_keys_kernel, dim3(grid(n)), dim3(TB), 0, s, (const int32_t*)t.perm.as<int32_t>(), n,
+                           soff, ns, skey, spos);
+        TFMM_LAUNCHED();
+        radix_sort_u32(skey, spos, skey2, spos2, n, bits, t.scratch.p, ctx->dev_err, s);
+        hipLaunchKernelGGL(set_apply_kernel, dim3(grid(n)), dim3(TB), 0, s, (const int32_t*)spos, n,
+                           (const uint64_t*)t.keys.as<uint64_t>(), (const int32_t*)t.perm.as<int32_t>(),
+                           t.keys2.as<uint64_t>(), t.perm2.as<int32_t>());
+        TFMM_LAUNCHED();
+        std::swap(t.keys.p, t.keys2.p);
+        std::swap(t.keys.cap, t.keys2.cap);
+        std::swap(t.perm.p, t.perm2.p);
+        std::swap(t.perm.cap, t.perm2.cap);
+    }
 
     // sorted particles, boundary levels
     t.Xm.ensure(ctx, un * 32);
@@ -617,7 +734,7 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     t.owner.ensure(ctx, un * 2);
     t.leaf_of.ensure(ctx, un * 4);
     hipLaunchKernelGGL(gather_kernel, dim3(grid(n)), dim3(TB), 0, s, pos, mass, t.keys.as<uint64_t>(),
-                       t.perm.as<int32_t>(), n, t.Xm.as<double4>(), t.lvlb.as<uint8_t>());
+                       t.perm.as<int32_t>(), n, soff, ns, t.Xm.as<double4>(), t.lvlb.as<uint8_t>());
     TFMM_LAUNCHED();
 
     // octree: leaf level of every particle, node starts per level, node table
@@ -633,7 +750,7 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     TreeHeader* hdr = t.scratch2.as<TreeHeader>();
     if (nw > 0) {
         hipLaunchKernelGGL(window_level_kernel, dim3(grid(nw)), dim3(TB), 0, s, (const uint64_t*)t.keys.as<uint64_t>(),
-                           nw, t.n_leaf, cl);
+                           nw, t.n_leaf, soff, ns, cl);
         TFMM_LAUNCHED();
     }
     hipLaunchKernelGGL(leaf_level_kernel, dim3((unsigned)nblk), dim3(TB), 0, s, (const int8_t*)cl, n, t.n_leaf,
@@ -641,7 +758,8 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     TFMM_LAUNCHED();
     hipLaunchKernelGGL(slot_scan_kernel, dim3(NSLOT), dim3(TB), 0, s, cnt, nblk, tot);
     TFMM_LAUNCHED();
-    hipLaunchKernelGGL(tree_header_kernel, dim3(1), dim3(kWave), 0, s, (const uint32_t*)tot, (const double*)cube, hdr);
+    hipLaunchKernelGGL(tree_header_kernel, dim3(1), dim3(kWave), 0, s, (const uint32_t*)tot, (const double*)cube, ns,
+                       hdr);
     TFMM_LAUNCHED();
     const TreeHeader H = read_back_checked(ctx, (const TreeHeader*)hdr, s);
     if (H.nonfinite) fail(TFMM_EINVAL, "positions contain non-finite values");
@@ -658,10 +776,8 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
                        (const uint8_t*)lam, (const uint32_t*)cnt, nblk, (const TreeHeader*)hdr,
                        t.leaf_of.as<int32_t>());
     TFMM_LAUNCHED();
-    if (nn > 1) {
-        hipLaunchKernelGGL(node_finish_kernel, dim3(grid(nn - 1)), dim3(TB), 0, s, nd, nn, n, (const TreeHeader*)hdr);
-        TFMM_LAUNCHED();
-    }
+    hipLaunchKernelGGL(node_finish_kernel, dim3(grid(nn)), dim3(TB), 0, s, nd, nn, n, (const TreeHeader*)hdr);
+    TFMM_LAUNCHED();
 
     // leaves, in node order
     t.flags.ensure(ctx, (size_t)std::max<int64_t>(n, nn) * 4 * 2);

@@ -1,7 +1,9 @@
 // Mutual dual-tree walk and per-target interaction lists.
 //
 // The walk processes a frontier of unordered node pairs level-synchronously
-// from (root, root).  For each pair:
+// from (root, root) (one such pair per set of a forest; the children of a
+// pair belong to its set, so nodes of different sets never meet, and each
+// set may have its own theta).  For each pair:
 //   A == B : a leaf gives a near (P2P) self pair; otherwise the children
 //            pairs (c_i, c_j), i <= j, join the next frontier;
 //   A != B : R = sqrt((dx*dx + dy*dy) + dz*dz), d = Z_A - Z_B.  The pair is a
@@ -26,10 +28,12 @@ namespace {
 constexpr int TB = 256;
 
 // Per node, packed for the walk: geo = (centre of mass x, y, z, r_max),
-// top = (child count, level, first child, 0).
+// top = (child count, level, first child, set).  theta: per set (forests
+// walked with several thetas), else nullptr and the passes' scalar applies.
 struct WalkNodes {
     const double4* geo;
     const int4* top;
+    const double* theta;
 };
 
 __global__ __launch_bounds__(TB) void walk_nodes_kernel(int64_t nn, const double4* __restrict__ Z,
@@ -37,12 +41,14 @@ __global__ __launch_bounds__(TB) void walk_nodes_kernel(int64_t nn, const double
                                                         const int32_t* __restrict__ nchild,
                                                         const int32_t* __restrict__ level,
                                                         const int32_t* __restrict__ child_first,
+                                                        const int32_t* __restrict__ first,
+                                                        const int64_t* __restrict__ set_off, int n_sets,
                                                         double4* __restrict__ geo, int4* __restrict__ top) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i >= nn) return;
     const double4 z = Z[i];
     geo[i] = make_double4(z.x, z.y, z.z, rmax[i]);
-    top[i] = make_int4(nchild[i], level[i], child_first[i], 0);
+    top[i] = make_int4(nchild[i], level[i], child_first[i], set_of(set_off, n_sets, first[i]));
 }
 
 struct Decision {
@@ -69,7 +75,8 @@ __device__ __forceinline__ Decision decide(const WalkNodes& w, int32_t A, int32_
     const double dx = ga.x - gb.x, dy = ga.y - gb.y, dz = ga.z - gb.z;
     const double R = sqrt((dx * dx + dy * dy) + dz * dz);
     const double ra = ga.w, rb = gb.w;
-    if (R > 0.0 && ra + rb <= theta * R) {
+    const double th = w.theta ? w.theta[ta.w] : theta;
+    if (R > 0.0 && ra + rb <= th * R) {
         d.kind = 1;
         return d;
     }
@@ -180,18 +187,19 @@ __device__ __forceinline__ void block_tiles(uint32_t nf, int64_t& t0, int64_t& t
     t1 = t0 + per < tiles ? t0 + per : tiles;
 }
 
-__global__ void walk_init_kernel(WalkState* __restrict__ st, int2* __restrict__ fr) {
+// The first frontier: (k, k) for the root k of every set.
+__global__ void walk_init_kernel(WalkState* __restrict__ st, int2* __restrict__ fr, int n_roots) {
     if (threadIdx.x == 0) {
-        st->nf[0] = 1u;
+        st->nf[0] = (uint32_t)n_roots;
         st->nf[1] = 0u;
         st->overflow = 0u;
         st->passes = 0u;
-        st->max_nf = 1u;
+        st->max_nf = (uint32_t)n_roots;
         st->pad = 0u;
         st->n_far[0] = st->n_far[1] = 0ull;
         st->n_near[0] = st->n_near[1] = 0ull;
-        fr[0] = make_int2(0, 0);
     }
+    for (int k = threadIdx.x; k < n_roots; k += blockDim.x) fr[k] = make_int2(k, k);
     for (int k = threadIdx.x; k < kMaxPasses; k += blockDim.x) {
         st->nf_pass[k] = 0u;
         st->ticket[k] = 0u;
@@ -743,17 +751,17 @@ void walk_bfs_sized(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
         cap_near = std::max<int64_t>(4096, 16 * nn);
         t.p2p_pairs.ensure(ctx, (size_t)cap_near * 8);
     }
-    t.w_fr.ensure(ctx, 4096 * 8);
+    t.w_fr.ensure(ctx, (size_t)std::max(4096, t.n_sets) * 8);
     t.w_off.ensure(ctx, (size_t)kWalkGrid * sizeof(U3L));
     t.w_state.ensure(ctx, sizeof(WalkState));
     t.scratch2.ensure(ctx, 256);
     WalkState* st = t.w_state.as<WalkState>();
     U3L* tot = t.scratch2.as<U3L>();
-    hipLaunchKernelGGL(walk_init_kernel, dim3(1), dim3(kWave), 0, s, st, t.w_fr.as<int2>());
+    hipLaunchKernelGGL(walk_init_kernel, dim3(1), dim3(TB), 0, s, st, t.w_fr.as<int2>(), t.n_sets);
     TFMM_LAUNCHED();
     DevBuf* cur = &t.w_fr;
     DevBuf* nxt = &t.w_fr2;
-    int64_t nf = 1, max_nf = 1, n_far = 0, n_near = 0;
+    int64_t nf = t.n_sets, max_nf = t.n_sets, n_far = 0, n_near = 0;
     t.walk_hint_nf.clear();
     for (int k = 0; nf > 0; ++k) {
         const int parity = k & 1;
@@ -835,9 +843,9 @@ bool walk_bfs_async(Tree& t, const WalkNodes& w, double theta, hipStream_t s) {
         t.w_epoch = 0;
     }
     WalkState* st = t.w_state.as<WalkState>();
-    hipLaunchKernelGGL(walk_init_kernel, dim3(1), dim3(kWave), 0, s, st, t.w_fr.as<int2>());
+    hipLaunchKernelGGL(walk_init_kernel, dim3(1), dim3(TB), 0, s, st, t.w_fr.as<int2>(), t.n_sets);
     TFMM_LAUNCHED();
-    int64_t bound = 1;  // a pass's frontier is at most 36 times the previous one
+    int64_t bound = t.n_sets;  // a pass's frontier is at most 36 times the previous one
     for (int k = 0; k < passes; ++k) {
         const int parity = k & 1;
         // grid from this pass's frontier in the previous walk (any grid covers
@@ -907,17 +915,27 @@ void aux_join(Tree& t, hipStream_t s) {
 // The frontier passes on s, then the far-list chain on the tree's second
 // stream (after the passes) and the near-list chain on s.  walk_lists_end
 // reads the totals back once the near chain is done.
-void walk_lists_begin(Tree& t, double theta, hipStream_t s, hipEvent_t passes_done) {
+void walk_lists_begin(Tree& t, const std::vector<double>& theta_in, hipStream_t s, hipEvent_t passes_done) {
     Ctx* ctx = t.ctx;
     const int64_t nn = t.n_nodes;
+    if (theta_in.size() != 1 && theta_in.size() != (size_t)t.n_sets) fail(TFMM_EINVAL, "theta: one value or one per set");
+    const std::vector<double> theta_keep = theta_in;  // the caller's vector may be the tree's own
+    const double theta = theta_keep[0];
+    const double* theta_dev = nullptr;
+    if (theta_keep.size() > 1) {
+        upload(t, t.set_theta, theta_keep.data(), theta_keep.size() * sizeof(double), 1, s);
+        theta_dev = t.set_theta.as<double>();
+    }
     t.w_geo.ensure(ctx, (size_t)std::max<int64_t>(nn, 1) * sizeof(double4));
     t.w_top.ensure(ctx, (size_t)std::max<int64_t>(nn, 1) * sizeof(int4));
     hipLaunchKernelGGL(walk_nodes_kernel, dim3(grid(nn)), dim3(TB), 0, s, nn, (const double4*)t.nd_Z.as<double4>(),
                        (const double*)t.nd_rmax.as<double>(), (const int32_t*)t.nd_nchild.as<int32_t>(),
                        (const int32_t*)t.nd_level.as<int32_t>(), (const int32_t*)t.nd_child_first.as<int32_t>(),
+                       (const int32_t*)t.nd_first.as<int32_t>(),
+                       t.n_sets > 1 ? (const int64_t*)t.set_off.as<int64_t>() : nullptr, t.n_sets,
                        t.w_geo.as<double4>(), t.w_top.as<int4>());
     TFMM_LAUNCHED();
-    WalkNodes w{t.w_geo.as<double4>(), t.w_top.as<int4>()};
+    WalkNodes w{t.w_geo.as<double4>(), t.w_top.as<int4>(), theta_dev};
     t.walk_valid = false;
     if (!walk_bfs_async(t, w, theta, s)) walk_bfs_sized(t, w, theta, s);
     t.walk_hint_far = t.n_m2l;
@@ -988,7 +1006,7 @@ void walk_lists_begin(Tree& t, double theta, hipStream_t s, hipEvent_t passes_do
                            t.multi_leaf.as<int32_t>(), &res->multi);
         TFMM_LAUNCHED();
     }
-    t.walk_theta = theta;
+    t.walk_theta = theta_keep;
 }
 
 void walk_lists_end(Tree& t, hipStream_t s) {
@@ -1004,7 +1022,7 @@ void walk_lists_end(Tree& t, hipStream_t s) {
     t.walk_valid = true;
 }
 
-void walk_tree(Tree& t, double theta, hipStream_t s) {
+void walk_tree(Tree& t, const std::vector<double>& theta, hipStream_t s) {
     walk_lists_begin(t, theta, s);
     aux_join(t, s);
     walk_lists_end(t, s);

@@ -50,3 +50,6 @@ def test_host_only_entry_points(lib):
     assert lib.tfmm_ctx_bytes_held(None) == 0
     assert lib.tfmm_ctx_trim(None) == _lib.EINVAL
     assert lib.tfmm_ctx_set_budget(None, 0) == _lib.EINVAL
+    assert lib.tfmm_build_forest(None, 1, None, None, None, 8, None, None) == _lib.EINVAL
+    assert lib.tfmm_forest_rebuild(None, 1, None, None, None, None) == _lib.EINVAL
+    assert lib.tfmm_evaluate_forest(None, None, None, None, None, None) == _lib.EINVAL
