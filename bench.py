@@ -22,7 +22,8 @@ Prints one JSON line.  Besides the headline value it reports:
   variants and the conserving overhead;
 * a bounded serving run: Poisson-arriving solves of N log-uniform in
   [1e3, 5e5], p in {2,4,6}, theta in {0.4,0.6,0.8}, plus resident leapfrog
-  sessions; FP32-batched server against FP64 one solve at a time on the same
+  sessions; FP64 one solve at a time, mixed precision on several slots, and
+  the same slots with small requests solved together as forests, on the same
   trace: solves/s at capacity, p50/p99 latency at a fixed arrival rate;
 * the two-body setup of the paper's distance test: force error of orders 0
   and 1 with and without realignment;
@@ -167,41 +168,52 @@ def run_disk(args):
 
 def run_serving(args):
     """A bounded serving run on one trace: capacity (every solve queued at
-    once) and latency at a fixed Poisson rate, FP32-batched against FP64 one
-    solve at a time; resident sessions step beside the solves."""
+    once) and latency at a fixed Poisson rate for three servers: FP64 one
+    solve at a time, mixed precision on several slots with one request per
+    launch set, and the same slots solving the small requests of equal order
+    and variant together as forests; resident sessions step beside the
+    solves."""
     from paper_2107_07166_amd.serve import (Server, close_sessions, make_inputs, make_sessions, make_trace,
                                             summarize)
 
     trace = make_trace(args.serve_requests, rate=args.serve_rate)
     inputs = {r.rid: make_inputs(r) for r in trace}
     burst = [dataclasses.replace(r, arrival=0.0) for r in trace]
-    servers = (("fp64_one_at_a_time", "fp64", 1), ("mixed32_batched", "mixed32", args.serve_slots))
+    servers = (("fp64_one_at_a_time", "fp64", 1, 1), ("mixed32_slots", "mixed32", args.serve_slots, 1),
+               ("mixed32_forests", "mixed32", args.serve_slots, 256))
     res = {"requests": len(trace), "sessions": args.serve_sessions, "rate_per_s": args.serve_rate,
            "slots_batched": args.serve_slots,
            "trace": "Poisson arrivals; N log-uniform in [1e3, 5e5]; ball/Plummer/disk; p in {2,4,6}; "
                     "theta in {0.4,0.6,0.8}; standard/conserving; eps=1e-3"}
     samples = {}
-    for name, prec, k in servers:
-        # untimed pass first: the first launch of every kernel loads its code
-        Server(slots=k, precision=prec).run(burst, inputs=inputs)
-        recs = Server(slots=k, precision=prec).run(burst, inputs=inputs)
-        cap = summarize(recs)
+    for name, prec, k, sets in servers:
+        srv = Server(slots=k, precision=prec, batch_max_sets=sets)
         sessions = make_sessions(args.serve_sessions, precision=prec, n_max=5e4)
         try:
-            recs = Server(slots=k, precision=prec).run(trace, sessions=sessions, inputs=inputs)
+            # untimed pass first: the first launch of every kernel loads its
+            # code and the slots grow their buffers (a running server's state)
+            srv.run(burst, inputs=inputs)
+            recs = srv.run(burst, inputs=inputs)
+            cap = summarize(recs)
+            burst_batch = float(np.mean([r.batch for r in recs if r.kind == "solve"]))
+            recs = srv.run(trace, sessions=sessions, inputs=inputs)
         finally:
             close_sessions(sessions)
+            srv.close()
         s = summarize(recs)
-        res[name] = {"capacity_solves_per_s": cap["solves_per_s"], "solves_per_s": s["solves_per_s"],
+        res[name] = {"slots": k, "capacity_solves_per_s": cap["solves_per_s"],
+                     "capacity_mean_requests_per_launch_set": burst_batch, "solves_per_s": s["solves_per_s"],
                      "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "session_steps": s["session_steps"],
                      "step_p50_ms": s.get("step_p50_ms"), "step_p99_ms": s.get("step_p99_ms"),
-                     "errors": s["errors"]}
+                     "errors": s["errors"] + cap["errors"], "slot_retries": srv.retries}
         samples[name] = {r.rid: r.sample for r in recs if r.kind == "solve" and not r.error}
-    a, b = samples["mixed32_batched"], samples["fp64_one_at_a_time"]
+    a, b = samples["mixed32_forests"], samples["fp64_one_at_a_time"]
     errs = [_erms(a[i], b[i]) for i in a if i in b]
     res["mixed_vs_fp64_rms_per_request"] = {"max": max(errs), "median": float(np.median(errs))}
-    res["capacity_ratio"] = (res["mixed32_batched"]["capacity_solves_per_s"]
+    res["capacity_ratio"] = (res["mixed32_forests"]["capacity_solves_per_s"]
                              / res["fp64_one_at_a_time"]["capacity_solves_per_s"])
+    res["forest_capacity_gain"] = (res["mixed32_forests"]["capacity_solves_per_s"]
+                                   / res["mixed32_slots"]["capacity_solves_per_s"])
     return res
 
 

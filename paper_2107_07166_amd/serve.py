@@ -7,10 +7,12 @@ worker is free and the solve at the head of the queue fits in the device
 memory budget, it is admitted, so requests that arrive while others run start
 as slots and memory free up.  The budget counts what the slots really hold:
 a slot keeps its grow-only tree, its context's reusable blocks and its
-request buffers between solves, and a running solve reserves the larger of
-that and its footprint (tfmm_footprint_bytes plus the request buffers); the
-library part of the reservation is the slot context's budget, so a solve
-cannot outgrow it.  When the head solve does not fit, idle slots give their
+request buffers between solves, and a running solve reserves what the slot
+holds plus its footprint (tfmm_footprint_bytes plus the request buffers)
+when the budget has room for that, else the larger of the two; the library
+part of the reservation is the slot context's budget, so a solve cannot
+outgrow it (a reused tree that would, under the smaller reservation, gives
+its memory back and solves once more from scratch).  When the head solve does not fit, idle slots give their
 memory back, the largest first.  Solves go first; a
 session step takes a free worker only while no admissible solve is waiting,
 and session steps hold at most `step_slots` workers at once (default half),
@@ -20,13 +22,16 @@ libtfmm context, its own HIP stream (default priority) and one reusable tree
 the GPU.  Sessions keep particles and tree resident in HBM between steps and
 are re-queued after every step.
 
-Every solve is deterministic, so its result is the same alone and in a mix.
-Latency is arrival -> completion on the device.
+The slots live as long as the Server (created by the first run, kept with
+what they hold for later runs, released by close()).  Every solve is
+deterministic, so its result is the same alone and in a mix.  Latency is
+arrival -> completion on the device.
 """
 
 from __future__ import annotations
 
 import collections
+import itertools
 import math
 import threading
 import time
@@ -36,7 +41,7 @@ from typing import List, Optional
 import numpy as np
 import torch
 
-from . import api, generators
+from . import _lib, api, generators
 from .session import Session, footprint_bytes as session_footprint
 
 
@@ -69,6 +74,7 @@ class Record:
     done: float = math.nan
     footprint: int = 0
     worker: int = -1
+    batch: int = 1                       # requests solved together in one forest
     sample: Optional[np.ndarray] = None  # forces at the first `sample_k` particles
     full: Optional[np.ndarray] = None    # all forces (only when requested)
     error: str = ""
@@ -119,6 +125,7 @@ class _Worker:
         self.dev = torch.device("cuda", device)
         self.n_leaf = n_leaf
         self.tree: Optional[api.Tree] = None
+        self.retries = 0  # solves run again from scratch after outgrowing the reservation
         self.pos = None
         self.mass = None
         self.force = None
@@ -148,17 +155,43 @@ class _Worker:
             self.force = torch.empty((cap, 3), dtype=torch.float64, device=self.dev)
         return self.pos[:n], self.mass[:n], self.force[:n]
 
-    def solve(self, req: Request, hp, hm, precision: str):
+    def solve(self, reqs: List[Request], inputs, precision: str):
+        """Forces for one request, or for several as one forest (one set of
+        launches; every set's forces are those of the request solved alone).
+        Returns the force buffer and the request boundaries in it.  A tree
+        reused from earlier requests may need to grow past the slot's
+        reservation: then the slot gives its memory back and solves once more
+        from scratch."""
+        off = np.cumsum([0] + [r.n for r in reqs]).astype(np.int64)
+        for attempt in (0, 1):
+            try:
+                return self._solve(reqs, inputs, precision, off), off
+            except api.TfmmError as e:
+                if attempt or e.status != _lib.ENOMEM or (self.tree is None and self.ctx.bytes_held() == 0):
+                    raise
+                self.stream.synchronize()
+                self.shrink()
+                self.retries += 1
+
+    def _solve(self, reqs, inputs, precision, off):
+        r0 = reqs[0]
         with torch.cuda.stream(self.stream):
-            pos, mass, force = self._buffers(req.n)
-            pos.copy_(hp, non_blocking=True)
-            mass.copy_(hm, non_blocking=True)
+            pos, mass, force = self._buffers(int(off[-1]))
+            for r, a, b in zip(reqs, off[:-1], off[1:]):
+                hp, hm = inputs[r.rid]
+                pos[a:b].copy_(hp, non_blocking=True)
+                mass[a:b].copy_(hm, non_blocking=True)
+            sets = None if len(reqs) == 1 else off
             if self.tree is None:
-                self.tree = api.Tree(self.ctx, pos, mass, n_leaf=self.n_leaf)
+                self.tree = api.Tree(self.ctx, pos, mass, n_leaf=self.n_leaf, offsets=sets)
             else:
-                self.tree.rebuild(pos, mass)
-            self.tree.evaluate(p=req.p, theta=req.theta, eps=req.eps, variant=req.variant, precision=precision,
-                               out=force)
+                self.tree.rebuild(pos, mass, offsets=sets)
+            if sets is None:
+                self.tree.evaluate(p=r0.p, theta=r0.theta, eps=r0.eps, variant=r0.variant, precision=precision,
+                                   out=force)
+            else:
+                self.tree.evaluate_forest([r.theta for r in reqs], p=r0.p, eps=r0.eps, variant=r0.variant,
+                                          precision=precision, out=force)
             self.stream.synchronize()
         return force
 
@@ -171,7 +204,16 @@ class _Worker:
 class Server:
     def __init__(self, slots: int = 8, precision: str = "mixed32", budget_bytes: int = 64 << 30,
                  n_leaf: int = 32, device: int = 0, sample_k: int = 16, keep_full: bool = False,
-                 step_slots: Optional[int] = None):
+                 step_slots: Optional[int] = None, batch_max_n: int = 50000, batch_max_total: int = 1 << 20,
+                 batch_max_sets: int = 256):
+        """batch_max_n: requests of at most this many particles are solved
+        together as one forest (same p, variant and softening; theta may
+        differ), up to batch_max_total particles and batch_max_sets requests
+        per forest; batch_max_sets = 1 solves every request alone."""
+        self._workers = None  # the slots, created at the first run and kept until close()
+        self.batch_max_n = int(batch_max_n)
+        self.batch_max_total = int(batch_max_total)
+        self.batch_max_sets = max(1, min(int(batch_max_sets), 4096))
         self.slots = int(slots)
         # most workers session steps may hold at once (the rest stay ready for solves)
         self.step_slots = max(1, self.slots // 2) if step_slots is None else max(1, int(step_slots))
@@ -182,10 +224,27 @@ class Server:
         self.sample_k = int(sample_k)
         self.keep_full = bool(keep_full)
 
-    def footprint(self, req: Request) -> int:
+    def footprint(self, req: Request, n: Optional[int] = None) -> int:
         """Device bytes a solve may need: the library's estimate for its tree
-        plus its request buffers."""
-        return api.footprint_bytes(req.n, req.p, self.n_leaf, self.precision) + STATE_BYTES * max(req.n, 1024)
+        plus its request buffers (n: the particles of a whole forest)."""
+        n = req.n if n is None else n
+        return api.footprint_bytes(n, req.p, self.n_leaf, self.precision) + STATE_BYTES * max(n, 1024)
+
+    def _batch(self, pending, room: int) -> List[Request]:
+        """The head request and the waiting requests that can share its forest
+        (queue order), within the batch limits and `room` bytes."""
+        head = pending[0]
+        batch, tot = [head], head.n
+        if self.batch_max_sets == 1 or head.n > self.batch_max_n:
+            return batch
+        for r in itertools.islice(pending, 1, None):
+            if len(batch) >= self.batch_max_sets:
+                break
+            if (r.n <= self.batch_max_n and (r.p, r.variant, r.eps) == (head.p, head.variant, head.eps)
+                    and tot + r.n <= self.batch_max_total and self.footprint(head, tot + r.n) <= room):
+                batch.append(r)
+                tot += r.n
+        return batch
 
     def run(self, requests: List[Request], sessions: Optional[List[Session]] = None,
             session_dt: float = 1e-3, inputs=None) -> List[Record]:
@@ -194,7 +253,9 @@ class Server:
         requests = sorted(requests, key=lambda r: r.arrival)
         inputs = inputs if inputs is not None else {r.rid: make_inputs(r) for r in requests}
         sessions = sessions or []
-        workers = [_Worker(i, self.device, self.n_leaf) for i in range(self.slots)]
+        if self._workers is None:
+            self._workers = [_Worker(i, self.device, self.n_leaf) for i in range(self.slots)]
+        workers = self._workers
         lock = threading.Condition()
         pending = collections.deque()      # solves, FIFO
         steps_q = collections.deque()      # session steps, FIFO
@@ -226,30 +287,35 @@ class Server:
         state["next_step_id"] += len(sessions)
         busy_sessions = set()
 
-        def execute(wid: int, req: Request, admitted: float, fp: int):
-            rec = Record(req.rid, req.kind, req.n, req.p, req.theta, req.variant, req.arrival, admitted,
-                         footprint=fp, worker=wid)
+        def execute(wid: int, reqs: List[Request], admitted: float, fp: int):
+            req = reqs[0]
+            recs = [Record(r.rid, r.kind, r.n, r.p, r.theta, r.variant, r.arrival, admitted, footprint=fp,
+                           worker=wid, batch=len(reqs)) for r in reqs]
             try:
                 if req.kind == "solve":
-                    hp, hm = inputs[req.rid]
-                    f = workers[wid].solve(req, hp, hm, self.precision)
-                    rec.sample = f[: self.sample_k].cpu().numpy()
-                    if self.keep_full:
-                        rec.full = f.cpu().numpy()
+                    f, off = workers[wid].solve(reqs, inputs, self.precision)
+                    for rec, a, b in zip(recs, off[:-1], off[1:]):
+                        rec.sample = f[a: a + min(self.sample_k, b - a)].cpu().numpy()
+                        if self.keep_full:
+                            rec.full = f[a:b].cpu().numpy()
                 else:
                     s = sessions[req.session]
                     s.step(req.dt, 1)
-                    rec.sample = s.force[: self.sample_k].cpu().numpy()
+                    recs[0].sample = s.force[: self.sample_k].cpu().numpy()
             except Exception as e:  # recorded, the server keeps going
-                rec.error = repr(e)
-            rec.done = time.perf_counter() - t0
+                for rec in recs:
+                    rec.error = repr(e)
+            done = time.perf_counter() - t0
+            for rec in recs:
+                rec.done = done
+            rec = recs[0]
             with lock:
-                records.append(rec)
+                records.extend(recs)
                 if req.kind == "solve":
                     held = workers[wid].held()
                     if held > reserved.pop(wid):
                         self.over_reservation += 1
-                    state["solves_left"] -= 1
+                    state["solves_left"] -= len(reqs)
                 else:
                     busy_sessions.discard(req.session)
                     if state["solves_left"] > 0:
@@ -278,20 +344,33 @@ class Server:
                                               error="footprint exceeds the budget"))
                         state["solves_left"] -= 1
                         continue
-                    lib_fp = api.footprint_bytes(req.n, req.p, self.n_leaf, self.precision)
+                    batch = self._batch(pending, self.budget - sess_bytes)
+                    n_batch = sum(r.n for r in batch)
+                    fp = self.footprint(req, n_batch)
+                    lib_fp = api.footprint_bytes(n_batch, req.p, self.n_leaf, self.precision)
                     free = state["free_workers"]
 
-                    def need_of(v):
-                        # bytes slot v reserves for this solve: the larger of what it
-                        # holds and the footprint, for the library and the buffers
-                        lib_need = max(workers[v].ctx.bytes_held(), lib_fp)
-                        return lib_need, lib_need + max(workers[v].tensor_bytes(), fp - lib_fp)
+                    def need_of(v, roomy=False):
+                        # bytes slot v reserves for this solve, for the library and the
+                        # buffers: the larger of what it holds and the footprint (tight;
+                        # a reused tree that must grow past it solves again from scratch),
+                        # or what it holds plus the footprint (roomy: room for every
+                        # grow-only buffer to grow)
+                        held_lib, held_buf = workers[v].ctx.bytes_held(), workers[v].tensor_bytes()
+                        if roomy:
+                            lib_need = held_lib + lib_fp
+                            return lib_need, lib_need + held_buf + fp - lib_fp
+                        lib_need = max(held_lib, lib_fp)
+                        return lib_need, lib_need + max(held_buf, fp - lib_fp)
 
                     # the free slot that grows least (ties: the one holding most)
                     wid = min(free, key=lambda v: (need_of(v)[1] - workers[v].held(), -workers[v].held()))
                     w = workers[wid]
-                    lib_need, need = need_of(wid)
+                    lib_need, need = need_of(wid, roomy=True)
                     total = total_bytes(exclude=wid) + need
+                    if total > self.budget:
+                        lib_need, need = need_of(wid)
+                        total = total_bytes(exclude=wid) + need
                     if total > self.budget:
                         # give back what idle slots keep, the largest first, then the chosen
                         # slot's own leftovers (its buffers may exceed what this solve needs)
@@ -303,12 +382,13 @@ class Server:
                                 break
                     if total > self.budget:
                         break  # wait for running solves: alone, the solve fits (checked above)
-                    pending.popleft()
+                    for r in batch:
+                        pending.remove(r)
                     reserved[wid] = need
                     w.ctx.set_budget(lib_need)
                     self.peak_reserved = max(self.peak_reserved, total)
                     free.remove(wid)
-                    th = threading.Thread(target=execute, args=(wid, req, now, fp), daemon=True)
+                    th = threading.Thread(target=execute, args=(wid, batch, now, fp), daemon=True)
                     threads.append(th)
                     th.start()
                 # session steps fill the workers no admissible solve is waiting for
@@ -322,7 +402,7 @@ class Server:
                         continue
                     busy_sessions.add(req.session)
                     wid = state["free_workers"].pop()
-                    th = threading.Thread(target=execute, args=(wid, req, now, 0), daemon=True)
+                    th = threading.Thread(target=execute, args=(wid, [req], now, 0), daemon=True)
                     threads.append(th)
                     th.start()
                 if state["solves_left"] <= 0 and len(state["free_workers"]) == self.slots:
@@ -333,9 +413,21 @@ class Server:
                 lock.wait(timeout=wait if wait is not None else 0.05)
         for th in threads:
             th.join()
-        for w in workers:
-            w.close()
+        self.retries = sum(w.retries for w in workers)
         return sorted(records, key=lambda r: (r.kind, r.rid))
+
+    def close(self) -> None:
+        """Release the slots (their contexts, trees and buffers)."""
+        if self._workers is not None:
+            for w in self._workers:
+                w.close()
+            self._workers = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def make_sessions(count: int = 16, seed: int = generators.SEED_BASE + 4, n_min: float = 1e3, n_max: float = 5e5,

@@ -106,24 +106,29 @@ def test_distance_test_setup(ctx, sep):
 
 
 def test_served_requests_match_oracle(ctx):
-    """Three requests served in a mix with others (four slots, two sessions)
+    """Three requests served in a mix with others (four slots, two sessions),
+    each solved in a forest with a companion of the same order and variant,
     return the oracle's forces for their own particle sets."""
     from paper_2107_07166_amd import generators
     from paper_2107_07166_amd.serve import Request, Server, close_sessions, make_sessions, make_trace
     mine = [Request(rid=0, arrival=0.0, n=12000, gen="plummer", seed=501, p=4, theta=0.6, variant="conserving"),
             Request(rid=1, arrival=0.0, n=7000, gen="disk", seed=502, p=6, theta=0.8, variant="standard"),
             Request(rid=2, arrival=0.0, n=3000, gen="ball", seed=503, p=2, theta=0.4, variant="conserving")]
+    mates = [Request(rid=10 + k, arrival=0.0, n=2000 + 500 * k, gen="ball", seed=510 + k, p=r.p, theta=0.5,
+                     variant=r.variant) for k, r in enumerate(mine)]
+    mine_and_mates = [x for pair in zip(mine, mates) for x in pair]
     others = make_trace(10, rate=400.0, seed=9, n_min=1e3, n_max=2e4)
     for k, r in enumerate(others):
         r.rid = 100 + k
     sessions = make_sessions(2, n_min=2e3, n_max=6e3)
     try:
         srv = Server(slots=4, keep_full=True)
-        recs = srv.run(mine + others, sessions=sessions)
+        recs = srv.run(mine_and_mates + others, sessions=sessions)
     finally:
         close_sessions(sessions)
     got = {r.rid: r for r in recs if r.kind == "solve"}
     assert all(not r.error for r in recs)
+    assert all(got[r.rid].batch > 1 for r in mine), [got[r.rid].batch for r in mine]
     for r in mine:
         pos, m = generators.generate(r.gen, r.n, r.seed)
         ref = oracle.Tree(pos, m, n_leaf=srv.n_leaf, theta=r.theta).forces(r.p, r.eps, r.variant)

@@ -1,4 +1,5 @@
-"""Serving: continuous admission, memory budget, sessions, alone == in the mix."""
+"""Serving: continuous admission, memory budget, sessions, forests of small
+requests, alone == in the mix."""
 
 import numpy as np
 import pytest
@@ -42,6 +43,8 @@ def test_alone_equals_in_the_mix(gpu):
     got = {r.rid: r.full for r in recs if r.kind == "solve"}
     assert all(not r.error for r in recs)
     assert sum(1 for r in recs if r.kind == "step") > 0
+    # requests of the same order and variant were solved together in forests
+    assert max(r.batch for r in recs if r.kind == "solve") > 1
     for r in base:
         assert np.array_equal(got[r.rid], alone[r.rid]), r.rid
 
@@ -51,13 +54,14 @@ def test_memory_budget_queues_and_rejects(gpu):
     reqs = _reqs()
     srv = Server(slots=4)
     fps = sorted(srv.footprint(r) for r in reqs)
-    # room for the largest request only: everything is served, one at a time
+    # room for the largest request only: everything is served, one launch
+    # set at a time (a forest of small requests that fits counts as one)
     srv_one = Server(slots=4, budget_bytes=fps[-1])
     recs = srv_one.run(reqs)
     assert all(not r.error for r in recs) and len(recs) == len(reqs)
-    spans = sorted((r.admitted, r.done) for r in recs)
+    spans = sorted(set((r.admitted, r.done) for r in recs))
     for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
-        assert a1 >= d0 - 1e-6  # never two at once under this budget
+        assert a1 >= d0 - 1e-6  # never two launch sets at once under this budget
     # a budget below the largest footprint rejects it and serves the rest
     recs = Server(slots=4, budget_bytes=fps[-2]).run(reqs)
     bad = [r for r in recs if r.error]
@@ -88,3 +92,19 @@ def test_memory_budget_counts_what_slots_hold(gpu):
     free = {r.rid: r.full for r in Server(slots=4, keep_full=True).run(reqs)}
     for r in recs:
         assert np.array_equal(r.full, free[r.rid]), r.rid
+
+
+def test_forest_batches_equal_requests_alone(gpu):
+    """A burst of small requests: with forests (many requests per launch set)
+    and without (batch_max_sets=1) every request gets the same forces."""
+    from paper_2107_07166_amd.serve import Server, make_trace
+    reqs = make_trace(40, rate=1e6, seed=21, n_min=500, n_max=2e4)
+    for r in reqs:
+        r.arrival = 0.0
+    batched = Server(slots=2, keep_full=True).run(reqs)
+    single = {r.rid: r.full for r in Server(slots=2, keep_full=True, batch_max_sets=1).run(reqs)}
+    assert all(not r.error for r in batched)
+    assert max(r.batch for r in batched) >= 4
+    assert all(r.batch == 1 for r in Server(slots=1, batch_max_sets=1).run(reqs[:3]))
+    for r in batched:
+        assert np.array_equal(r.full, single[r.rid]), (r.rid, r.batch)
