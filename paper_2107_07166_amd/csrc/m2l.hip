@@ -231,9 +231,13 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
 // (p = 6, theta = 0.8) the far field took 4.54 ms in four launches against
 // 4.81 ms in two (P with Q'_x, Q'_y with Q'_z; 264 registers) and 4.97 ms in
 // one; reading the moments where the contraction uses them instead of into
-// registers first was slower in every split.  At p = 5 the fused kernel (285
-// registers) beats four launches (2.7 against 3.0 ms on 2^20 Plummer
-// particles).
+// registers first was slower in every split.  Computing the g-derivatives once
+// per pair and sharing them through LDS (a workgroup of four wavefronts per
+// two targets: the first builds the tensors of a block of pairs, then each
+// contracts one polynomial; 256 registers with spills, two waves per SIMD)
+// gave the same locals bit for bit but took 6.5 ms against 4.5.  At p = 5 the
+// fused kernel (285 registers) beats four launches (2.7 against 3.0 ms on 2^20
+// Plummer particles).
 constexpr int kConsSplitP = 6;
 
 template <int P, int VAR, typename T>
