@@ -107,6 +107,25 @@ __device__ __forceinline__ void consume(const typename Vec4<T>::type* src, int n
     }
 }
 
+// One staged chunk for a lane's R targets: FP32 (or FP64) partial sums of the
+// chunk, then added to the lane's FP64 accumulators (inactive lanes add zeros).
+template <typename T, bool SAFE, bool POT, int R>
+__device__ __forceinline__ void chunk(bool act, const typename Vec4<T>::type* src, int ng, const T* tx,
+                                      const T* ty, const T* tz, T eps2, double* ax, double* ay, double* az,
+                                      double* ap) {
+    T sx[R], sy[R], sz[R], sp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sx[r] = sy[r] = sz[r] = sp[r] = T(0);
+    if (act) consume<T, SAFE, POT, R>(src, ng, tx, ty, tz, eps2, sx, sy, sz, sp);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        ax[r] += (double)sx[r];
+        ay[r] += (double)sy[r];
+        az[r] += (double)sz[r];
+        if constexpr (POT) ap[r] += (double)sp[r];
+    }
+}
+
 // POT: the near-field potential too (-sum m_b (r^2 + eps^2)^(-1/2), the
 // particle's own term included when eps > 0; the caller removes it).
 template <typename T, bool SAFE, bool POT>
@@ -188,22 +207,28 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
 
             for (int c0 = 0; c0 < total; c0 += CH) {
                 const int cnt = (total - c0) < CH ? (total - c0) : CH;
-                // stage: lane takes sources c0 + lane + 64 k; entry by binary search
+                // stage: lane takes the consecutive sources c0 + SPL lane + k; the
+                // entry of the first by binary search, then at most one step per
+                // source (every entry holds at least one source)
                 int idx[SPL], ent[SPL];
-#pragma unroll
-                for (int k = 0; k < SPL; ++k) {
-                    const int sidx = c0 + lane + kWave * k;
+                {
+                    const int s0 = c0 + SPL * lane;
                     int lo = 0;
 #pragma unroll
                     for (int st = kWave / 2; st > 0; st >>= 1)
-                        if (e_start[lo + st] <= sidx) lo += st;
-                    ent[k] = lo;
-                    idx[k] = e_first[lo] + (sidx - e_start[lo]);
+                        if (e_start[lo + st] <= s0) lo += st;
+#pragma unroll
+                    for (int k = 0; k < SPL; ++k) {
+                        const int sidx = s0 + k;
+                        if (k > 0 && lo + 1 < kWave && e_start[lo + 1] <= sidx) ++lo;
+                        ent[k] = lo;
+                        idx[k] = e_first[lo] + (sidx - e_start[lo]);
+                    }
                 }
                 V4 v[SPL];
 #pragma unroll
                 for (int k = 0; k < SPL; ++k)
-                    if (lane + kWave * k < cnt) v[k] = P[idx[k]];
+                    if (SPL * lane + k < cnt) v[k] = P[idx[k]];
                 // the chunk padded to a multiple of G; group g owns sources
                 // g, g + G, ..., stored contiguously at g * gs (gs odd, so the
                 // groups' reads of one step fall in distinct LDS banks)
@@ -215,7 +240,7 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                 const uint32_t gm = (uint32_t)__builtin_amdgcn_readfirstlane((65536 + G - 1) / G);
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
-                    const int c = lane + kWave * k;
+                    const int c = SPL * lane + k;
                     if (c < cnt) {
                         V4 w;
                         w.x = (T)((double)v[k].x + e_off[0][ent[k]]);
@@ -232,24 +257,12 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
                     stage[(c - q * G) * gs + q] = pad;
                 }
                 __syncthreads();
-                T sx[RMAX], sy[RMAX], sz[RMAX], sp[RMAX];
-#pragma unroll
-                for (int r = 0; r < RMAX; ++r) sx[r] = sy[r] = sz[r] = sp[r] = T(0);
-                if (act) {
-                    const V4* src = stage + g * gs;
-                    switch (R) {
-                        case 1: consume<T, SAFE, POT, 1>(src, ng, tx, ty, tz, eps2, sx, sy, sz, sp); break;
-                        case 2: consume<T, SAFE, POT, 2>(src, ng, tx, ty, tz, eps2, sx, sy, sz, sp); break;
-                        case 3: consume<T, SAFE, POT, 3>(src, ng, tx, ty, tz, eps2, sx, sy, sz, sp); break;
-                        default: consume<T, SAFE, POT, 4>(src, ng, tx, ty, tz, eps2, sx, sy, sz, sp); break;
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < RMAX; ++r) {
-                    ax[r] += (double)sx[r];
-                    ay[r] += (double)sy[r];
-                    az[r] += (double)sz[r];
-                    if constexpr (POT) ap[r] += (double)sp[r];
+                const V4* src = stage + g * gs;
+                switch (R) {
+                    case 1: chunk<T, SAFE, POT, 1>(act, src, ng, tx, ty, tz, eps2, ax, ay, az, ap); break;
+                    case 2: chunk<T, SAFE, POT, 2>(act, src, ng, tx, ty, tz, eps2, ax, ay, az, ap); break;
+                    case 3: chunk<T, SAFE, POT, 3>(act, src, ng, tx, ty, tz, eps2, ax, ay, az, ap); break;
+                    default: chunk<T, SAFE, POT, 4>(act, src, ng, tx, ty, tz, eps2, ax, ay, az, ap); break;
                 }
                 __syncthreads();
             }
