@@ -196,16 +196,23 @@ def run_serving(args):
             recs = srv.run(burst, inputs=inputs)
             cap = summarize(recs)
             burst_batch = float(np.mean([r.batch for r in recs if r.kind == "solve"]))
-            recs = srv.run(trace, sessions=sessions, inputs=inputs)
+            # the latency trace three times: one 64-request p99 is close to the
+            # slowest request, and a stall of the host now and then moves it
+            reps = []
+            for _ in range(args.serve_reps):
+                recs = srv.run(trace, sessions=sessions, inputs=inputs)
+                reps.append(summarize(recs))
         finally:
             close_sessions(sessions)
             srv.close()
-        s = summarize(recs)
+        med = {key: float(np.median([r[key] for r in reps])) for key in ("solves_per_s", "p50_ms", "p99_ms")}
         res[name] = {"slots": k, "capacity_solves_per_s": cap["solves_per_s"],
-                     "capacity_mean_requests_per_launch_set": burst_batch, "solves_per_s": s["solves_per_s"],
-                     "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "session_steps": s["session_steps"],
-                     "step_p50_ms": s.get("step_p50_ms"), "step_p99_ms": s.get("step_p99_ms"),
-                     "errors": s["errors"] + cap["errors"], "slot_retries": srv.retries}
+                     "capacity_mean_requests_per_launch_set": burst_batch, "solves_per_s": med["solves_per_s"],
+                     "p50_ms": med["p50_ms"], "p99_ms": med["p99_ms"],
+                     "p99_ms_each_run": [r["p99_ms"] for r in reps],
+                     "session_steps": int(np.median([r["session_steps"] for r in reps])),
+                     "step_p50_ms": reps[-1].get("step_p50_ms"), "step_p99_ms": reps[-1].get("step_p99_ms"),
+                     "errors": sum(r["errors"] for r in reps) + cap["errors"], "slot_retries": srv.retries}
         samples[name] = {r.rid: r.sample for r in recs if r.kind == "solve" and not r.error}
     a, b = samples["mixed32_forests"], samples["fp64_one_at_a_time"]
     errs = [_erms(a[i], b[i]) for i in a if i in b]
@@ -275,6 +282,7 @@ def main():
     ap.add_argument("--serve-sessions", type=int, default=4)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-rate", type=float, default=100.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-reps", type=int, default=3, help="runs of the latency trace per server (medians)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "

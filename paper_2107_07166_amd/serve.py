@@ -16,7 +16,9 @@ its memory back and solves once more from scratch).  When the head solve does no
 memory back, the largest first.  Solves go first; a
 session step takes a free worker only while no admissible solve is waiting,
 and session steps hold at most `step_slots` workers at once (default half),
-so an arriving solve finds a worker ready.  Every worker owns a
+so an arriving solve finds a worker ready; while any solve runs, no new
+session step starts (`steps_beside_solves`, default 0), since steps would
+share the device with the solves and stretch their latency.  Every worker owns a
 libtfmm context, its own HIP stream (default priority) and one reusable tree
 (device buffers are grow-only), so the work of several requests overlaps on
 the GPU.  Sessions keep particles and tree resident in HBM between steps and
@@ -205,7 +207,7 @@ class Server:
     def __init__(self, slots: int = 8, precision: str = "mixed32", budget_bytes: int = 64 << 30,
                  n_leaf: int = 32, device: int = 0, sample_k: int = 16, keep_full: bool = False,
                  step_slots: Optional[int] = None, batch_max_n: int = 50000, batch_max_total: int = 1 << 20,
-                 batch_max_sets: int = 256):
+                 batch_max_sets: int = 256, steps_beside_solves: int = 0):
         """batch_max_n: requests of at most this many particles are solved
         together as one forest (same p, variant and softening; theta may
         differ), up to batch_max_total particles and batch_max_sets requests
@@ -217,6 +219,9 @@ class Server:
         self.slots = int(slots)
         # most workers session steps may hold at once (the rest stay ready for solves)
         self.step_slots = max(1, self.slots // 2) if step_slots is None else max(1, int(step_slots))
+        # session steps are background work: while a solve runs, at most this
+        # many of them may start (they share the device with the solves)
+        self.steps_beside_solves = max(0, int(steps_beside_solves))
         self.precision = precision
         self.budget = int(budget_bytes)
         self.n_leaf = int(n_leaf)
@@ -301,7 +306,8 @@ class Server:
                 else:
                     s = sessions[req.session]
                     s.step(req.dt, 1)
-                    recs[0].sample = s.force[: self.sample_k].cpu().numpy()
+                    with s._stream_ctx():  # the copy waits for the step on the session's stream
+                        recs[0].sample = s.force[: self.sample_k].cpu().numpy()
             except Exception as e:  # recorded, the server keeps going
                 for rec in recs:
                     rec.error = repr(e)
@@ -394,7 +400,8 @@ class Server:
                 # session steps fill the workers no admissible solve is waiting for
                 # (here either no solve waits or the head solve does not fit yet)
                 rounds = len(steps_q)
-                while steps_q and state["free_workers"] and rounds > 0 and len(busy_sessions) < self.step_slots:
+                step_cap = self.step_slots if not reserved else min(self.step_slots, self.steps_beside_solves)
+                while steps_q and state["free_workers"] and rounds > 0 and len(busy_sessions) < step_cap:
                     rounds -= 1
                     req = steps_q.popleft()
                     if req.session in busy_sessions:
