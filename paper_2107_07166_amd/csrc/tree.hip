@@ -395,7 +395,8 @@ __global__ __launch_bounds__(TB) void node_create_kernel(NodeArrays nd, int64_t 
                                                          const uint8_t* __restrict__ lam,
                                                          const uint32_t* __restrict__ boff, int64_t nblk,
                                                          const TreeHeader* __restrict__ h,
-                                                         int32_t* __restrict__ leaf_of) {
+                                                         int32_t* __restrict__ leaf_of,
+                                                         int32_t* __restrict__ leaves) {
     __shared__ unsigned long long bal[TB / kWave][NSLOT];
     __shared__ uint32_t woff[TB / kWave][NSLOT];
     __shared__ int64_t sLB[kLevels + 2];
@@ -409,10 +410,14 @@ __global__ __launch_bounds__(TB) void node_create_kernel(NodeArrays nd, int64_t 
         const unsigned long long bl = __ballot(a <= l && l <= b);
         if (lane == 0) bal[wv][l] = bl;
     }
+    {
+        const unsigned long long bl = __ballot(a <= b);  // a leaf starts here (at level b)
+        if (lane == 0) bal[wv][NSLOT - 1] = bl;
+    }
     if (tid < kLevels + 2) sLB[tid] = h->LB[tid];
-    if (tid <= kLevels) sboff[tid] = boff[(int64_t)tid * nblk + blockIdx.x];
+    if (tid < NSLOT) sboff[tid] = boff[(int64_t)tid * nblk + blockIdx.x];
     __syncthreads();
-    if (tid <= kLevels) {
+    if (tid < NSLOT) {
         uint32_t run = 0;
 #pragma unroll
         for (int q = 0; q < TB / kWave; ++q) {
@@ -428,6 +433,8 @@ __global__ __launch_bounds__(TB) void node_create_kernel(NodeArrays nd, int64_t 
     };
     auto incl = [&](int l) -> int64_t { return rank(l) + ((a <= l && l <= b) ? 1 : 0); };
     leaf_of[j] = (int32_t)(sLB[b] + incl(b) - 1);
+    // the list of leaves, in particle order (every user takes each leaf on its own)
+    if (a <= b) leaves[rank(NSLOT - 1)] = (int32_t)(sLB[b] + rank(b));
     for (int l = a; l <= b; ++l) {
         const int64_t id = sLB[l] + rank(l);
         nd.level[id] = l;
@@ -462,19 +469,6 @@ __global__ __launch_bounds__(TB) void node_finish_kernel(NodeArrays nd, int64_t 
     nd.count[c] = (int32_t)(end - nd.first[c]);
     if (P >= 0 && (c + 1 >= h->LB[l + 1] || nd.parent[c + 1] != P))
         nd.nchild[P] = (int32_t)(c - nd.child_first[P] + 1);
-}
-
-__global__ __launch_bounds__(TB) void leaf_flag_kernel(const int32_t* __restrict__ nchild, int64_t nn,
-                                                       uint32_t* __restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i < nn) flag[i] = nchild[i] == 0 ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(TB) void leaf_compact_kernel(const uint32_t* __restrict__ flag,
-                                                          const uint32_t* __restrict__ excl, int64_t nn,
-                                                          int32_t* __restrict__ leaves) {
-    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i < nn && flag[i]) leaves[excl[i]] = (int32_t)i;
 }
 
 // Mass and centre of mass of the leaves (all levels in one launch).
@@ -771,27 +765,17 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
     const int64_t nn = t.n_nodes;
     ensure_nodes(t, std::max<int64_t>(nn, 1), 0, s);
     NodeArrays nd = node_arrays(t);
+    t.leaves.ensure(ctx, (size_t)std::max<int64_t>(t.n_leaves, 1) * 4);
     hipLaunchKernelGGL(node_create_kernel, dim3((unsigned)nblk), dim3(TB), 0, s, nd, n,
                        (const uint64_t*)t.keys.as<uint64_t>(), (const uint8_t*)t.lvlb.as<uint8_t>(),
                        (const uint8_t*)lam, (const uint32_t*)cnt, nblk, (const TreeHeader*)hdr,
-                       t.leaf_of.as<int32_t>());
+                       t.leaf_of.as<int32_t>(), t.leaves.as<int32_t>());
     TFMM_LAUNCHED();
     hipLaunchKernelGGL(node_finish_kernel, dim3(grid(nn)), dim3(TB), 0, s, nd, nn, n, (const TreeHeader*)hdr);
     TFMM_LAUNCHED();
-
-    // leaves, in node order
     t.flags.ensure(ctx, (size_t)std::max<int64_t>(n, nn) * 4 * 2);
     t.scratch.ensure(ctx, scan_scratch_bytes(std::max<int64_t>(n, nn)) + 256);
-    uint32_t* flag = t.flags.as<uint32_t>();
-    uint32_t* excl = flag + std::max<int64_t>(n, nn);
     uint32_t* total = reinterpret_cast<uint32_t*>(t.scratch2.as<char>() + sizeof(TreeHeader));
-    hipLaunchKernelGGL(leaf_flag_kernel, dim3(grid(nn)), dim3(TB), 0, s, nd.nchild, nn, flag);
-    TFMM_LAUNCHED();
-    exclusive_scan_u32(flag, excl, nn, t.scratch.p, total, ctx->dev_err, s);
-    t.leaves.ensure(ctx, (size_t)std::max<int64_t>(t.n_leaves, 1) * 4);
-    hipLaunchKernelGGL(leaf_compact_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)flag,
-                       (const uint32_t*)excl, nn, t.leaves.as<int32_t>());
-    TFMM_LAUNCHED();
 
     // geometry: leaves, then inner nodes level by level, deepest first; the
     // top levels (at most kTopNodes nodes together) in a single block

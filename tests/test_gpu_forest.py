@@ -216,3 +216,38 @@ def test_forest_argument_errors(ctx):
                            f.data_ptr(), 1e-3, 1, 0, None)
     assert rc == _lib.EINVAL and "one particle set" in lib.tfmm_last_error(ctx.handle).decode()
     t.close()
+
+
+def test_forest_of_many_small_sets(ctx):
+    """4096 sets (the limit; the sort by set takes two 8-bit passes) of 1 to
+    40 particles: every set alone and in the forest give the same forces."""
+    from paper_2107_07166_amd import api
+    rng = np.random.default_rng(77)
+    sizes = rng.integers(1, 41, 4096)
+    specs = [("ball", int(n), 1000 + k, float(rng.choice([0.3, 0.5, 0.7]))) for k, n in enumerate(sizes)]
+    parts, off, pos, mass, thetas = _sets(specs)
+    kw = dict(p=3, eps=1e-3, variant="conserving", precision="mixed32")
+    t = api.Tree(ctx, _dev(pos), _dev(mass), n_leaf=N_LEAF, offsets=off)
+    f = t.evaluate_forest(thetas, **kw).cpu().numpy()
+    assert t.info()["nodes"] >= 4096
+    t.close()
+    for k in rng.choice(4096, 24, replace=False):
+        (p, m), th = parts[k], thetas[k]
+        one = api.Tree(ctx, _dev(p), _dev(m), n_leaf=N_LEAF)
+        fa = one.evaluate(theta=float(th), **kw).cpu().numpy()
+        one.close()
+        assert np.array_equal(f[off[k]:off[k + 1]], fa), k
+
+
+def test_forest_with_scalar_degree(ctx):
+    """The scalar-degree knob (locals of order K + 1) on a forest equals the
+    sets alone."""
+    from paper_2107_07166_amd import api
+    parts, off, pos, mass, thetas = _sets(SETS[:6])
+    kw = dict(p=3, eps=1e-3, variant="conserving", precision="fp64", scalar_degree=4)
+    alone = _alone(ctx, parts, thetas, **kw)
+    t = api.Tree(ctx, _dev(pos), _dev(mass), n_leaf=N_LEAF, offsets=off)
+    f = t.evaluate_forest(thetas, **kw).cpu().numpy()
+    t.close()
+    for k, (fa, *_) in enumerate(alone):
+        assert np.array_equal(f[off[k]:off[k + 1]], fa), k
