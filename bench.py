@@ -53,8 +53,8 @@ P2P_FLOP_PER_PAIR = 20        # per directed particle interaction (convention)
 # factor a plain copy of known size reads) and WRITE_SIZE (x1); see
 # profiles/p2p_plummer1m_counters.md.  Valid only for the kernel source the
 # counters were taken with (first 16 hex digits of its sha256).
-P2P_TRAFFIC_BYTES = (2 * 225455 + 32009) * 1024
-P2P_TRAFFIC_SOURCE_SHA = "d8db2db14a6c4d73"
+P2P_TRAFFIC_BYTES = (2 * 227115 + 32009) * 1024
+P2P_TRAFFIC_SOURCE_SHA = "8eaba0fa02df4bfb"
 
 
 def _p2p_traffic():
