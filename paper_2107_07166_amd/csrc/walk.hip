@@ -631,12 +631,30 @@ __global__ __launch_bounds__(TB) void node_items_kernel(const uint32_t* __restri
     prows[i] = n > 1u ? n * (uint32_t)count[i] : 0u;
 }
 
-// One thread per near entry; the entry that starts an item writes it.
-__global__ __launch_bounds__(TB) void item_write_kernel(const uint32_t* __restrict__ tgt,
-                                                        const uint32_t* __restrict__ P,
-                                                        const uint32_t* __restrict__ off, int64_t ne,
+// One thread per item (grid-stride over the item count on the device): its
+// leaf is the last node whose first item is at or before it (nodes without
+// items share their first-item index with the next node); item k of a list
+// starts at its first entry q with P[q] - P[q0] >= k kItemSources (P grows
+// along a list, by at most kItemSources per entry, so every item has a first
+// entry), found by binary search, and ends where item k + 1 starts.
+__device__ __forceinline__ uint32_t item_start(const uint32_t* __restrict__ P, uint32_t q0, uint32_t q1,
+                                               uint32_t k) {
+    if (k == 0u) return q0;
+    const uint32_t p0 = P[q0], want = k * kItemSources;
+    uint32_t lo = q0 + 1u, hi = q1 - 1u;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2u;
+        if (P[mid] - p0 >= want) hi = mid;
+        else lo = mid + 1u;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(TB) void item_write_kernel(const uint32_t* __restrict__ P,
+                                                        const uint32_t* __restrict__ off, int64_t nn,
                                                         const uint32_t* __restrict__ nitems,
                                                         const uint32_t* __restrict__ item0,
+                                                        const uint32_t* __restrict__ n_items,
                                                         const uint32_t* __restrict__ pbase,
                                                         const int32_t* __restrict__ count,
                                                         int32_t* __restrict__ it_leaf, uint32_t* __restrict__ it_q0,
@@ -645,23 +663,26 @@ __global__ __launch_bounds__(TB) void item_write_kernel(const uint32_t* __restri
                                                         int32_t* __restrict__ leaf_nitems,
                                                         int32_t* __restrict__ multi_leaf,
                                                         uint32_t* __restrict__ multi_count) {
-    const int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (q >= ne) return;
-    const uint32_t L = tgt[q];
-    const uint32_t q0 = off[L];
-    const uint32_t k = (P[q] - P[q0]) / kItemSources;
-    if ((uint32_t)q != q0 && k == (P[q - 1] - P[q0]) / kItemSources) return;
-    const uint32_t n = nitems[L];
-    const uint32_t i = item0[L] + k;
-    it_leaf[i] = (int32_t)L;
-    it_q0[i] = (uint32_t)q;
-    if (k > 0u) it_q1[i - 1] = (uint32_t)q;
-    if (k + 1u == n) it_q1[i] = off[L + 1];
-    it_pbase[i] = n > 1u ? pbase[L] + k * (uint32_t)count[L] : 0u;
-    if (k == 0u) {
-        leaf_item0[L] = (int32_t)item0[L];
-        leaf_nitems[L] = (int32_t)n;
-        if (n > 1u) multi_leaf[atomicAdd(multi_count, 1u)] = (int32_t)L;
+    const uint32_t total = *n_items;
+    for (uint32_t i = (uint32_t)(blockIdx.x * TB + threadIdx.x); i < total; i += gridDim.x * TB) {
+        int64_t lo = 0, hi = nn - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (item0[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t L = lo;
+        const uint32_t n = nitems[L], k = i - item0[L];
+        const uint32_t q0 = off[L], q1 = off[L + 1];
+        it_leaf[i] = (int32_t)L;
+        it_q0[i] = item_start(P, q0, q1, k);
+        it_q1[i] = k + 1u < n ? item_start(P, q0, q1, k + 1u) : q1;
+        it_pbase[i] = n > 1u ? pbase[L] + k * (uint32_t)count[L] : 0u;
+        if (k == 0u) {
+            leaf_item0[L] = (int32_t)item0[L];
+            leaf_nitems[L] = (int32_t)n;
+            if (n > 1u) multi_leaf[atomicAdd(multi_count, 1u)] = (int32_t)L;
+        }
     }
 }
 
@@ -998,9 +1019,10 @@ void walk_lists_begin(Tree& t, const std::vector<double>& theta_in, hipStream_t 
         t.leaf_nitems.ensure(ctx, (size_t)(nn + 1) * 4);
         t.multi_leaf.ensure(ctx, (size_t)(nn + 1) * 4);
         t.multi_count = &res->multi;
-        hipLaunchKernelGGL(item_write_kernel, dim3(grid(ne)), dim3(TB), 0, s, (const uint32_t*)tg.as<uint32_t>(),
-                           (const uint32_t*)P, (const uint32_t*)t.p2p_off.as<uint32_t>(), ne, (const uint32_t*)nit,
-                           (const uint32_t*)it0, (const uint32_t*)pbs, t.nd_count.as<int32_t>(),
+        hipLaunchKernelGGL(item_write_kernel, dim3((unsigned)std::min<int64_t>(2048, grid(ne))), dim3(TB), 0, s,
+                           (const uint32_t*)P, (const uint32_t*)t.p2p_off.as<uint32_t>(), nn, (const uint32_t*)nit,
+                           (const uint32_t*)it0, (const uint32_t*)&res->items, (const uint32_t*)pbs,
+                           t.nd_count.as<int32_t>(),
                            t.it_leaf.as<int32_t>(), t.it_q0.as<uint32_t>(), t.it_q1.as<uint32_t>(),
                            t.it_pbase.as<uint32_t>(), t.leaf_item0.as<int32_t>(), t.leaf_nitems.as<int32_t>(),
                            t.multi_leaf.as<int32_t>(), &res->multi);
