@@ -23,7 +23,8 @@ Prints one JSON line.  Besides the headline value it reports:
 * a bounded serving run: Poisson-arriving solves of N log-uniform in
   [1e3, 5e5], p in {2,4,6}, theta in {0.4,0.6,0.8}, plus resident leapfrog
   sessions; FP64 one solve at a time, mixed precision on several slots, and
-  the same slots with small requests solved together as forests, on the same
+  the same slots with requests of up to 2e5 particles solved together as
+  forests, on the same
   trace: solves/s at capacity, p50/p99 latency at a fixed arrival rate;
 * the two-body setup of the paper's distance test: force error of orders 0
   and 1 with and without realignment;
@@ -193,8 +194,12 @@ def run_serving(args):
             # untimed pass first: the first launch of every kernel loads its
             # code and the slots grow their buffers (a running server's state)
             srv.run(burst, inputs=inputs)
-            recs = srv.run(burst, inputs=inputs)
-            cap = summarize(recs)
+            caps = []
+            for _ in range(3):  # a burst lasts tens of milliseconds: the median of three
+                recs = srv.run(burst, inputs=inputs)
+                caps.append(summarize(recs))
+            cap = {"solves_per_s": float(np.median([c["solves_per_s"] for c in caps])),
+                   "errors": sum(c["errors"] for c in caps)}
             burst_batch = float(np.mean([r.batch for r in recs if r.kind == "solve"]))
             # the latency trace three times: one 64-request p99 is close to the
             # slowest request, and a stall of the host now and then moves it
@@ -207,6 +212,7 @@ def run_serving(args):
             srv.close()
         med = {key: float(np.median([r[key] for r in reps])) for key in ("solves_per_s", "p50_ms", "p99_ms")}
         res[name] = {"slots": k, "capacity_solves_per_s": cap["solves_per_s"],
+                     "capacity_each_run": [c["solves_per_s"] for c in caps],
                      "capacity_mean_requests_per_launch_set": burst_batch, "solves_per_s": med["solves_per_s"],
                      "p50_ms": med["p50_ms"], "p99_ms": med["p99_ms"],
                      "p99_ms_each_run": [r["p99_ms"] for r in reps],

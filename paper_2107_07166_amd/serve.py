@@ -206,7 +206,7 @@ class _Worker:
 class Server:
     def __init__(self, slots: int = 8, precision: str = "mixed32", budget_bytes: int = 64 << 30,
                  n_leaf: int = 32, device: int = 0, sample_k: int = 16, keep_full: bool = False,
-                 step_slots: Optional[int] = None, batch_max_n: int = 50000, batch_max_total: int = 1 << 20,
+                 step_slots: Optional[int] = None, batch_max_n: int = 200000, batch_max_total: int = 1 << 20,
                  batch_max_sets: int = 256, steps_beside_solves: int = 0):
         """batch_max_n: requests of at most this many particles are solved
         together as one forest (same p, variant and softening; theta may
