@@ -341,29 +341,41 @@ __global__ __launch_bounds__(TB) void leaf_level_kernel(const int8_t* __restrict
     }
 }
 
-// Exclusive scan over the blocks of one slot's counts (one block per slot).
+// Exclusive scan over the blocks of one slot's counts (one block per slot):
+// every thread takes a contiguous run of the counts, the run totals are
+// scanned across the block (wave scans, then the waves' totals), and each
+// thread writes its run's exclusive prefixes.
 __global__ __launch_bounds__(TB) void slot_scan_kernel(uint32_t* __restrict__ cnt, int64_t nblk,
                                                        uint32_t* __restrict__ tot) {
-    __shared__ uint32_t sh[TB];
+    __shared__ uint32_t wsum[TB / kWave];
     uint32_t* c = cnt + (int64_t)blockIdx.x * nblk;
-    uint32_t carry = 0;
-    for (int64_t c0 = 0; c0 < nblk; c0 += TB) {
-        const int64_t i = c0 + threadIdx.x;
-        const uint32_t x = (i < nblk) ? c[i] : 0u;
-        sh[threadIdx.x] = x;
-        __syncthreads();
-        for (int d = 1; d < TB; d <<= 1) {
-            const uint32_t y = (threadIdx.x >= (unsigned)d) ? sh[threadIdx.x - d] : 0u;
-            __syncthreads();
-            sh[threadIdx.x] += y;
-            __syncthreads();
-        }
-        if (i < nblk) c[i] = carry + sh[threadIdx.x] - x;
-        const uint32_t last = sh[TB - 1];
-        __syncthreads();
-        carry += last;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int64_t per = (nblk + TB - 1) / TB;
+    const int64_t i0 = (int64_t)tid * per;
+    const int64_t i1 = i0 + per < nblk ? i0 + per : nblk;
+    uint32_t run = 0;
+    for (int64_t i = i0; i < i1; ++i) run += c[i];
+    uint32_t v = run;  // inclusive scan of the run totals over the wave
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)v, d, kWave);
+        if (lane >= d) v += u;
     }
-    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+    if (lane == kWave - 1) wsum[wv] = v;
+    __syncthreads();
+    uint32_t base = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < TB / kWave; ++q) {
+        if (q < wv) base += wsum[q];
+        all += wsum[q];
+    }
+    uint32_t acc = base + v - run;
+    for (int64_t i = i0; i < i1; ++i) {
+        const uint32_t x = c[i];
+        c[i] = acc;
+        acc += x;
+    }
+    if (tid == 0) tot[blockIdx.x] = all;
 }
 
 // Level boundaries and sizes of the octree (read back by the host once).
