@@ -19,9 +19,9 @@ and session steps hold at most `step_slots` workers at once (default half),
 so an arriving solve finds a worker ready; while any solve runs, no new
 session step starts (`steps_beside_solves`, default 0), since steps would
 share the device with the solves and stretch their latency.  Every worker owns a
-libtfmm context, its own HIP stream (default priority) and one reusable tree
-(device buffers are grow-only), so the work of several requests overlaps on
-the GPU.  Sessions keep particles and tree resident in HBM between steps and
+libtfmm context, its own HIP stream (default priority), one reusable tree
+(device buffers are grow-only) and, during a run, one host thread fed
+through a queue, so the work of several requests overlaps on the GPU.  Sessions keep particles and tree resident in HBM between steps and
 are re-queued after every step.
 
 The slots live as long as the Server (created by the first run, kept with
@@ -35,6 +35,7 @@ from __future__ import annotations
 import collections
 import itertools
 import math
+import queue
 import threading
 import time
 from dataclasses import dataclass, field
@@ -332,7 +333,19 @@ class Server:
                 state["free_workers"].append(wid)
                 lock.notify_all()
 
-        threads = []
+        # one thread per slot for the whole run, fed through its own queue
+        jobs = [queue.SimpleQueue() for _ in workers]
+
+        def slot_loop(wid: int):
+            while True:
+                job = jobs[wid].get()
+                if job is None:
+                    return
+                execute(wid, *job)
+
+        threads = [threading.Thread(target=slot_loop, args=(v,), daemon=True) for v in range(len(workers))]
+        for th in threads:
+            th.start()
         nxt = 0
         with lock:
             while True:
@@ -394,9 +407,7 @@ class Server:
                     w.ctx.set_budget(lib_need)
                     self.peak_reserved = max(self.peak_reserved, total)
                     free.remove(wid)
-                    th = threading.Thread(target=execute, args=(wid, batch, now, fp), daemon=True)
-                    threads.append(th)
-                    th.start()
+                    jobs[wid].put((batch, now, fp))
                 # session steps fill the workers no admissible solve is waiting for
                 # (here either no solve waits or the head solve does not fit yet)
                 rounds = len(steps_q)
@@ -409,15 +420,15 @@ class Server:
                         continue
                     busy_sessions.add(req.session)
                     wid = state["free_workers"].pop()
-                    th = threading.Thread(target=execute, args=(wid, [req], now, 0), daemon=True)
-                    threads.append(th)
-                    th.start()
+                    jobs[wid].put(([req], now, 0))
                 if state["solves_left"] <= 0 and len(state["free_workers"]) == self.slots:
                     break
                 wait = None
                 if nxt < len(requests):
                     wait = max(0.0, requests[nxt].arrival - (time.perf_counter() - t0))
                 lock.wait(timeout=wait if wait is not None else 0.05)
+        for q in jobs:
+            q.put(None)
         for th in threads:
             th.join()
         self.retries = sum(w.retries for w in workers)
