@@ -320,15 +320,33 @@ __global__ __launch_bounds__(kWave) void p2p_reduce_kernel(const int32_t* __rest
     const int32_t L = multi_leaf[blockIdx.x];
     const int32_t ni = leaf_nitems[L], i0 = leaf_item0[L];
     const int32_t fa = first[L], na = count[L];
+    constexpr int B = 8;  // items whose rows are loaded together (sums stay in item order)
     for (int32_t r = threadIdx.x; r < na; r += kWave) {
         double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-        for (int32_t i = 0; i < ni; ++i) {
-            const int64_t row = (int64_t)it_pbase[i0 + i] + r;
-            const double* p = partial + 3 * row;
-            sx += p[0];
-            sy += p[1];
-            sz += p[2];
-            if constexpr (POT) sp += partial_pot[row];
+        for (int32_t i = 0; i < ni; i += B) {
+            int64_t row[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) row[u] = i + u < ni ? (int64_t)it_pbase[i0 + i + u] + r : 0;
+            double v[B][4];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                if (i + u < ni) {
+                    const double* p = partial + 3 * row[u];
+                    v[u][0] = p[0];
+                    v[u][1] = p[1];
+                    v[u][2] = p[2];
+                    if constexpr (POT) v[u][3] = partial_pot[row[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                if (i + u < ni) {
+                    sx += v[u][0];
+                    sy += v[u][1];
+                    sz += v[u][2];
+                    if constexpr (POT) sp += v[u][3];
+                }
+            }
         }
         near[3 * (int64_t)(fa + r)] = sx;
         near[3 * (int64_t)(fa + r) + 1] = sy;
