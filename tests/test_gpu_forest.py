@@ -251,3 +251,30 @@ def test_forest_with_scalar_degree(ctx):
     t.close()
     for k, (fa, *_) in enumerate(alone):
         assert np.array_equal(f[off[k]:off[k + 1]], fa), k
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_random_forests_equal_sets_alone(ctx, seed):
+    """Seeded random forests: 2 to 40 sets of 1 to 3000 particles from every
+    generator, per-set thetas, a random order, variant and precision; each
+    set's forces equal its forces alone bit for bit."""
+    from paper_2107_07166_amd import api
+    rng = np.random.default_rng(900 + seed)
+    k = int(rng.integers(2, 41))
+    specs = [(str(rng.choice(["ball", "plummer", "disk", "same"])), int(rng.integers(1, 3001)),
+              int(rng.integers(1 << 20)), float(rng.choice([0.0, 0.3, 0.5, 0.7, 0.9]))) for _ in range(k)]
+    p = int(rng.integers(1, 8))
+    variant = str(rng.choice(["standard", "conserving"]))
+    precision = str(rng.choice(["fp64", "mixed32"]))
+    n_leaf = int(rng.choice([1, 4, 16, 64]))
+    print(f"\n  seed {seed}: {k} sets, p={p} {variant} {precision} n_leaf={n_leaf}", flush=True)
+    parts, off, pos, mass, thetas = _sets(specs)
+    kw = dict(p=p, eps=float(rng.choice([0.0, 1e-3])), variant=variant, precision=precision)
+    t = api.Tree(ctx, _dev(pos), _dev(mass), n_leaf=n_leaf, offsets=off)
+    f = t.evaluate_forest(thetas, **kw).cpu().numpy()
+    t.close()
+    for j, ((pp, m), th) in enumerate(zip(parts, thetas)):
+        one = api.Tree(ctx, _dev(pp), _dev(m), n_leaf=n_leaf)
+        fa = one.evaluate(theta=float(th), **kw).cpu().numpy()
+        one.close()
+        assert np.array_equal(f[off[j]:off[j + 1]], fa), j
