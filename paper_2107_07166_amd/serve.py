@@ -267,9 +267,10 @@ class Server:
         steps_q = collections.deque()      # session steps, FIFO
         records: List[Record] = []
         # Memory: the sessions' footprints, plus per slot either the bytes
-        # reserved for the solve it runs (the larger of what it held and the
-        # solve's footprint, the library part enforced through the slot
-        # context's budget) or, while it runs no solve, what it holds.
+        # reserved for the solve it runs (what it held plus the solve's
+        # footprint, or the larger of the two when the budget is short; the
+        # library part enforced through the slot context's budget) or, while
+        # it runs no solve, what it holds.
         sess_bytes = sum(session_footprint(s.n, s.params["p"], s.n_leaf, s.params["precision"]) for s in sessions)
         reserved = {}                      # slot -> bytes reserved for its running solve
         state = {"free_workers": list(range(self.slots)), "solves_left": len(requests), "next_step_id": 10**9,
