@@ -301,10 +301,20 @@ int tfmm_ctx_create(int device, size_t hbm_budget_bytes, tfmm_ctx** out) {
         diag_scratch_init(device);
         c->pinned_bytes = 1 << 16;
         TFMM_HIP(hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault));
+        void* mb = nullptr;
+        TFMM_HIP(hipHostMalloc(&mb, kBoxBytes, hipHostMallocCoherent | hipHostMallocMapped));
+        c->mbox = static_cast<uint32_t*>(mb);
+        std::memset(mb, 0, kBoxBytes);
+        void* mbd = nullptr;
+        TFMM_HIP(hipHostGetDevicePointer(&mbd, mb, 0));
+        c->mbox_dev = static_cast<uint32_t*>(mbd);
         TFMM_HIP(hipMalloc(reinterpret_cast<void**>(&c->dev_err), 256));
         TFMM_HIP(hipMemset(c->dev_err, 0, 256));
     });
     if (rc != TFMM_OK) {
+        if (c->pinned) (void)hipHostFree(c->pinned);
+        if (c->mbox) (void)hipHostFree(c->mbox);
+        if (c->dev_err) (void)hipFree(c->dev_err);
         delete c;
         return rc;
     }
@@ -322,6 +332,7 @@ int tfmm_ctx_destroy(tfmm_ctx* ctx) {
     (void)hipDeviceSynchronize();
     ctx->trim_cache();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->mbox) (void)hipHostFree(ctx->mbox);
     if (ctx->dev_err) (void)hipFree(ctx->dev_err);
     delete ctx;
     return TFMM_OK;

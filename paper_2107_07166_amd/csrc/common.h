@@ -69,6 +69,9 @@ struct Ctx {
     bool broken = false;
     void* pinned = nullptr;  // small pinned host staging area
     size_t pinned_bytes = 0;
+    uint32_t* mbox = nullptr;      // pinned, device-coherent read-back mailbox (host address)
+    uint32_t* mbox_dev = nullptr;  // the same memory as the device sees it
+    uint32_t mbox_seq = 0;         // sequence number of the last read-back
     uint32_t* dev_err = nullptr;  // device word set by a kernel whose bounded wait ran out
     int live_trees = 0;
     void* alloc(size_t bytes, size_t* got);  // *got: the block's size (>= bytes)
@@ -216,12 +219,15 @@ struct U3 {
 };
 size_t scan_scratch_bytes(int64_t n);
 // Exclusive scan of n values (in == out allowed); writes the total to
-// *total_dev (device).  err: the context's device error word.
-void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
-                        uint32_t* total_dev, uint32_t* err, hipStream_t s);
+// *total_dev (device).
+void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch, uint32_t* total_dev,
+                        hipStream_t s);
+// Two scans of n values each (one launch when n is small).
+void exclusive_scan2_u32(const uint32_t* in0, uint32_t* out0, uint32_t* total0, const uint32_t* in1,
+                         uint32_t* out1, uint32_t* total1, int64_t n, void* scratch, hipStream_t s);
 // The same over gathered values: value i = val[idx[i]] (val non-negative).
 void exclusive_scan_gather_u32(const int32_t* idx, const int32_t* val, uint32_t* out, int64_t n, void* scratch,
-                               uint32_t* total_dev, uint32_t* err, hipStream_t s);
+                               uint32_t* total_dev, hipStream_t s);
 
 // ---- radix sort (sort.hip) ----------------------------------------------------
 size_t sort_scratch_bytes(int64_t n, int bits);
@@ -243,20 +249,28 @@ void radix_sort_pairs(const int2* pairs, int64_t np, bool self_dummy, uint32_t s
 void radix_sort_pairs_packed16(const int2* pairs, int64_t np, uint32_t* keys, uint32_t* keys_alt, int bits,
                                void* scratch, uint32_t* err, hipStream_t s);
 
-// Copies one device value to the host together with the context's device
-// error word, with a single synchronisation; fails if a kernel set the word.
+// Mailbox layout: word 0 the sequence number of the last read-back, word 1
+// the device error word, the payload from word kBoxHeaderWords on.
+constexpr int kBoxHeaderWords = 16;
+constexpr size_t kBoxPayload = 32768;
+constexpr size_t kBoxBytes = kBoxHeaderWords * 4 + kBoxPayload;
+// Copies bytes (a multiple of 4, at most kBoxPayload) from device memory to
+// out once the work queued on s before it is done; with check_err, fails if a
+// kernel set the context's device error word.
+void read_back_bytes(Ctx* ctx, const void* dev, size_t bytes, void* out, bool check_err, hipStream_t s);
+
+template <typename V>
+V read_back(Ctx* ctx, const V* dev, hipStream_t s) {
+    V v;
+    read_back_bytes(ctx, dev, sizeof(V), &v, false, s);
+    return v;
+}
+
+// The same, failing if a kernel set the device error word.
 template <typename V>
 V read_back_checked(Ctx* ctx, const V* dev, hipStream_t s) {
-    static_assert(sizeof(V) <= 32768, "read-back value too large");
-    char* h = static_cast<char*>(ctx->pinned);
-    TFMM_HIP(hipMemcpyAsync(h, dev, sizeof(V), hipMemcpyDeviceToHost, s));
-    TFMM_HIP(hipMemcpyAsync(h + 32768, ctx->dev_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    TFMM_HIP(hipStreamSynchronize(s));
     V v;
-    std::memcpy(&v, h, sizeof(V));
-    uint32_t e;
-    std::memcpy(&e, h + 32768, sizeof(e));
-    if (e != 0u) fail(TFMM_EDEVICE, "a device-side wait ran past its bound (internal error); results are invalid");
+    read_back_bytes(ctx, dev, sizeof(V), &v, true, s);
     return v;
 }
 

@@ -505,7 +505,7 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
                 hipLaunchKernelGGL((radix_up_kernel<K, HV, true, Src>), dim3(nb), dim3(RB), 0, s, src, n, shift,
                                    (int64_t)nb, cnt);
                 TFMM_LAUNCHED();
-                exclusive_scan_u32(cnt, cnt, nc, sscr, total, err, s);
+                exclusive_scan_u32(cnt, cnt, nc, sscr, total, s);
                 hipLaunchKernelGGL((radix_down_kernel<K, HV, Src>), dim3(nb), dim3(RB), 0, s, src, ko, vo, n, shift,
                                    (int64_t)nb, (const uint32_t*)cnt);
                 TFMM_LAUNCHED();
@@ -514,7 +514,7 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
                 hipLaunchKernelGGL((radix_up_kernel<K, HV, false, ArraySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, n, shift,
                                    (int64_t)nb, cnt);
                 TFMM_LAUNCHED();
-                exclusive_scan_u32(cnt, cnt, nc, sscr, total, err, s);
+                exclusive_scan_u32(cnt, cnt, nc, sscr, total, s);
                 hipLaunchKernelGGL((radix_down_kernel<K, HV, ArraySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, ko, vo, n,
                                    shift, (int64_t)nb, (const uint32_t*)cnt);
                 TFMM_LAUNCHED();
@@ -523,7 +523,7 @@ void radix_sort_run(Src src, K* kout, int32_t* vout, K* kalt, int32_t* valt, int
                 hipLaunchKernelGGL((radix_up_kernel<K, HV, false, KeySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, n, shift,
                                    (int64_t)nb, cnt);
                 TFMM_LAUNCHED();
-                exclusive_scan_u32(cnt, cnt, nc, sscr, total, err, s);
+                exclusive_scan_u32(cnt, cnt, nc, sscr, total, s);
                 hipLaunchKernelGGL((radix_down_kernel<K, HV, KeySrc<K>>), dim3(nb), dim3(RB), 0, s, prev, ko, vo, n,
                                    shift, (int64_t)nb, (const uint32_t*)cnt);
                 TFMM_LAUNCHED();

@@ -651,15 +651,6 @@ void ensure_nodes(Tree& t, int64_t cap, int64_t keep, hipStream_t s) {
     t.nd_parent.ensure_keep(t.ctx, c * 4, s);
 }
 
-template <typename V>
-V read_back(Ctx* ctx, const V* dev, hipStream_t s) {
-    TFMM_HIP(hipMemcpyAsync(ctx->pinned, dev, sizeof(V), hipMemcpyDeviceToHost, s));
-    TFMM_HIP(hipStreamSynchronize(s));
-    V v;
-    std::memcpy(&v, ctx->pinned, sizeof(V));
-    return v;
-}
-
 }  // namespace
 
 void upload(Tree& t, DevBuf& dst, const void* src, size_t bytes, int slot, hipStream_t s) {
@@ -830,7 +821,7 @@ void build_tree(Tree& t, const double* pos, const double* mass, hipStream_t s) {
         t.rmax_items.ensure(ctx, (size_t)ub * 8);
         hipLaunchKernelGGL(rmax_chunks_kernel, dim3(grid(nn)), dim3(TB), 0, s, nd.count, nn, c);
         TFMM_LAUNCHED();
-        exclusive_scan_u32(c, base, nn, t.scratch.p, total, ctx->dev_err, s);
+        exclusive_scan_u32(c, base, nn, t.scratch.p, total, s);
         hipLaunchKernelGGL(rmax_items_kernel, dim3(grid(nn)), dim3(TB), 0, s, nn, (const uint32_t*)c,
                            (const uint32_t*)base, t.rmax_items.as<int2>());
         TFMM_LAUNCHED();

@@ -694,15 +694,6 @@ int bits_for(int64_t n) {
     return b;
 }
 
-template <typename V>
-V read_back(Ctx* ctx, const V* dev, hipStream_t s) {
-    TFMM_HIP(hipMemcpyAsync(ctx->pinned, dev, sizeof(V), hipMemcpyDeviceToHost, s));
-    TFMM_HIP(hipStreamSynchronize(s));
-    V v;
-    std::memcpy(&v, ctx->pinned, sizeof(V));
-    return v;
-}
-
 // Stable sort by target of the directed entries of np node pairs (read
 // straight from the pair array), then CSR offsets from the sorted targets.
 // With self_dummy, the second entry of a self pair gets key nn and sorts
@@ -996,8 +987,7 @@ void walk_lists_begin(Tree& t, const std::vector<double>& theta_in, hipStream_t 
         uint32_t* P = t.w_c.as<uint32_t>();
         t.scratch_b.ensure(ctx, scan_scratch_bytes(ne) + 256);
         // P[q] = source particles before entry q (gathered from the source leaf counts)
-        exclusive_scan_gather_u32(t.p2p_src.as<int32_t>(), t.nd_count.as<int32_t>(), P, ne, t.scratch_b.p, junk,
-                                  ctx->dev_err, s);
+        exclusive_scan_gather_u32(t.p2p_src.as<int32_t>(), t.nd_count.as<int32_t>(), P, ne, t.scratch_b.p, junk, s);
         // per node: items and partial rows, then their offsets
         t.w_fl.ensure(ctx, (size_t)(nn + 1) * 16);
         uint32_t* nit = t.w_fl.as<uint32_t>();
@@ -1007,8 +997,7 @@ void walk_lists_begin(Tree& t, const std::vector<double>& theta_in, hipStream_t 
         hipLaunchKernelGGL(node_items_kernel, dim3(grid(nn)), dim3(TB), 0, s, (const uint32_t*)t.p2p_off.as<uint32_t>(),
                            (const uint32_t*)P, nn, t.nd_count.as<int32_t>(), nit, prw);
         TFMM_LAUNCHED();
-        exclusive_scan_u32(nit, it0, nn, t.scratch_b.p, &res->items, ctx->dev_err, s);
-        exclusive_scan_u32(prw, pbs, nn, t.scratch_b.p, &res->partial, ctx->dev_err, s);
+        exclusive_scan2_u32(nit, it0, &res->items, prw, pbs, &res->partial, nn, t.scratch_b.p, s);
         // there are at most ne items, so every item array is sized by ne
         const size_t ni = (size_t)std::max<int64_t>(ne, 1);
         t.it_leaf.ensure(ctx, ni * 4);
