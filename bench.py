@@ -12,10 +12,10 @@ L2L, P2P, L2P.
 Prints one JSON line.  Besides the headline value it reports:
 
 * the standard variant and the FP64 path at the same workload (every variant
-  timed the same way: K steps after W warm-up steps, with the per-phase HIP
-  events of the library on);
+  timed the same way: K steps after W warm-up steps);
 * per-phase device times (rebuild, walk, moments, M2L, P2P, L2L, L2P, the
-  interaction pass where P2P and M2L run side by side);
+  interaction pass where P2P and M2L run side by side) from K further steps
+  with the library's per-phase HIP events on;
 * the roofline of the dominant kernel (P2P) and the algorithmic FLOP rate of
   the whole interaction pass (P2P + M2L);
 * the exponential disk (N = 2^22, p = 6, theta = 0.8): ms per step of both
@@ -54,8 +54,8 @@ P2P_FLOP_PER_PAIR = 20        # per directed particle interaction (convention)
 # factor a plain copy of known size reads) and WRITE_SIZE (x1); see
 # profiles/p2p_plummer1m_counters.md.  Valid only for the kernel source the
 # counters were taken with (first 16 hex digits of its sha256).
-P2P_TRAFFIC_BYTES = (2 * 227115 + 32009) * 1024
-P2P_TRAFFIC_SOURCE_SHA = "8eaba0fa02df4bfb"
+P2P_TRAFFIC_BYTES = (2 * 226412 + 32009) * 1024
+P2P_TRAFFIC_SOURCE_SHA = "86831685a88e238a"
 
 
 def _p2p_traffic():
@@ -80,8 +80,10 @@ def _erms(f, ref):
 
 
 def _timed_steps(tree, pd, md, out, w, variant, precision, steps, warmup):
-    """K timed steps (rebuild + evaluate) after W warm-up steps, with the
-    library's phase events on; returns (seconds per step, phase times)."""
+    """K timed steps (rebuild + evaluate) after W warm-up steps, then K more
+    with the library's phase events on (the events cost a few per cent of a
+    step of their own, so they stay out of the timed steps); returns
+    (seconds per step, phase times).  Every variant is timed this way."""
     import torch
 
     def step():
@@ -91,12 +93,15 @@ def _timed_steps(tree, pd, md, out, w, variant, precision, steps, warmup):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    tree.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    tree.set_timing(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
     ph = tree.phase_times()
     tree.set_timing(False)
     return dt, ph
