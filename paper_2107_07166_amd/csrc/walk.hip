@@ -985,7 +985,8 @@ void walk_lists_begin(Tree& t, const std::vector<double>& theta_in, hipStream_t 
         // work items over the sorted near entries (tg holds the sorted targets)
         t.w_c.ensure(ctx, (size_t)std::max<int64_t>(ne, 1) * 4);
         uint32_t* P = t.w_c.as<uint32_t>();
-        t.scratch_b.ensure(ctx, scan_scratch_bytes(ne) + 256);
+        // the same scratch serves the scan over the entries and the two over the nodes
+        t.scratch_b.ensure(ctx, scan_scratch_bytes(std::max<int64_t>(ne, nn)) + 256);
         // P[q] = source particles before entry q (gathered from the source leaf counts)
         exclusive_scan_gather_u32(t.p2p_src.as<int32_t>(), t.nd_count.as<int32_t>(), P, ne, t.scratch_b.p, junk, s);
         // per node: items and partial rows, then their offsets
