@@ -166,13 +166,16 @@ int scalar_degree(const tfmm_params* p) {
 
 // Two streams: s (the caller's) and the tree's second stream a.
 //   a: moments (during the frontier passes) -> far-list chain -> M2L -> L2L
-//   s: sources -> frontier passes -> near-list chain -> P2P -> [join a] -> L2P
+//      -> L2P's far part
+//   s: sources -> frontier passes -> near-list chain -> P2P -> split-leaf
+//      reduction -> [join a] -> forces (near + far)
 // The latency-bound list chains hide behind each other, and P2P starts as
 // soon as the near lists exist, beside M2L and L2L on the second stream.
 // Adds the phase times of the last timed evaluation to the tree's sums.
 // Events: moments [0,1], M2L [7,2], L2L [2,3] on the tree's second stream;
 // P2P [6,4] (the near-field kernel; the partial-sum reduction follows it),
-// L2P [8,5] on the caller's stream (8: after the streams join);
+// the forces from near and far parts [8,5] on the caller's stream (8: after
+// the streams join; L2P's far part runs before the join, after L2L);
 // whole evaluation [0,5]; walk [11, later of 7 and 6], its frontier passes
 // [11,12] (only in evaluations that walked).
 double elapsed_ms(Tree& t, int i, int j) {
@@ -187,7 +190,7 @@ void fold_times(Tree& t) {
     t.t_sum[0] += elapsed_ms(t, 7, 2);  // M2L
     t.t_sum[1] += elapsed_ms(t, 6, 4);  // P2P
     t.t_sum[2] += elapsed_ms(t, 2, 3);  // L2L
-    t.t_sum[3] += elapsed_ms(t, 8, 5);  // L2P
+    t.t_sum[3] += elapsed_ms(t, 8, 5);  // forces after the join
     t.t_sum[4] += elapsed_ms(t, 0, 1);  // moments
     t.t_sum[5] += elapsed_ms(t, 0, 5);  // whole evaluation after the tree build
     {
@@ -258,6 +261,9 @@ void evaluate(Tree& t, const tfmm_params* prm, const double* theta_sets, double*
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[2], a));
     run_l2l(t, pe, ve, a);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[3], a));
+    // the far-field part of L2P beside the near field; only the sum of the
+    // two waits for both
+    run_l2p_far(t, pe, ve, a);
     if (need_walk) walk_lists_end(t, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[6], s));
     run_p2p(t, prm->precision, eps2, potential != nullptr, s);
@@ -265,7 +271,7 @@ void evaluate(Tree& t, const tfmm_params* prm, const double* theta_sets, double*
     run_p2p_reduce(t, potential != nullptr, s);
     aux_join(t, s);
     if (t.timing) TFMM_HIP(hipEventRecord(t.ev[8], s));
-    run_l2p(t, pe, ve, prm->G, force, s);
+    run_force_combine(t, prm->G, force, s);
     if (potential) {
         // far-field potential from the standard expansion of order p (every
         // variant), after the forces on the same stream
@@ -668,7 +674,7 @@ size_t tfmm_footprint_bytes(int64_t n, int p, int n_leaf, int precision) {
     const double nn = 4.0 * (double)n / (double)n_leaf + 1024.0;  // nodes (generous)
     const double nc = c_le(p), ncp = (double)round_up(c_le(p), 4), nloc = 4.0 * c_le(p - 1) + nc;
     double b = 0;
-    b += (double)n * (8 + 8 + 4 + 4 + 1 + 4 + 8 + 32 + 4 + (precision == TFMM_MIXED32 ? 16 : 32) + 24);
+    b += (double)n * (8 + 8 + 4 + 4 + 1 + 4 + 8 + 32 + 4 + (precision == TFMM_MIXED32 ? 16 : 32) + 24 + 24);
     b += nn * (4 * 6 + 8 + 32 + 32 + 8 + 8 + 4);
     b += nn * (nc * 8 + ncp * 12 + 2 * nloc * 8);
     b += nn * (400.0 * 8 * 2 + 80.0 * 8 * 2);  // pair lists, directed lists, frontiers

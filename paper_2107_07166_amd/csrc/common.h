@@ -184,6 +184,7 @@ struct Tree {
     DevBuf loc_leaf;              // FP64 gathered locals per leaf (per node when built level by level)
     DevBuf loc_has;               // uint8 per node: its gathered locals exist (level-by-level pass)
     DevBuf near3;                 // FP64 near-field acceleration (3 per sorted particle)
+    DevBuf far3;                  // FP64 far-field acceleration (3 per sorted particle)
     DevBuf near_pot, partial_pot; // FP64 near-field potential (per sorted particle / per partial row)
     DevBuf loc_pot, loc_pot_leaf; // FP64 standard locals with L_0 (potential output only)
 
@@ -300,7 +301,10 @@ void run_p2p_reduce(Tree& t, bool with_pot, hipStream_t s);
 void run_m2l_pot(Tree& t, int p, int mom_p, int precision, double eps2, hipStream_t s);
 void run_potential_down(Tree& t, int p, int precision, double eps2, double G, double* pot, hipStream_t s);
 void run_l2l(Tree& t, int p, int variant, hipStream_t s);
-void run_l2p(Tree& t, int p, int variant, double G, double* force, hipStream_t s);
+// Far-field acceleration of every particle into t.far3 (after L2L, on the
+// stream L2L ran on), then the forces G m (near + far) in caller order.
+void run_l2p_far(Tree& t, int p, int variant, hipStream_t s);
+void run_force_combine(Tree& t, double G, double* force, hipStream_t s);
 void run_diagnostics(int64_t n, const double* pos, const double* vel, const double* mass,
                      const double* force, double* out_host, Ctx* ctx, hipStream_t s);
 void diag_scratch_init(int device);  // with the device current

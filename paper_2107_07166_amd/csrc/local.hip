@@ -235,14 +235,15 @@ void l2l_levels(Tree& t, hipStream_t s) {
     }
 }
 
+// Far-field acceleration at every particle (sorted order) from its leaf's
+// locals, into far3 (three values per particle).  It runs on the tree's
+// second stream right after L2L, beside the near field.
 template <int P, int VAR>
-__global__ __launch_bounds__(LB) void l2p_kernel(int64_t n, const double4* __restrict__ Xm,
-                                                 const int32_t* __restrict__ leaf_of,
-                                                 const int32_t* __restrict__ perm,
-                                                 const double4* __restrict__ Z,
-                                                 const double* __restrict__ loc_leaf,
-                                                 const double* __restrict__ near, double G,
-                                                 double* __restrict__ force) {
+__global__ __launch_bounds__(LB) void l2p_far_kernel(int64_t n, const double4* __restrict__ Xm,
+                                                     const int32_t* __restrict__ leaf_of,
+                                                     const double4* __restrict__ Z,
+                                                     const double* __restrict__ loc_leaf,
+                                                     double* __restrict__ far3) {
     using E = Expansion<P>;
     const int64_t j = (int64_t)blockIdx.x * LB + threadIdx.x;
     if (j >= n) return;
@@ -258,11 +259,24 @@ __global__ __launch_bounds__(LB) void l2p_kernel(int64_t n, const double4* __res
     } else {
         E::l2p_std(loc_leaf + (int64_t)leaf * E::NC, dx, dy, dz, a);
     }
-    const double s = G * x.w;
+    far3[3 * j] = a[0];
+    far3[3 * j + 1] = a[1];
+    far3[3 * j + 2] = a[2];
+}
+
+// The force G m (near + far) of every particle, into its caller-order slot.
+__global__ __launch_bounds__(LB) void force_combine_kernel(int64_t n, const double4* __restrict__ Xm,
+                                                           const int32_t* __restrict__ perm,
+                                                           const double* __restrict__ near,
+                                                           const double* __restrict__ far3, double G,
+                                                           double* __restrict__ force) {
+    const int64_t j = (int64_t)blockIdx.x * LB + threadIdx.x;
+    if (j >= n) return;
+    const double s = G * Xm[j].w;
     const int64_t o = perm[j];
-    force[3 * o] = s * (near[3 * j] + a[0]);
-    force[3 * o + 1] = s * (near[3 * j + 1] + a[1]);
-    force[3 * o + 2] = s * (near[3 * j + 2] + a[2]);
+    force[3 * o] = s * (near[3 * j] + far3[3 * j]);
+    force[3 * o + 1] = s * (near[3 * j + 1] + far3[3 * j + 1]);
+    force[3 * o + 2] = s * (near[3 * j + 2] + far3[3 * j + 2]);
 }
 
 // Potential output: phi_a = sum_{|j| <= p} L_j x^j / j! (standard locals with
@@ -330,16 +344,16 @@ void l2l_dispatch(Tree& t, int variant, hipStream_t s) {
 }
 
 template <int P>
-void l2p_dispatch(Tree& t, int variant, double G, double* force, hipStream_t s) {
+void l2p_far_dispatch(Tree& t, int variant, hipStream_t s) {
     const int64_t n = t.n;
     if (variant == TFMM_CONSERVING)
-        hipLaunchKernelGGL((l2p_kernel<P, TFMM_CONSERVING>), dim3((unsigned)cdiv(n, LB)), dim3(LB), 0, s, n,
-                           t.Xm.as<double4>(), t.leaf_of.as<int32_t>(), t.perm.as<int32_t>(), t.nd_Z.as<double4>(),
-                           t.loc_leaf.as<double>(), t.near3.as<double>(), G, force);
+        hipLaunchKernelGGL((l2p_far_kernel<P, TFMM_CONSERVING>), dim3((unsigned)cdiv(n, LB)), dim3(LB), 0, s, n,
+                           t.Xm.as<double4>(), t.leaf_of.as<int32_t>(), t.nd_Z.as<double4>(),
+                           t.loc_leaf.as<double>(), t.far3.as<double>());
     else
-        hipLaunchKernelGGL((l2p_kernel<P, TFMM_STANDARD>), dim3((unsigned)cdiv(n, LB)), dim3(LB), 0, s, n,
-                           t.Xm.as<double4>(), t.leaf_of.as<int32_t>(), t.perm.as<int32_t>(), t.nd_Z.as<double4>(),
-                           t.loc_leaf.as<double>(), t.near3.as<double>(), G, force);
+        hipLaunchKernelGGL((l2p_far_kernel<P, TFMM_STANDARD>), dim3((unsigned)cdiv(n, LB)), dim3(LB), 0, s, n,
+                           t.Xm.as<double4>(), t.leaf_of.as<int32_t>(), t.nd_Z.as<double4>(),
+                           t.loc_leaf.as<double>(), t.far3.as<double>());
     TFMM_LAUNCHED();
 }
 
@@ -376,18 +390,26 @@ void run_potential_down(Tree& t, int p, int precision, double eps2, double G, do
     }
 }
 
-void run_l2p(Tree& t, int p, int variant, double G, double* force, hipStream_t s) {
+void run_l2p_far(Tree& t, int p, int variant, hipStream_t s) {
+    t.far3.ensure(t.ctx, (size_t)t.n * 24);
     switch (p) {
-        case 1: l2p_dispatch<1>(t, variant, G, force, s); break;
-        case 2: l2p_dispatch<2>(t, variant, G, force, s); break;
-        case 3: l2p_dispatch<3>(t, variant, G, force, s); break;
-        case 4: l2p_dispatch<4>(t, variant, G, force, s); break;
-        case 5: l2p_dispatch<5>(t, variant, G, force, s); break;
-        case 6: l2p_dispatch<6>(t, variant, G, force, s); break;
-        case 7: l2p_dispatch<7>(t, variant, G, force, s); break;
-        case 8: l2p_dispatch<8>(t, variant, G, force, s); break;
+        case 1: l2p_far_dispatch<1>(t, variant, s); break;
+        case 2: l2p_far_dispatch<2>(t, variant, s); break;
+        case 3: l2p_far_dispatch<3>(t, variant, s); break;
+        case 4: l2p_far_dispatch<4>(t, variant, s); break;
+        case 5: l2p_far_dispatch<5>(t, variant, s); break;
+        case 6: l2p_far_dispatch<6>(t, variant, s); break;
+        case 7: l2p_far_dispatch<7>(t, variant, s); break;
+        case 8: l2p_far_dispatch<8>(t, variant, s); break;
         default: fail(TFMM_EINVAL, "p must be in 1..8");
     }
+}
+
+void run_force_combine(Tree& t, double G, double* force, hipStream_t s) {
+    const int64_t n = t.n;
+    hipLaunchKernelGGL(force_combine_kernel, dim3((unsigned)cdiv(n, LB)), dim3(LB), 0, s, n, t.Xm.as<double4>(),
+                       t.perm.as<int32_t>(), t.near3.as<double>(), t.far3.as<double>(), G, force);
+    TFMM_LAUNCHED();
 }
 
 }  // namespace tfmm
