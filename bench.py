@@ -200,7 +200,7 @@ def run_serving(args):
             # code and the slots grow their buffers (a running server's state)
             srv.run(burst, inputs=inputs)
             caps = []
-            for _ in range(3):  # a burst lasts tens of milliseconds: the median of three
+            for _ in range(7):  # a burst lasts tens of milliseconds: the median of seven
                 recs = srv.run(burst, inputs=inputs)
                 caps.append(summarize(recs))
             cap = {"solves_per_s": float(np.median([c["solves_per_s"] for c in caps])),
