@@ -239,7 +239,8 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
 // fused kernel (285 registers) beats four launches (2.7 against 3.0 ms on 2^20
 // Plummer particles).  In FP64 the fused p = 4 kernel also runs at one wave
 // per SIMD (256 + 76 registers), yet four launches of 126-136 registers are
-// slower there too (4.25 against 3.82-3.87 ms on the same workload).
+// slower there too (4.25 against 3.82-3.87 ms on the same workload), and so
+// are two launches of two polynomials (3.84-3.90 against 3.70-3.75 ms).
 constexpr int kConsSplitP = 6;
 
 template <int P, int VAR, typename T>
