@@ -37,7 +37,9 @@
  *    the stream work that reads or writes them;
  *  - `stream` is a hipStream_t (NULL = the null stream); work is enqueued on
  *    it in order.  Calls return after enqueueing, except where noted as
- *    "synchronising" (they wait for the stream);
+ *    "synchronising" (they wait for the work queued on the stream so far:
+ *    the host polls a pinned word that a kernel writes after that work, for
+ *    at most 20 ms, then blocks in the runtime);
  *  - a context is not thread-safe: use one per host thread;
  *  - after TFMM_EDEVICE the context is unusable and must be destroyed.
  */
