@@ -143,7 +143,10 @@ def run_headline(w, pos, mass, args):
 
 def run_disk(args):
     """Exponential disk, N = 2^22, p = 6, theta = 0.8: both variants timed the
-    same way; the cost of realignment at a high order and a wide angle."""
+    same way on one tree; the cost of realignment at a high order and a wide
+    angle.  Leaves of up to 128 particles (the conserving variant's fastest
+    leaf size here; the far field dominates at p = 6); the standard variant
+    is also timed at its own fastest leaf size, 96."""
     import torch
 
     from paper_2107_07166_amd import api
@@ -155,10 +158,10 @@ def run_disk(args):
     pd = torch.from_numpy(pos).to(dev)
     md = torch.from_numpy(mass).to(dev)
     ctx = api.Context(0)
-    tree = api.Tree(ctx, pd, md, n_leaf=args.n_leaf)
+    tree = api.Tree(ctx, pd, md, n_leaf=args.disk_n_leaf)
     out = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
     res = {"workload": f"disk4m: exponential disk N={w.n}, scale length 1, sech^2 height 0.05, eps=1e-3, "
-                       f"p={w.p}, theta={w.theta}", "n": w.n}
+                       f"p={w.p}, theta={w.theta}", "n": w.n, "n_leaf": args.disk_n_leaf}
     for variant in ("standard", "conserving"):
         dt, ph = _timed_steps(tree, pd, md, out, w, variant, "mixed32", args.disk_steps, 2)
         d = ctx.diagnostics(pd, md, out)
@@ -168,6 +171,11 @@ def run_disk(args):
     res["conserving_overhead_evaluation"] = (res["conserving"]["phases_ms"]["total"]
                                              / res["standard"]["phases_ms"]["total"] - 1.0)
     res["tree"] = tree.info()
+    tree.close()
+    tree = api.Tree(ctx, pd, md, n_leaf=96)
+    dt, ph = _timed_steps(tree, pd, md, out, w, "standard", "mixed32", args.disk_steps, 2)
+    res["standard_leaf96"] = {"n_leaf": 96, "ms_per_step": dt * 1e3, "evals_per_s": w.n / dt}
+    res["conserving_overhead_vs_fastest_standard"] = res["conserving"]["ms_per_step"] / (dt * 1e3) - 1.0
     tree.close()
     ctx.close()
     return res
@@ -297,6 +305,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--disk-steps", type=int, default=8)
+    ap.add_argument("--disk-n-leaf", type=int, default=128)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-sessions", type=int, default=4)
     ap.add_argument("--serve-slots", type=int, default=4)
