@@ -11,10 +11,14 @@
 //               by the scalar of Eq. realign2 / nab-expansion, (R.R + eps^2)
 //               ^(-3/2) (1 - R.delta / |R|^2): G_0 = (R.R+eps^2)^(-3/2),
 //               G_e = -G_0 R_e / |R|^2 (Eq. aaB0 after the sum over B).
-// Each half wavefront (32 lanes) owns one target node: its lanes stride over
-// the target's source list, each lane accumulating a private local expansion,
-// and a DPP reduction across the half wave produces the node's locals (written
-// once, no atomics, fixed order -> reproducible).
+// Each row of 16 lanes owns one target node: its lanes stride over the
+// target's source list, each lane accumulating a private local expansion, and
+// a DPP reduction across the row produces the node's locals (written once, no
+// atomics, fixed order -> reproducible).  Far lists are a few dozen to a few
+// hundred sources long; with 32 lanes per target the short lists of the disk
+// (75 per node at theta = 0.8) left a third of the lanes idle in their last
+// round: 16 lanes took 3-6 % off the evaluation on the disk and the binary and
+// changed nothing on the Plummer sphere (lists of ~400).
 #include "common.h"
 #include "expansions_gen.h"
 
@@ -29,15 +33,14 @@ constexpr int MB = 256;         // largest block (4 waves); launches may use few
 // already does with four-wave blocks and would only slow the near field.
 constexpr int kConsBlock = 64;
 constexpr int kStdBlock = 256;
-constexpr int LPT = 32;         // lanes per target node
+constexpr int LPT = 16;         // lanes per target node (one DPP row)
 constexpr int TPW = kWave / LPT;  // target nodes per wavefront
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 
 // Reductions with DPP lane moves only (no LDS): pairs and quads (quad_perm),
-// half rows (row_half_mirror), rows (row_mirror), then row 0 into row 1 and
-// row 2 into row 3 (row_bcast:15).  Lanes not addressed by a row mask add zero.
+// half rows (row_half_mirror), then rows (row_mirror).
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ int dpp_i(int v) {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xF, false);
@@ -54,14 +57,14 @@ __device__ __forceinline__ double dpp(double v) {
     return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
-// Sum over each half wavefront (32 lanes), results in lanes 31 and 63.
+// Sum over each row of 16 lanes, the result in every lane of the row.
+static_assert(LPT == 16, "the reduction sums one DPP row");
 template <typename T>
-__device__ __forceinline__ T half_wave_sum_last(T v) {
-    v += dpp<0xB1>(v);        // quad_perm [1,0,3,2]
-    v += dpp<0x4E>(v);        // quad_perm [2,3,0,1]
-    v += dpp<0x141>(v);       // row_half_mirror
-    v += dpp<0x140>(v);       // row_mirror
-    v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+__device__ __forceinline__ T row_sum(T v) {
+    v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);  // row_half_mirror
+    v += dpp<0x140>(v);  // row_mirror
     return v;
 }
 
@@ -86,8 +89,8 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
     const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     if (wave * TPW >= n_targets) return;
-    const int half = lane / LPT, sl = lane % LPT;
-    const int64_t ti = wave * TPW + half;
+    const int row = lane / LPT, sl = lane % LPT;
+    const int64_t ti = wave * TPW + row;
     const bool has = ti < n_targets;
     const int32_t A = (int32_t)(has ? ti : wave * TPW);
     const double4 za = Z[A];
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
         }
     }
 #pragma unroll
-    for (int k = 0; k < NOUT; ++k) acc[k] = half_wave_sum_last(acc[k]);
+    for (int k = 0; k < NOUT; ++k) acc[k] = row_sum(acc[k]);
     if (has && q1 > q0 && sl == LPT - 1) {
         double* out = loc + (int64_t)A * NOUT;
 #pragma unroll
@@ -152,8 +155,20 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
 // PS: order of the realigned standard force.  PS == P is the conserving
 // variant of order P; PS < P keeps its projection scalar to degree P - 1
 // (Knob<PS, P - 1>), with moments and locals of order P.
+// Minimum waves per SIMD asked of the compiler for a pass.  The FP32 P pass
+// at order 6 (conserving, or the knob with a force of order 5) fits 128
+// registers without spills, four waves per SIMD instead of three; on the
+// 2^22-particle disk that takes 0.03-0.1 ms off a 4.7-5.1 ms evaluation with
+// the same locals bit for bit.  The Q' passes (190 registers) spill 17-36
+// registers at three waves and were slower (4.9 against 4.1 ms of far field);
+// orders 7 and 8 spill over 100 at four.
+constexpr int cons_pass_waves(int P, int PS, int MASK, int tsize) {
+    return (tsize == 4 && P == 6 && PS >= 5 && MASK == 1) ? 4 : 1;
+}
+
 template <int P, int PS, int MASK, typename T>
-__global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
+__global__ __launch_bounds__(MB) __attribute__((amdgpu_waves_per_eu(cons_pass_waves(P, PS, MASK, sizeof(T)))))
+void m2l_cons_pass_kernel(int64_t n_targets,
                                                            const uint32_t* __restrict__ off,
                                                            const uint32_t* __restrict__ src, uint32_t src_mask,
                                                            const double4* __restrict__ Z, const T* __restrict__ W,
@@ -166,8 +181,8 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
     const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     if (wave * TPW >= n_targets) return;
-    const int half = lane / LPT, sl = lane % LPT;
-    const int64_t ti = wave * TPW + half;
+    const int row = lane / LPT, sl = lane % LPT;
+    const int64_t ti = wave * TPW + row;
     const bool has = ti < n_targets;
     const int32_t A = (int32_t)(has ? ti : wave * TPW);
     const double4 za = Z[A];
@@ -211,7 +226,7 @@ __global__ __launch_bounds__(MB) void m2l_cons_pass_kernel(int64_t n_targets,
         if constexpr (MASK & 8) E::cons_qz(G, w, Rz, acc + NC1 * slot++);
     }
 #pragma unroll
-    for (int k = 0; k < NPOLY * NC1; ++k) acc[k] = half_wave_sum_last(acc[k]);
+    for (int k = 0; k < NPOLY * NC1; ++k) acc[k] = row_sum(acc[k]);
     if (has && q1 > q0 && sl == LPT - 1) {
         double* out = loc + (int64_t)A * (4 * NC1);
         int slot = 0;
