@@ -55,8 +55,8 @@ P2P_FLOP_PER_PAIR = 20        # per directed particle interaction (convention)
 # factor a plain copy of known size reads) and WRITE_SIZE (x1); see
 # profiles/p2p_plummer1m_counters.md.  Valid only for the kernel source the
 # counters were taken with (first 16 hex digits of its sha256).
-P2P_TRAFFIC_BYTES = (2 * 226412 + 32009) * 1024
-P2P_TRAFFIC_SOURCE_SHA = "86831685a88e238a"
+P2P_TRAFFIC_BYTES = (2 * 141322 + 32239) * 1024
+P2P_TRAFFIC_SOURCE_SHA = "21e0660b9e0ee718"
 
 
 def _p2p_traffic():

@@ -26,13 +26,14 @@ namespace tfmm {
 namespace {
 
 constexpr int MB = 256;         // largest block (4 waves); launches may use fewer
-// Block size of the force M2L launch.  M2L runs beside the near-field kernel
-// (one-wave blocks, most of the device); smaller M2L blocks get a larger share
-// of the compute units.  The conserving far field is the heavier one and
-// finishes with the near field only with one-wave blocks; the standard one
-// already does with four-wave blocks and would only slow the near field.
-constexpr int kConsBlock = 64;
-constexpr int kStdBlock = 256;
+// Block size of the force M2L launches.  M2L runs beside the near-field
+// kernel (one-wave blocks, most of the device); smaller M2L blocks get a
+// larger share of the compute units.  With one-wave blocks the standard far
+// field finishes early and the evaluation is 1-6 % faster than with four-wave
+// blocks (Plummer sphere, binary, disk), although the near field then runs
+// longer beside it; the conserving one, the heavier, needs them to finish
+// with the near field at all.
+constexpr int kForceBlock = 64;
 constexpr int LPT = 16;         // lanes per target node (one DPP row)
 constexpr int TPW = kWave / LPT;  // target nodes per wavefront
 
@@ -86,7 +87,8 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
     constexpr int NOUT = CONS ? 4 * NC1 : NC;
     // wave index through readfirstlane: the compiler then keeps the target's
     // list bounds in scalar registers
-    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+    // target nodes in chunks of 64 blocks per XCD
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(xcd_block<64>(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     if (wave * TPW >= n_targets) return;
     const int row = lane / LPT, sl = lane % LPT;
@@ -178,7 +180,8 @@ void m2l_cons_pass_kernel(int64_t n_targets,
     constexpr int NC1 = E::NC1;
     constexpr int NCP = (NC + 3) / 4 * 4;
     constexpr int NPOLY = (MASK & 1) + ((MASK >> 1) & 1) + ((MASK >> 2) & 1) + ((MASK >> 3) & 1);
-    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+    // target nodes in chunks of 64 blocks per XCD
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(xcd_block<64>(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     if (wave * TPW >= n_targets) return;
     const int row = lane / LPT, sl = lane % LPT;
@@ -263,7 +266,7 @@ void launch(Tree& t, double eps2, hipStream_t s) {
     const int64_t nt = t.n_nodes;  // every node; nodes with an empty far list write nothing
     if (nt <= 0) return;
     const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
-    const int mb = VAR == TFMM_STANDARD ? kStdBlock : kConsBlock;
+    const int mb = kForceBlock;
     const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, mb));
     if constexpr (VAR == TFMM_CONSERVING && P >= kConsSplitP) {
         auto pass = [&](auto kern) {
@@ -293,7 +296,7 @@ void launch_knob(Tree& t, double eps2, hipStream_t s) {
     const int64_t nt = t.n_nodes;
     if (nt <= 0) return;
     const T* W = (sizeof(T) == 4) ? reinterpret_cast<const T*>(t.W32.p) : reinterpret_cast<const T*>(t.W64.p);
-    const int mb = kConsBlock;
+    const int mb = kForceBlock;
     const dim3 grid((unsigned)cdiv(cdiv(nt, TPW) * kWave, mb));
     auto pass = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, dim3(mb), 0, s, nt, t.m2l_off.template as<uint32_t>(),

@@ -150,15 +150,17 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const int32_t* __restrict__ 
     __shared__ double e_off[3][kWave];
     __shared__ double red[POT ? 4 : 3][kWave];
     const int lane = threadIdx.x;
-    const int32_t A = it_leaf[blockIdx.x];
+    // work items (in target leaf order) in chunks of 32 per XCD
+    const uint32_t blk = xcd_block<32>(blockIdx.x, gridDim.x);
+    const int32_t A = it_leaf[blk];
     const int32_t fa = first[A], na = count[A];
     const double4 za = Z[A];
-    const uint32_t q0 = it_q0[blockIdx.x], q1 = it_q1[blockIdx.x];
+    const uint32_t q0 = it_q0[blk], q1 = it_q1[blk];
     // a leaf served by one item writes the result, otherwise its own partial slot
     const bool whole = leaf_nitems[A] == 1;
-    double* out = whole ? near + 3 * (int64_t)fa : partial + 3 * (int64_t)it_pbase[blockIdx.x];
+    double* out = whole ? near + 3 * (int64_t)fa : partial + 3 * (int64_t)it_pbase[blk];
     double* pout = nullptr;
-    if constexpr (POT) pout = whole ? near_pot + fa : partial_pot + it_pbase[blockIdx.x];
+    if constexpr (POT) pout = whole ? near_pot + fa : partial_pot + it_pbase[blk];
     V4 pad;
     pad.x = far_away<T>();
     pad.y = far_away<T>();
