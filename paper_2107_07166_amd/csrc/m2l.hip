@@ -149,6 +149,17 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
     }
 }
 
+// Minimum waves per SIMD asked of the compiler for a pass.  The FP32 P pass
+// at order 6 (conserving, or the knob with a force of order 5) fits 128
+// registers without spills, four waves per SIMD instead of three; on the
+// 2^22-particle disk that takes 0.07-0.14 ms off a 4.6-5.0 ms evaluation with
+// the same locals bit for bit.  The Q' passes (190 registers) spill 23-29
+// registers at three waves and were much slower (evaluation 5.3 against 4.6
+// ms); orders 7 and 8 spill over 100 at four.
+constexpr int cons_pass_waves(int P, int PS, int MASK, int tsize) {
+    return (tsize == 4 && P == 6 && PS >= 5 && MASK == 1) ? 4 : 1;
+}
+
 // Conserving M2L for a subset of the output polynomials per launch (bit 0:
 // P, bits 1..3: Q'_x,y,z), for orders whose four accumulator sets do not fit
 // the registers together: every launch recomputes the g-derivatives of its
@@ -157,24 +168,12 @@ __global__ __launch_bounds__(MB) void m2l_kernel(int64_t n_targets,
 // PS: order of the realigned standard force.  PS == P is the conserving
 // variant of order P; PS < P keeps its projection scalar to degree P - 1
 // (Knob<PS, P - 1>), with moments and locals of order P.
-// Minimum waves per SIMD asked of the compiler for a pass.  The FP32 P pass
-// at order 6 (conserving, or the knob with a force of order 5) fits 128
-// registers without spills, four waves per SIMD instead of three; on the
-// 2^22-particle disk that takes 0.03-0.1 ms off a 4.7-5.1 ms evaluation with
-// the same locals bit for bit.  The Q' passes (190 registers) spill 17-36
-// registers at three waves and were slower (4.9 against 4.1 ms of far field);
-// orders 7 and 8 spill over 100 at four.
-constexpr int cons_pass_waves(int P, int PS, int MASK, int tsize) {
-    return (tsize == 4 && P == 6 && PS >= 5 && MASK == 1) ? 4 : 1;
-}
-
 template <int P, int PS, int MASK, typename T>
 __global__ __launch_bounds__(MB) __attribute__((amdgpu_waves_per_eu(cons_pass_waves(P, PS, MASK, sizeof(T)))))
-void m2l_cons_pass_kernel(int64_t n_targets,
-                                                           const uint32_t* __restrict__ off,
-                                                           const uint32_t* __restrict__ src, uint32_t src_mask,
-                                                           const double4* __restrict__ Z, const T* __restrict__ W,
-                                                           double eps2, double* __restrict__ loc) {
+void m2l_cons_pass_kernel(int64_t n_targets, const uint32_t* __restrict__ off,
+                          const uint32_t* __restrict__ src, uint32_t src_mask,
+                          const double4* __restrict__ Z, const T* __restrict__ W,
+                          double eps2, double* __restrict__ loc) {
     using E = Expansion<P>;
     constexpr int NC = E::NC;
     constexpr int NC1 = E::NC1;
