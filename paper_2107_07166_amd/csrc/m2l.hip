@@ -18,7 +18,9 @@
 // hundred sources long; with 32 lanes per target the short lists of the disk
 // (75 per node at theta = 0.8) left a third of the lanes idle in their last
 // round: 16 lanes took 3-6 % off the evaluation on the disk and the binary and
-// changed nothing on the Plummer sphere (lists of ~400).
+// changed nothing for the default variants on the Plummer sphere (lists of
+// ~400, where 32 lanes are busy; the raised scalar degrees, whose far field
+// is not hidden beside the near field, are 6-12 % slower there).
 #include "common.h"
 #include "expansions_gen.h"
 
