@@ -43,20 +43,21 @@ __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 
 // Reductions with DPP lane moves only (no LDS): pairs and quads (quad_perm),
-// half rows (row_half_mirror), then rows (row_mirror).
-template <int CTRL, int ROWMASK>
+// half rows (row_half_mirror), then rows (row_mirror); every row and bank
+// takes part.
+template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
-template <int CTRL, int ROWMASK = 0xF>
+template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(dpp_i<CTRL, ROWMASK>(__float_as_int(v)));
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
 }
-template <int CTRL, int ROWMASK = 0xF>
+template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
     const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-    const int lo = dpp_i<CTRL, ROWMASK>((int)(uint32_t)u);
-    const int hi = dpp_i<CTRL, ROWMASK>((int)(uint32_t)(u >> 32));
+    const int lo = dpp_i<CTRL>((int)(uint32_t)u);
+    const int hi = dpp_i<CTRL>((int)(uint32_t)(u >> 32));
     return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
