@@ -270,12 +270,13 @@ __global__ __launch_bounds__(LB) void l2p_far_kernel(int64_t n, const double4* _
 // same words).  A block's particles are consecutive in sorted order, so they
 // belong to a few consecutive leaves: the block copies their locals into LDS
 // once (coalesced) and every thread reads its leaf's coefficients from there.
-// At most 16 leaves and 32 KB of coefficients per round; blocks spanning more
+// At most 8 leaves and 32 KB of coefficients per round; blocks spanning more
 // leaves take several rounds.  On the 2^22-particle disk (p = 6) this took
-// the kernel from 0.36 to 0.25 ms with the same forces bit for bit; at lower
-// orders and for the standard locals (fewer coefficients, and the staged
-// kernel holds more registers) it was slower.
-constexpr int kL2pSlots = 16;
+// the kernel from 0.36 to 0.22 ms with the same forces bit for bit (16 slots
+// per round: 0.25 ms, the staging area then limiting the kernel to fewer
+// waves); at lower orders and for the standard locals (fewer coefficients,
+// and the staged kernel holds more registers) it was slower.
+constexpr int kL2pSlots = 8;
 
 template <int P, int VAR>
 __device__ __forceinline__ void l2p_eval(const double* __restrict__ l, double dx, double dy, double dz, double* a) {
@@ -285,11 +286,10 @@ __device__ __forceinline__ void l2p_eval(const double* __restrict__ l, double dx
 }
 
 template <int P, int VAR>
-__global__ __launch_bounds__(LB) void l2p_far_staged_kernel(int64_t n, const double4* __restrict__ Xm,
-                                                            const int32_t* __restrict__ leaf_of,
-                                                            const double4* __restrict__ Z,
-                                                            const double* __restrict__ loc_leaf,
-                                                            double* __restrict__ far3) {
+__global__ __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(P == 6 ? 4 : 1)))
+void l2p_far_staged_kernel(int64_t n, const double4* __restrict__ Xm, const int32_t* __restrict__ leaf_of,
+                           const double4* __restrict__ Z, const double* __restrict__ loc_leaf,
+                           double* __restrict__ far3) {
     using E = Expansion<P>;
     constexpr int NL = VAR == TFMM_CONSERVING ? 4 * E::NC1 : E::NC;  // coefficients per leaf
     constexpr int STRIDE = NL | 1;  // odd: the slots' words fall in different banks
